@@ -1,0 +1,194 @@
+/*
+ * leyenda.h -- C ABI of an MI355X (gfx950) record sorter.
+ *
+ * Sorts 100-byte records by their 10-byte key: the record format of the
+ * paper's workloads (Section 4.1: a 10-byte key followed by a 90-byte value).
+ * Keys compare as unsigned byte strings, most significant byte first -- the
+ * order in which the 256-way digit buckets of Algorithm 1 (Adaptive Parallel
+ * MSD Radix Sort, Section 3.1) split the key from radix 0 upward, and the order
+ * of the worked bucket example of Section 2.2.  Records with equal keys keep
+ * their input order (a stable sort; the paper leaves ties open), so the output
+ * is unique and every entry point below returns exactly the same bytes for the
+ * same input, whatever its tuning.
+ *
+ * Conventions for every entry point:
+ *   - Return value: LEYENDA_OK (0) or a negative leyenda_status.  No exception
+ *     or signal crosses this boundary.  leyenda_last_error() gives a text for
+ *     the last failure on the calling thread.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  GPU
+ *     work is enqueued on it and the call returns before that work finishes
+ *     unless stated otherwise; results are valid after the stream is
+ *     synchronized.  Concurrent calls on different streams are allowed; two
+ *     calls on the same stream run in order.
+ *   - Record buffers are arrays of n * 100 bytes, 4-byte aligned.  The caller
+ *     owns every buffer passed in; the library owns only its scratch memory,
+ *     drawn from a per-device, per-stream pool that it keeps between calls
+ *     (released by leyenda_release_workspaces()).
+ *   - On error, output buffers hold unspecified bytes, but nothing is written
+ *     outside them.
+ */
+#ifndef LEYENDA_H
+#define LEYENDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LEYENDA_RECORD_BYTES 100
+#define LEYENDA_KEY_BYTES 10
+/* Largest record count of one sort, run or batch segment: record indices are
+ * carried in 32 bits inside the (key, index) tuples (AlphaSort-style key +
+ * pointer pairs, Sections 2.1 and 3.2). */
+#define LEYENDA_MAX_RECORDS 0xFFFFFFFEull
+
+typedef enum {
+    LEYENDA_OK = 0,
+    LEYENDA_EINVAL = -1,  /* bad argument: NULL with n > 0, misaligned, overlapping, bad params */
+    LEYENDA_ENOMEM = -2,  /* device or pinned-host allocation failed */
+    LEYENDA_EBUDGET = -3, /* the work cannot be planned within the given device budget */
+    LEYENDA_EHIP = -4,    /* a HIP runtime call failed (see leyenda_last_error) */
+    LEYENDA_ETOOBIG = -5, /* more than LEYENDA_MAX_RECORDS records in one sort/run/segment */
+    LEYENDA_EINTERNAL = -6 /* a device-side capacity guard fired (a bug; see leyenda_sort_stats) */
+} leyenda_status;
+
+/* ---------------------------------------------------------------------------
+ * Internal (device-resident) sort -- Algorithm 1 of Section 3.1 plus the
+ * key-pointer extraction and record scatter of Section 3.2.
+ *
+ * records_dev: device pointer, n records (read only).
+ * out_dev:     device pointer, n records; receives the records in key order.
+ *              Must not overlap records_dev.
+ * n:           0 is a no-op returning LEYENDA_OK.
+ * Steps run on the GPU: extraction of (key, index) tuples with the first-digit
+ * histogram, device-wide MSD digit partitions of buckets larger than the big
+ * bucket threshold, per-bucket sorts in LDS (radix partition, then a
+ * comparison sort of tiny buckets) and the record gather.
+ * ------------------------------------------------------------------------- */
+int leyenda_sort(const void *records_dev, uint64_t n, void *out_dev, void *stream);
+
+/* Device bytes of scratch memory leyenda_sort uses for n records under the
+ * current parameters (tuple buffers, index array, bucket tables). */
+uint64_t leyenda_workspace_bytes(uint64_t n);
+
+/* ---------------------------------------------------------------------------
+ * Limited-memory (external) sort -- Section 3.2, "Overlapping Computation with
+ * I/O": a sort stage that sorts chunks into sorted intermediate runs, then a
+ * merge stage that merges the runs with a K-way merge, partition by
+ * partition.  Host buffers must be pinned (hipHostMalloc, or torch
+ * pin_memory()).  Both calls are synchronous: they return when the host
+ * output is complete.
+ *
+ * leyenda_sort_runs:
+ *   host_records: n records in pinned host memory (read only unless aliased).
+ *   device_budget_bytes: cap on the device memory the call allocates.
+ *   host_runs: n records of pinned host memory; run r is written, sorted,
+ *              over the input range it came from, so host_runs may equal
+ *              host_records (in-place run formation).
+ *   run_bounds: array of k_max + 1 entries; on success run r covers records
+ *              [run_bounds[r], run_bounds[r+1]) and run_bounds[0] = 0,
+ *              run_bounds[k] = n.
+ *   k_out: number of runs written.
+ *   Returns LEYENDA_EBUDGET if the budget cannot hold the smallest run plan or
+ *   more than k_max runs would be needed.
+ *
+ * leyenda_merge:
+ *   host_runs, run_bounds, k: k sorted runs (as produced above; ties between
+ *              runs are ordered by run, which is input order).
+ *   host_out: n = run_bounds[k] records of pinned host memory; receives the
+ *              merged output.  Must not overlap host_runs.
+ * ------------------------------------------------------------------------- */
+int leyenda_sort_runs(const void *host_records, uint64_t n, uint64_t device_budget_bytes,
+                      void *host_runs, uint64_t *run_bounds, uint64_t k_max, uint64_t *k_out,
+                      void *stream);
+int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, uint64_t k, void *host_out,
+                  uint64_t device_budget_bytes, void *stream);
+
+/* Run plan of leyenda_sort_runs for n records under a budget: records per run
+ * and number of runs (host-only arithmetic, no GPU work).  LEYENDA_EBUDGET if
+ * the budget is too small. */
+int leyenda_plan_runs(uint64_t n, uint64_t device_budget_bytes, uint64_t *run_records,
+                      uint64_t *num_runs);
+
+/* ---------------------------------------------------------------------------
+ * Batched sort: many independent sort requests in one launch sequence (the
+ * analogue of Algorithm 1's shared small-bucket task queue, applied across
+ * requests).  Each segment is sorted on its own, exactly as leyenda_sort would
+ * sort it; segments never interact.  Segment buffers are device pointers.
+ * The launch sequence is captured once per stream into a HIP graph and
+ * replayed; per-batch arguments travel in a device descriptor table.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    const void *in; /* device, n records */
+    void *out;      /* device, n records, not overlapping in */
+    uint64_t n;
+} leyenda_segment;
+
+int leyenda_sort_batch(const leyenda_segment *segs, uint64_t count, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Tuning parameters.  They change speed only, never the output bytes.
+ * digit_bits     radix digit width in bits (8: 256 buckets per pass, Algorithm 1).
+ * tile_items     keys per thread in a device-wide partition tile (8 or 16; a
+ *                tile is 256 * tile_items keys).
+ * big_threshold  buckets with more keys than this get another device-wide
+ *                partition pass (Algorithm 1's bigBucketThreshold);
+ *                1 <= big_threshold <= local_capacity.
+ * tiny_threshold buckets of at most this many keys inside a local sort are
+ *                ordered by comparisons instead of another radix partition
+ *                (Algorithm 1's tinyBucketThreshold); 1..64.
+ * local_capacity keys one workgroup sorts in LDS (2048).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t digit_bits;
+    uint32_t tile_items;
+    uint32_t big_threshold;
+    uint32_t tiny_threshold;
+    uint32_t local_capacity;
+} leyenda_params;
+
+int leyenda_get_params(leyenda_params *out);
+int leyenda_set_params(const leyenda_params *p); /* LEYENDA_EINVAL if out of range */
+/* Loads a flat JSON object with any of the field names above (the file the
+ * autotuner writes).  Unknown keys are ignored. */
+int leyenda_load_params(const char *json_path);
+
+/* ---------------------------------------------------------------------------
+ * Diagnostics.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t levels;          /* device-wide partition levels that moved data */
+    uint32_t segments[12];    /* big buckets planned at each level */
+    uint64_t moved[12];       /* keys moved by the device-wide partition at each level */
+    uint64_t tasks;           /* local-sort tasks */
+    uint32_t guard;           /* nonzero if a device-side capacity guard fired */
+} leyenda_stats;
+
+/* Synchronizes `stream` and reports the plan of the last leyenda_sort on it. */
+int leyenda_sort_stats(void *stream, leyenda_stats *out);
+
+const char *leyenda_status_string(int status);
+const char *leyenda_last_error(void);
+/* Frees every cached workspace (synchronizes the device first). */
+int leyenda_release_workspaces(void);
+
+/* ---------------------------------------------------------------------------
+ * Step-level entry points used by the parity tests (same kernels as the sort).
+ *
+ * leyenda_debug_extract: for each record i, hi[i] = big-endian key bytes 0..7,
+ *   lo[i] = (big-endian key bytes 8..9) << 32 | i, and hist[b] = number of
+ *   records whose key byte 0 is b (256 counters).  All device pointers.
+ * leyenda_debug_gather: out[j] = records[idx[j]] for j < n (device pointers;
+ *   idx holds n indices below n_records).
+ * ------------------------------------------------------------------------- */
+int leyenda_debug_extract(const void *records_dev, uint64_t n, uint64_t *hi_dev, uint64_t *lo_dev,
+                          uint32_t *hist_dev, void *stream);
+int leyenda_debug_gather(const void *records_dev, uint64_t n_records, const uint32_t *idx_dev,
+                         uint64_t n, void *out_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LEYENDA_H */

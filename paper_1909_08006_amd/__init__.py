@@ -1,0 +1,238 @@
+"""Python binding of the MI355X record sorter (``lib/libleyenda.so``).
+
+Argument marshalling only: every step of every sort runs in the HIP library
+(``csrc/``) behind the C ABI declared in ``include/leyenda.h``.  PyTorch
+supplies device memory, pinned host memory and streams.  There is no CPU
+fallback: if the library is missing, :func:`load` raises.
+
+Records are 100 bytes (10-byte key, 90-byte value, Section 4.1 of the paper);
+tensors are ``torch.uint8`` of shape ``(n, 100)`` (or flat, ``n * 100``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libleyenda.so")
+RECORD_BYTES = 100
+KEY_BYTES = 10
+
+_lib = None
+
+STATUS = {0: "LEYENDA_OK", -1: "LEYENDA_EINVAL", -2: "LEYENDA_ENOMEM", -3: "LEYENDA_EBUDGET",
+          -4: "LEYENDA_EHIP", -5: "LEYENDA_ETOOBIG", -6: "LEYENDA_EINTERNAL"}
+
+
+class LeyendaError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {detail}")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("digit_bits", ctypes.c_uint32), ("tile_items", ctypes.c_uint32),
+                ("big_threshold", ctypes.c_uint32), ("tiny_threshold", ctypes.c_uint32),
+                ("local_capacity", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_uint32), ("segments", ctypes.c_uint32 * 12),
+                ("moved", ctypes.c_uint64 * 12), ("tasks", ctypes.c_uint64), ("guard", ctypes.c_uint32)]
+
+
+class Segment(ctypes.Structure):
+    _fields_ = [("inp", ctypes.c_void_p), ("out", ctypes.c_void_p), ("n", ctypes.c_uint64)]
+
+
+def load():
+    """Load the HIP library (built by ``build.py``); raise if it is not there."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+    P64 = ctypes.POINTER(ctypes.c_uint64)
+    sig = {
+        "leyenda_sort": ([vp, u64, vp, vp], i32),
+        "leyenda_workspace_bytes": ([u64], u64),
+        "leyenda_sort_runs": ([vp, u64, u64, vp, P64, u64, P64, vp], i32),
+        "leyenda_merge": ([vp, P64, u64, vp, u64, vp], i32),
+        "leyenda_plan_runs": ([u64, u64, P64, P64], i32),
+        "leyenda_sort_batch": ([ctypes.POINTER(Segment), u64, vp], i32),
+        "leyenda_get_params": ([ctypes.POINTER(Params)], i32),
+        "leyenda_set_params": ([ctypes.POINTER(Params)], i32),
+        "leyenda_load_params": ([ctypes.c_char_p], i32),
+        "leyenda_sort_stats": ([vp, ctypes.POINTER(Stats)], i32),
+        "leyenda_status_string": ([i32], ctypes.c_char_p),
+        "leyenda_last_error": ([], ctypes.c_char_p),
+        "leyenda_release_workspaces": ([], i32),
+        "leyenda_debug_extract": ([vp, u64, vp, vp, vp, vp], i32),
+        "leyenda_debug_gather": ([vp, u64, vp, u64, vp, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != 0:
+        raise LeyendaError(rc, where, load().leyenda_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _nrec(t) -> int:
+    if t.dtype.itemsize != 1 or t.numel() % RECORD_BYTES:
+        raise ValueError("record tensors are uint8 with a multiple of 100 bytes")
+    if not t.is_contiguous():
+        raise ValueError("record tensors must be contiguous")
+    return t.numel() // RECORD_BYTES
+
+
+# ---- sorting -------------------------------------------------------------------
+
+def sort(records, out=None, stream=None):
+    """Stable sort of device-resident records by key; returns ``out``.
+
+    Asynchronous on ``stream`` (default: torch's current stream)."""
+    import torch
+    n = _nrec(records)
+    if not records.is_cuda:
+        raise ValueError("sort() takes a device tensor; use sort_runs()/merge() for host data")
+    if out is None:
+        out = torch.empty_like(records)
+    elif _nrec(out) != n or not out.is_cuda:
+        raise ValueError("out must be a device tensor of the same size")
+    _check(load().leyenda_sort(records.data_ptr(), n, out.data_ptr(), _stream_ptr(stream)), "leyenda_sort")
+    return out
+
+
+def workspace_bytes(n: int) -> int:
+    return int(load().leyenda_workspace_bytes(n))
+
+
+def plan_runs(n: int, budget_bytes: int) -> tuple[int, int]:
+    r, k = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(load().leyenda_plan_runs(n, budget_bytes, ctypes.byref(r), ctypes.byref(k)), "leyenda_plan_runs")
+    return int(r.value), int(k.value)
+
+
+def sort_runs(host_records, budget_bytes: int, host_runs=None, k_max: int = 4096, stream=None):
+    """Sorted runs of pinned host records within a device budget.
+
+    Returns ``(host_runs, run_bounds)``; ``host_runs`` may be ``host_records``
+    itself (runs are written over their own input ranges)."""
+    import torch
+    n = _nrec(host_records)
+    if host_runs is None:
+        host_runs = torch.empty_like(host_records, pin_memory=True)
+    bounds = (ctypes.c_uint64 * (k_max + 1))()
+    k = ctypes.c_uint64(0)
+    _check(load().leyenda_sort_runs(host_records.data_ptr(), n, budget_bytes, host_runs.data_ptr(), bounds, k_max,
+                                    ctypes.byref(k), _stream_ptr(stream)), "leyenda_sort_runs")
+    return host_runs, [int(bounds[i]) for i in range(k.value + 1)]
+
+
+def merge(host_runs, run_bounds: Sequence[int], budget_bytes: int, host_out=None, stream=None):
+    """K-way merge of sorted runs (pinned host memory) into ``host_out``."""
+    import torch
+    n = _nrec(host_runs)
+    if host_out is None:
+        host_out = torch.empty_like(host_runs, pin_memory=True)
+    k = len(run_bounds) - 1
+    b = (ctypes.c_uint64 * len(run_bounds))(*run_bounds)
+    if run_bounds[-1] != n:
+        raise ValueError("run_bounds must end at the record count")
+    _check(load().leyenda_merge(host_runs.data_ptr(), b, k, host_out.data_ptr(), budget_bytes, _stream_ptr(stream)),
+           "leyenda_merge")
+    return host_out
+
+
+def sort_batch(pairs: Iterable, stream=None) -> None:
+    """Sort many independent requests in one launch sequence.
+
+    ``pairs``: iterable of ``(in_tensor, out_tensor)`` device tensors."""
+    segs = []
+    for a, b in pairs:
+        n = _nrec(a)
+        if _nrec(b) != n:
+            raise ValueError("segment output size differs from its input")
+        segs.append((a.data_ptr(), b.data_ptr(), n))
+    arr = (Segment * max(1, len(segs)))()
+    for i, (a, b, n) in enumerate(segs):
+        arr[i].inp, arr[i].out, arr[i].n = a, b, n
+    _check(load().leyenda_sort_batch(arr, len(segs), _stream_ptr(stream)), "leyenda_sort_batch")
+
+
+# ---- parameters and diagnostics -----------------------------------------------------
+
+def get_params() -> dict:
+    p = Params()
+    _check(load().leyenda_get_params(ctypes.byref(p)), "leyenda_get_params")
+    return p.as_dict()
+
+
+def set_params(**kw) -> dict:
+    p = Params()
+    _check(load().leyenda_get_params(ctypes.byref(p)), "leyenda_get_params")
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, int(v))
+    _check(load().leyenda_set_params(ctypes.byref(p)), "leyenda_set_params")
+    return p.as_dict()
+
+
+def load_params(path: str) -> dict:
+    _check(load().leyenda_load_params(path.encode()), "leyenda_load_params")
+    return get_params()
+
+
+def stats(stream=None) -> dict:
+    s = Stats()
+    _check(load().leyenda_sort_stats(_stream_ptr(stream), ctypes.byref(s)), "leyenda_sort_stats")
+    return {"levels": int(s.levels), "segments": list(s.segments), "moved": [int(x) for x in s.moved],
+            "tasks": int(s.tasks), "guard": int(s.guard)}
+
+
+def release_workspaces() -> None:
+    _check(load().leyenda_release_workspaces(), "leyenda_release_workspaces")
+
+
+def debug_extract(records, stream=None):
+    """(hi, lo, hist) tuples of the extraction step, as int64 tensors + int32 histogram."""
+    import torch
+    n = _nrec(records)
+    dev = records.device
+    hi = torch.empty(n, dtype=torch.int64, device=dev)
+    lo = torch.empty(n, dtype=torch.int64, device=dev)
+    hist = torch.empty(256, dtype=torch.int32, device=dev)
+    _check(load().leyenda_debug_extract(records.data_ptr(), n, hi.data_ptr(), lo.data_ptr(), hist.data_ptr(),
+                                        _stream_ptr(stream)), "leyenda_debug_extract")
+    return hi, lo, hist
+
+
+def debug_gather(records, idx, stream=None):
+    """out[j] = records[idx[j]] with the sort's gather kernel (idx: int32 device tensor)."""
+    import torch
+    n_rec = _nrec(records)
+    n = idx.numel()
+    out = torch.empty((n, RECORD_BYTES), dtype=torch.uint8, device=records.device)
+    _check(load().leyenda_debug_gather(records.data_ptr(), n_rec, idx.data_ptr(), n, out.data_ptr(),
+                                       _stream_ptr(stream)), "leyenda_debug_gather")
+    return out

@@ -1,0 +1,126 @@
+// Internal definitions shared by the device kernels and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ley {
+
+constexpr int kRec = 100;          // record bytes (Section 4.1)
+constexpr int kKeyBits = 80;       // 10-byte key
+constexpr int kRB = 8;             // digit width: 256-way buckets per pass (Algorithm 1)
+constexpr int kRadix = 1 << kRB;
+constexpr int kWG = 256;           // threads per workgroup, all kernels (4 wave64)
+constexpr int kWaves = kWG / 64;
+constexpr int kNH = 4;             // digit windows histogrammed per read (constant windows are skipped)
+constexpr int kMaxLev = (kKeyBits + kRB - 1) / kRB;  // device-wide partition levels at most
+constexpr int kLocalCap = 2048;    // keys per local (LDS) sort task
+constexpr int kLocalItems = kLocalCap / kWG;
+constexpr uint16_t kNoScatter = 0xFFFF;
+
+constexpr uint64_t kFlagAgg = 1ull << 62;  // look-back status: tile aggregate published
+constexpr uint64_t kFlagInc = 2ull << 62;  // look-back status: inclusive prefix published
+constexpr uint64_t kCountMask = (1ull << 62) - 1;
+
+constexpr uint8_t kTaskSorted = 1;  // task range is already in final order
+
+// A bucket that gets a device-wide partition pass at some level.
+struct Seg {
+    uint64_t start;       // first key in the tuple arrays
+    uint32_t count;
+    uint32_t first_tile;  // its tiles at this level are [first_tile, first_tile + ntiles)
+    uint32_t ntiles;
+    uint32_t done;        // histogram tiles finished (the last one plans the segment)
+    uint16_t pos;         // key bit where histogram window 0 starts
+    uint16_t spos;        // key bit of the partition digit, or kNoScatter
+    uint8_t buf;          // tuple buffer holding the segment
+    uint8_t jstar;        // histogram window turned into bucket offsets
+    uint16_t req;         // batch request the segment belongs to
+};
+static_assert(sizeof(Seg) == 32, "Seg layout");
+
+// A local-sort task: a contiguous range of whole buckets, each small enough
+// for LDS, or a range that is already in order.
+struct Task {
+    uint64_t start;
+    uint32_t count;
+    uint8_t buf;
+    uint8_t flags;
+    uint16_t pos;
+};
+static_assert(sizeof(Task) == 16, "Task layout");
+
+// Per-sort control block (device memory).
+struct Ctl {
+    uint32_t nseg[kMaxLev + 2];
+    uint32_t ntiles[kMaxLev + 2];
+    uint32_t tile_ctr[kMaxLev + 2];
+    uint32_t ntask;
+    uint32_t task_ctr;
+    uint32_t guard;
+    uint32_t pad;
+    unsigned long long moved[kMaxLev + 2];
+};
+
+// Batch request (level-0 segment) descriptor.
+struct Req {
+    const uint8_t *in;
+    uint8_t *out;
+    uint64_t start;       // first key of the request in the batch's tuple space
+    uint64_t n;
+    uint32_t first_tile;  // its level-0 tiles
+    uint32_t ntiles;
+};
+
+// Batch header: sizes the kernels read from device memory, so a captured
+// launch sequence can be replayed for another batch.
+struct Hdr {
+    uint64_t n_total;     // keys over all requests
+    uint32_t nreq;
+    uint32_t tiles0;      // level-0 tiles over all requests
+};
+
+// Runtime tuning values the kernels read.
+struct Tune {
+    uint32_t tile_items;   // 8 or 16
+    uint32_t tile;         // kWG * tile_items
+    uint32_t big;          // big-bucket threshold
+    uint32_t tiny;         // comparison-sort threshold inside the local sort
+};
+
+// Device workspace views for one sort.
+struct Work {
+    uint64_t *H[2];      // big-endian key bytes 0..7
+    uint64_t *L[2];      // (key bytes 8..9) << 32 | record index
+    uint32_t *idx;       // sorted record index per output position
+    Ctl *ctl;
+    Seg *segs[2];        // by level parity
+    uint32_t *hist[2];   // [seg][kNH][kRadix], by level parity
+    uint32_t *tile_seg[2];
+    unsigned long long *status;  // [tile][kRadix]
+    Task *tasks;
+    Req *reqs;
+    Hdr *hdr;
+    uint64_t n;          // keys in the tuple space
+    uint32_t max_seg, max_tiles, max_tasks, max_reqs;
+};
+
+// Workspace sizing for a tuple space of n keys and up to `reqs` requests.
+struct Layout {
+    uint64_t n;
+    uint32_t max_seg, max_tiles, max_tasks, max_reqs;
+    size_t off_H0, off_H1, off_L0, off_L1, off_idx, off_ctl, off_seg0, off_seg1, off_hist0,
+        off_hist1, off_ts0, off_ts1, off_status, off_tasks, off_reqs, off_hdr, total;
+};
+Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t);
+Work bind_layout(const Layout &L, void *base);
+
+// Launch wrappers (sort_kernels.hip).  All return hipError_t of the launches.
+hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
+                            hipStream_t s, int cus);
+hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,
+                                uint64_t n, hipStream_t s);
+hipError_t launch_gather_batch(const Work &w, uint32_t nreq, hipStream_t s, int cus);
+hipError_t launch_debug_extract(const uint8_t *rec, uint64_t n, uint64_t *hi, uint64_t *lo,
+                                uint32_t *hist, hipStream_t s);
+
+}  // namespace ley

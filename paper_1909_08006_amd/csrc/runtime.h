@@ -1,0 +1,22 @@
+// Host-side helpers shared by the runtime translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+
+#include "../../include/leyenda.h"
+#include "common.h"
+
+namespace ley {
+
+int fail(int status, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+leyenda_params current_params();
+Tune tune_of(const leyenda_params &p);
+int device_cus();
+int get_workspace(hipStream_t stream, size_t bytes, void **out);
+int remember_layout(hipStream_t stream, const Layout &L);
+bool overlaps(const void *a, uint64_t abytes, const void *b, uint64_t bbytes);
+int check_records(const void *in, const void *out, uint64_t n, const char *who);
+int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t);
+
+}  // namespace ley

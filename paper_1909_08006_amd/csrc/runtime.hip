@@ -1,0 +1,383 @@
+// Host runtime of the record sorter: parameters, workspace pool, argument
+// checks and the leyenda_sort entry point (C ABI declared in leyenda.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "../../include/leyenda.h"
+#include "common.h"
+#include "runtime.h"
+
+namespace ley {
+
+// ---------------------------------------------------------------------------
+// errors
+
+static thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(LEYENDA_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// parameters
+
+static std::mutex g_param_mu;
+static leyenda_params g_params = {8, 16, 2048, 32, 2048};
+
+leyenda_params current_params() {
+    std::lock_guard<std::mutex> lk(g_param_mu);
+    return g_params;
+}
+
+Tune tune_of(const leyenda_params &p) {
+    Tune t;
+    t.tile_items = p.tile_items;
+    t.tile = kWG * p.tile_items;
+    t.big = p.big_threshold;
+    t.tiny = p.tiny_threshold;
+    return t;
+}
+
+static bool params_ok(const leyenda_params &p) {
+    return p.digit_bits == 8 && (p.tile_items == 8 || p.tile_items == 16) && p.local_capacity == kLocalCap &&
+           p.big_threshold >= 1 && p.big_threshold <= p.local_capacity && p.tiny_threshold >= 1 &&
+           p.tiny_threshold <= 64;
+}
+
+// ---------------------------------------------------------------------------
+// device facts
+
+int device_cus() {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cus[dev] = v;
+    }
+    return cus[dev];
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout and pool
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t) {
+    Layout L{};
+    L.n = n;
+    const uint64_t segs = std::max<uint64_t>(reqs, n / ((uint64_t)t.big + 1)) + 1;
+    const uint64_t tiles = (n + t.tile - 1) / t.tile + segs + reqs;
+    const uint64_t tasks = 3 * (n / kLocalCap) + 4ull * (kMaxLev + 1) * segs + reqs + 64;
+    L.max_seg = (uint32_t)std::min<uint64_t>(segs, 0xFFFFFFFFull);
+    L.max_tiles = (uint32_t)std::min<uint64_t>(tiles, 0xFFFFFFFFull);
+    L.max_tasks = (uint32_t)std::min<uint64_t>(tasks, 0xFFFFFFFFull);
+    L.max_reqs = std::max<uint32_t>(reqs, 1);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
+    const size_t nn = std::max<uint64_t>(n, 1);
+    L.off_H0 = take(nn * 8);
+    L.off_H1 = take(nn * 8);
+    L.off_L0 = take(nn * 8);
+    L.off_L1 = take(nn * 8);
+    L.off_idx = take(nn * 4);
+    L.off_ctl = take(sizeof(Ctl));
+    L.off_seg0 = take((size_t)L.max_seg * sizeof(Seg));
+    L.off_seg1 = take((size_t)L.max_seg * sizeof(Seg));
+    L.off_hist0 = take((size_t)L.max_seg * kNH * kRadix * 4);
+    L.off_hist1 = take((size_t)L.max_seg * kNH * kRadix * 4);
+    L.off_ts0 = take((size_t)L.max_tiles * 4);
+    L.off_ts1 = take((size_t)L.max_tiles * 4);
+    L.off_status = take((size_t)L.max_tiles * kRadix * 8);
+    L.off_tasks = take((size_t)L.max_tasks * sizeof(Task));
+    L.off_reqs = take((size_t)L.max_reqs * sizeof(Req));
+    L.off_hdr = take(sizeof(Hdr));
+    L.total = o;
+    return L;
+}
+
+Work bind_layout(const Layout &L, void *base) {
+    char *b = static_cast<char *>(base);
+    Work w{};
+    w.H[0] = reinterpret_cast<uint64_t *>(b + L.off_H0);
+    w.H[1] = reinterpret_cast<uint64_t *>(b + L.off_H1);
+    w.L[0] = reinterpret_cast<uint64_t *>(b + L.off_L0);
+    w.L[1] = reinterpret_cast<uint64_t *>(b + L.off_L1);
+    w.idx = reinterpret_cast<uint32_t *>(b + L.off_idx);
+    w.ctl = reinterpret_cast<Ctl *>(b + L.off_ctl);
+    w.segs[0] = reinterpret_cast<Seg *>(b + L.off_seg0);
+    w.segs[1] = reinterpret_cast<Seg *>(b + L.off_seg1);
+    w.hist[0] = reinterpret_cast<uint32_t *>(b + L.off_hist0);
+    w.hist[1] = reinterpret_cast<uint32_t *>(b + L.off_hist1);
+    w.tile_seg[0] = reinterpret_cast<uint32_t *>(b + L.off_ts0);
+    w.tile_seg[1] = reinterpret_cast<uint32_t *>(b + L.off_ts1);
+    w.status = reinterpret_cast<unsigned long long *>(b + L.off_status);
+    w.tasks = reinterpret_cast<Task *>(b + L.off_tasks);
+    w.reqs = reinterpret_cast<Req *>(b + L.off_reqs);
+    w.hdr = reinterpret_cast<Hdr *>(b + L.off_hdr);
+    w.n = L.n;
+    w.max_seg = L.max_seg;
+    w.max_tiles = L.max_tiles;
+    w.max_tasks = L.max_tasks;
+    w.max_reqs = L.max_reqs;
+    return w;
+}
+
+struct PoolEntry {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    Layout layout{};
+};
+
+static std::mutex g_pool_mu;
+static std::map<std::pair<int, hipStream_t>, PoolEntry> g_pool;
+
+// Workspace of at least `bytes` for work on `stream` (one per device and
+// stream, so concurrent sorts on different streams never share scratch).
+int get_workspace(hipStream_t stream, size_t bytes, void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    PoolEntry &pe = g_pool[{dev, stream}];
+    if (pe.ptr && pe.bytes >= bytes) { *out = pe.ptr; return LEYENDA_OK; }
+    if (pe.ptr) {
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        e = hipFree(pe.ptr);
+        pe.ptr = nullptr;
+        pe.bytes = 0;
+        if (e != hipSuccess) return hip_fail(e, "hipFree");
+    }
+    void *p = nullptr;
+    e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LEYENDA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    pe.ptr = p;
+    pe.bytes = bytes;
+    *out = p;
+    return LEYENDA_OK;
+}
+
+int remember_layout(hipStream_t stream, const Layout &L) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LEYENDA_EHIP;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_pool[{dev, stream}].layout = L;
+    return LEYENDA_OK;
+}
+
+static int find_workspace(hipStream_t stream, void **ptr, Layout *L) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LEYENDA_EHIP;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_pool.find({dev, stream});
+    if (it == g_pool.end() || !it->second.ptr) return fail(LEYENDA_EINVAL, "no sort has run on this stream");
+    *ptr = it->second.ptr;
+    *L = it->second.layout;
+    return LEYENDA_OK;
+}
+
+int release_all() {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    for (auto &kv : g_pool) {
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    }
+    g_pool.clear();
+    return LEYENDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// argument checks
+
+bool overlaps(const void *a, uint64_t abytes, const void *b, uint64_t bbytes) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bbytes && y < x + abytes;
+}
+
+int check_records(const void *in, const void *out, uint64_t n, const char *who) {
+    if (n > LEYENDA_MAX_RECORDS) return fail(LEYENDA_ETOOBIG, "%s: %llu records exceed the per-sort limit", who,
+                                             (unsigned long long)n);
+    if (!in || !out) return fail(LEYENDA_EINVAL, "%s: NULL buffer", who);
+    if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 3u)
+        return fail(LEYENDA_EINVAL, "%s: buffers must be 4-byte aligned", who);
+    if (overlaps(in, n * kRec, out, n * kRec)) return fail(LEYENDA_EINVAL, "%s: input and output overlap", who);
+    return LEYENDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the single-request sort
+
+__global__ void k_setup_single(Req *reqs, Hdr *hdr, const uint8_t *in, uint8_t *out, uint64_t n,
+                               uint32_t tiles) {
+    Req r;
+    r.in = in; r.out = out; r.start = 0; r.n = n; r.first_tile = 0; r.ntiles = tiles;
+    reqs[0] = r;
+    Hdr h;
+    h.n_total = n; h.nreq = 1; h.tiles0 = tiles;
+    *hdr = h;
+}
+
+int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t) {
+    const Layout L = plan_layout(n, 1, t);
+    void *ws = nullptr;
+    int rc = get_workspace(stream, L.total, &ws);
+    if (rc) return rc;
+    remember_layout(stream, L);
+    const Work w = bind_layout(L, ws);
+    const uint32_t tiles0 = (uint32_t)((n + t.tile - 1) / t.tile);
+    k_setup_single<<<1, 1, 0, stream>>>(w.reqs, w.hdr, static_cast<const uint8_t *>(records_dev),
+                                        static_cast<uint8_t *>(out_dev), n, tiles0);
+    hipError_t e = launch_sort_core(w, t, 1, tiles0, stream, device_cus());
+    if (e != hipSuccess) return hip_fail(e, "sort kernels");
+    e = launch_gather_single(static_cast<const uint8_t *>(records_dev), n, w.idx, static_cast<uint8_t *>(out_dev),
+                             n, stream);
+    if (e != hipSuccess) return hip_fail(e, "gather kernel");
+    return LEYENDA_OK;
+}
+
+}  // namespace ley
+
+using namespace ley;
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" int leyenda_sort(const void *records_dev, uint64_t n, void *out_dev, void *stream) {
+    if (n == 0) return LEYENDA_OK;
+    int rc = check_records(records_dev, out_dev, n, "leyenda_sort");
+    if (rc) return rc;
+    return sort_device(records_dev, n, out_dev, static_cast<hipStream_t>(stream), tune_of(current_params()));
+}
+
+extern "C" uint64_t leyenda_workspace_bytes(uint64_t n) {
+    return plan_layout(n, 1, tune_of(current_params())).total;
+}
+
+extern "C" int leyenda_get_params(leyenda_params *out) {
+    if (!out) return fail(LEYENDA_EINVAL, "leyenda_get_params: NULL");
+    *out = current_params();
+    return LEYENDA_OK;
+}
+
+extern "C" int leyenda_set_params(const leyenda_params *p) {
+    if (!p || !params_ok(*p)) return fail(LEYENDA_EINVAL, "leyenda_set_params: parameter out of range");
+    std::lock_guard<std::mutex> lk(g_param_mu);
+    g_params = *p;
+    return LEYENDA_OK;
+}
+
+static bool json_field(const std::string &s, const char *name, uint32_t *v) {
+    const std::string key = std::string("\"") + name + "\"";
+    size_t p = s.find(key);
+    if (p == std::string::npos) return false;
+    p = s.find(':', p + key.size());
+    if (p == std::string::npos) return false;
+    *v = (uint32_t)strtoul(s.c_str() + p + 1, nullptr, 10);
+    return true;
+}
+
+extern "C" int leyenda_load_params(const char *json_path) {
+    if (!json_path) return fail(LEYENDA_EINVAL, "leyenda_load_params: NULL path");
+    FILE *f = fopen(json_path, "rb");
+    if (!f) return fail(LEYENDA_EINVAL, "leyenda_load_params: cannot open %s", json_path);
+    std::string s;
+    char buf[4096];
+    size_t k;
+    while ((k = fread(buf, 1, sizeof(buf), f)) > 0) s.append(buf, k);
+    fclose(f);
+    leyenda_params p = current_params();
+    json_field(s, "digit_bits", &p.digit_bits);
+    json_field(s, "tile_items", &p.tile_items);
+    json_field(s, "big_threshold", &p.big_threshold);
+    json_field(s, "tiny_threshold", &p.tiny_threshold);
+    json_field(s, "local_capacity", &p.local_capacity);
+    return leyenda_set_params(&p);
+}
+
+extern "C" int leyenda_sort_stats(void *stream, leyenda_stats *out) {
+    if (!out) return fail(LEYENDA_EINVAL, "leyenda_sort_stats: NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *ws = nullptr;
+    Layout L{};
+    int rc = find_workspace(s, &ws, &L);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    Ctl c;
+    e = hipMemcpy(&c, static_cast<char *>(ws) + L.off_ctl, sizeof(Ctl), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    memset(out, 0, sizeof(*out));
+    for (int l = 0; l < kMaxLev && l < 12; l++) {
+        out->segments[l] = c.nseg[l];
+        out->moved[l] = c.moved[l];
+        if (c.moved[l]) out->levels = l + 1;
+    }
+    out->tasks = c.ntask;
+    out->guard = c.guard;
+    return LEYENDA_OK;
+}
+
+extern "C" const char *leyenda_status_string(int status) {
+    switch (status) {
+        case LEYENDA_OK: return "ok";
+        case LEYENDA_EINVAL: return "invalid argument";
+        case LEYENDA_ENOMEM: return "out of memory";
+        case LEYENDA_EBUDGET: return "does not fit the device budget";
+        case LEYENDA_EHIP: return "HIP runtime error";
+        case LEYENDA_ETOOBIG: return "too many records";
+        case LEYENDA_EINTERNAL: return "internal capacity guard";
+        default: return "unknown status";
+    }
+}
+
+extern "C" const char *leyenda_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int leyenda_release_workspaces(void) { return release_all(); }
+
+extern "C" int leyenda_debug_extract(const void *records_dev, uint64_t n, uint64_t *hi_dev, uint64_t *lo_dev,
+                                     uint32_t *hist_dev, void *stream) {
+    if (n == 0) return LEYENDA_OK;
+    if (n > LEYENDA_MAX_RECORDS) return fail(LEYENDA_ETOOBIG, "leyenda_debug_extract: too many records");
+    if (!records_dev || !hi_dev || !lo_dev || !hist_dev) return fail(LEYENDA_EINVAL, "leyenda_debug_extract: NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemsetAsync(hist_dev, 0, kRadix * 4, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    e = launch_debug_extract(static_cast<const uint8_t *>(records_dev), n, hi_dev, lo_dev, hist_dev, s);
+    return e == hipSuccess ? LEYENDA_OK : hip_fail(e, "extract kernel");
+}
+
+extern "C" int leyenda_debug_gather(const void *records_dev, uint64_t n_records, const uint32_t *idx_dev,
+                                    uint64_t n, void *out_dev, void *stream) {
+    if (n == 0) return LEYENDA_OK;
+    if (n > LEYENDA_MAX_RECORDS || n_records > LEYENDA_MAX_RECORDS)
+        return fail(LEYENDA_ETOOBIG, "leyenda_debug_gather: too many records");
+    if (!records_dev || !idx_dev || !out_dev) return fail(LEYENDA_EINVAL, "leyenda_debug_gather: NULL");
+    if (overlaps(records_dev, n_records * kRec, out_dev, n * kRec))
+        return fail(LEYENDA_EINVAL, "leyenda_debug_gather: input and output overlap");
+    hipError_t e = launch_gather_single(static_cast<const uint8_t *>(records_dev), n_records, idx_dev,
+                                        static_cast<uint8_t *>(out_dev), n, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LEYENDA_OK : hip_fail(e, "gather kernel");
+}

@@ -1,0 +1,805 @@
+// Device kernels of the in-HBM record sort (gfx950, wave64).
+//
+// The schedule follows Algorithm 1 (Adaptive Parallel MSD Radix Sort,
+// Section 3.1) on the key-pointer tuples of Section 3.2:
+//
+//   k_init      request table -> level-0 buckets and tile map
+//   k_extract   (key, index) tuple per record + histograms of the leading
+//               digits (AlphaSort-style key-pointer extraction, Section 3.2);
+//               the workgroup finishing a bucket's last tile plans it
+//   k_hist      per level >= 1: histograms of big buckets, then planning
+//   k_scatter   per level: stable device-wide partition of big buckets by one
+//               digit (ParallelRadixSort, "cache aware scattering": tiles are
+//               ranked and staged in LDS, then written as runs), with tile
+//               offsets from a decoupled look-back over per-tile digit counts
+//   k_local     per small bucket, in one workgroup's LDS: radix partition on
+//               the first varying digit (SingleThreadRadixSort), recursion on
+//               sub-buckets above the tiny threshold, and a comparison sort of
+//               tiny sub-buckets (ComparisonSort)
+//   k_gather    record scatter by the sorted tuples: out[j] = in[idx[j]]
+//
+// Tuples are kept as two arrays (struct of arrays): H = key bytes 0..7 as a
+// big-endian u64, L = key bytes 8..9 (big-endian) << 32 | record index.
+// (H, L) compared as an unsigned 128-bit number is the key order with ties
+// broken by record index, i.e. exactly the stable order.
+#include "common.h"
+
+namespace ley {
+
+// ---------------------------------------------------------------------------
+// small helpers
+
+// Bits [pos, pos + kRB) of the 80-bit key (most significant bit first); bits
+// past the key read as zero.  pos < 80.
+__device__ __forceinline__ uint32_t digit_at(uint64_t h, uint64_t l, uint32_t pos) {
+    const uint64_t k2 = (l >> 32) << 48;
+    uint64_t w;
+    if (pos == 0) w = h;
+    else if (pos < 64) w = (h << pos) | (k2 >> (64 - pos));
+    else w = k2 << (pos - 64);
+    return (uint32_t)(w >> (64 - kRB));
+}
+
+__device__ __forceinline__ unsigned long long ld_agent(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_agent32(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const uint32_t lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Stable rank of digit d among the earlier lanes of this wave and the earlier
+// calls of this wave (counted in cnt[]), over lanes with valid == true.
+__device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint32_t *cnt) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRB; b++) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    const uint32_t below = __popcll(peers & lanemask_lt());
+    uint32_t base = 0;
+    if (valid) base = cnt[d];
+    __builtin_amdgcn_wave_barrier();
+    if (valid && below == 0) cnt[d] = base + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    return base + below;
+}
+
+// Exclusive prefix sum over the workgroup's 256 threads (one value each).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp /*[kWaves]*/) {
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= (uint32_t)off) x += y;
+    }
+    if (lane == 63) tmp[w] = x;
+    __syncthreads();
+    uint32_t pre = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; k++) pre += (k < (int)w) ? tmp[k] : 0u;
+    __syncthreads();
+    return pre + x - v;
+}
+
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+// A segment read back from a device table is inside the tuple space and owns
+// the tile that points at it (defence against a fired capacity guard).
+__device__ __forceinline__ bool seg_ok(const Work &w, const Seg &sg, uint32_t tile) {
+    return sg.count > 0 && sg.start + sg.count <= w.n && tile >= sg.first_tile &&
+           tile - sg.first_tile < sg.ntiles && sg.buf <= 1;
+}
+
+// ---------------------------------------------------------------------------
+// planning of one big bucket (Algorithm 1: big buckets recurse on the next
+// digit, small ones go to the task queue, tiny ones are sorted by comparison
+// inside the local sort).  Called by all threads of a workgroup.
+
+__device__ void emit_task(const Work &w, uint64_t start, uint32_t count, uint8_t buf, uint8_t flags,
+                          uint16_t pos) {
+    const uint32_t j = atomicAdd(&w.ctl->ntask, 1u);
+    if (j >= w.max_tasks) { atomicOr(&w.ctl->guard, 1u); return; }
+    Task t;
+    t.start = start; t.count = count; t.buf = buf; t.flags = flags; t.pos = pos;
+    w.tasks[j] = t;
+}
+
+// A range whose keys are all equal is already in final (index) order; it is
+// cut into local-capacity chunks so each task stays bounded.
+__device__ void emit_sorted(const Work &w, uint64_t start, uint64_t count, uint8_t buf) {
+    const uint64_t nch = (count + kLocalCap - 1) / kLocalCap;
+    const uint32_t j0 = atomicAdd(&w.ctl->ntask, (uint32_t)nch);
+    if ((uint64_t)j0 + nch > w.max_tasks) { atomicOr(&w.ctl->guard, 2u); return; }
+    for (uint64_t k = 0; k < nch; k++) {
+        Task t;
+        t.start = start + k * kLocalCap;
+        t.count = (uint32_t)min<uint64_t>(kLocalCap, count - k * kLocalCap);
+        t.buf = buf; t.flags = kTaskSorted; t.pos = 0;
+        w.tasks[j0 + k] = t;
+    }
+}
+
+__device__ void new_segment(const Work &w, const Tune &tu, int lev, uint64_t start, uint32_t count,
+                            uint32_t pos, uint8_t buf, uint16_t req) {
+    const uint32_t s = atomicAdd(&w.ctl->nseg[lev], 1u);
+    const uint32_t nt = (count + tu.tile - 1) / tu.tile;
+    const uint32_t ft = atomicAdd(&w.ctl->ntiles[lev], nt);
+    if (s >= w.max_seg || (uint64_t)ft + nt > w.max_tiles) { atomicOr(&w.ctl->guard, 4u); return; }
+    Seg g;
+    g.start = start; g.count = count; g.first_tile = ft; g.ntiles = nt; g.done = 0;
+    g.pos = (uint16_t)pos; g.spos = kNoScatter; g.buf = buf; g.jstar = 0; g.req = req;
+    w.segs[lev & 1][s] = g;
+}
+
+__device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s) {
+    __shared__ uint32_t p_cnt[kRadix];
+    __shared__ uint32_t p_base[kRadix];
+    __shared__ uint32_t p_tmp[kWaves];
+    const uint32_t d = threadIdx.x;
+    Seg *sp = &w.segs[lev & 1][s];
+    const Seg sg = *sp;
+    uint32_t *hs = w.hist[lev & 1] + (size_t)s * kNH * kRadix;
+
+    if (sg.count <= tu.big) {  // small bucket: one local-sort task as it is
+        if (d == 0) {
+            sp->spos = kNoScatter;
+            emit_task(w, sg.start, sg.count, sg.buf, 0, sg.pos);
+        }
+        return;
+    }
+    uint32_t c[kNH];
+#pragma unroll
+    for (int j = 0; j < kNH; j++) c[j] = ld_agent32(&hs[j * kRadix + d]);
+    int jstar = -1;
+#pragma unroll
+    for (int j = 0; j < kNH; j++) {
+        if (jstar < 0 && sg.pos + j * kRB < kKeyBits) {
+            const int isconst = __syncthreads_or(c[j] == sg.count);
+            if (!isconst) jstar = j;
+        }
+    }
+    if (jstar < 0) {  // every window constant over the bucket: skip them without moving data
+        const uint32_t np = sg.pos + kNH * kRB;
+        if (d == 0) {
+            sp->spos = kNoScatter;
+            if (np >= kKeyBits) emit_sorted(w, sg.start, sg.count, sg.buf);
+            else new_segment(w, tu, lev + 1, sg.start, sg.count, np, sg.buf, sg.req);
+        }
+        return;
+    }
+    const uint32_t p = sg.pos + jstar * kRB;
+    uint32_t cnt = c[0];
+#pragma unroll
+    for (int j = 1; j < kNH; j++) if (j == jstar) cnt = c[j];
+    const uint32_t base = block_excl_scan(cnt, p_tmp);
+    hs[jstar * kRadix + d] = base;  // bucket offsets used by k_scatter
+    p_cnt[d] = cnt;
+    p_base[d] = base;
+    if (d == 0) {
+        sp->spos = (uint16_t)p;
+        sp->jstar = (uint8_t)jstar;
+        atomicAdd(&w.ctl->moved[lev], (unsigned long long)sg.count);
+    }
+    const uint8_t cbuf = sg.buf ^ 1;
+    const uint32_t cpos = p + kRB;
+    if (cnt > tu.big) {
+        if (cpos < kKeyBits) new_segment(w, tu, lev + 1, sg.start + base, cnt, cpos, cbuf, sg.req);
+        else emit_sorted(w, sg.start + base, cnt, cbuf);  // all 80 key bits fixed: equal keys
+    }
+    __syncthreads();
+    if (d == 0) {  // pack consecutive small buckets into tasks of at most kLocalCap keys
+        uint64_t cur_start = 0;
+        uint32_t cur = 0;
+        for (int e = 0; e < kRadix; e++) {
+            const uint32_t ce = p_cnt[e];
+            if (ce == 0) continue;
+            if (ce > tu.big) {
+                if (cur) { emit_task(w, cur_start, cur, cbuf, 0, (uint16_t)p); cur = 0; }
+                continue;
+            }
+            if (cur && cur + ce > (uint32_t)kLocalCap) { emit_task(w, cur_start, cur, cbuf, 0, (uint16_t)p); cur = 0; }
+            if (cur == 0) cur_start = sg.start + p_base[e];
+            cur += ce;
+        }
+        if (cur) emit_task(w, cur_start, cur, cbuf, 0, (uint16_t)p);
+    }
+    __syncthreads();
+}
+
+// The workgroup that finishes the last histogram tile of bucket s plans it.
+__device__ __forceinline__ void finish_tile(const Work &w, const Tune &tu, int lev, uint32_t s,
+                                            uint32_t ntiles_s) {
+    __shared__ int s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t prev = atomicAdd(&w.segs[lev & 1][s].done, 1u);
+        s_last = (prev == ntiles_s - 1);
+    }
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        plan_segment(w, tu, lev, s);
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// k_init: level-0 buckets (one per request) and their tile map
+
+__global__ __launch_bounds__(kWG) void k_init(Work w) {
+    const Hdr hd = *w.hdr;
+    if (blockIdx.x == 0) {
+        uint32_t *c = reinterpret_cast<uint32_t *>(w.ctl);
+        for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += kWG) c[i] = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            w.ctl->nseg[0] = hd.nreq;
+            w.ctl->ntiles[0] = hd.tiles0;
+        }
+    }
+    for (uint32_t r = blockIdx.x; r < hd.nreq; r += gridDim.x) {
+        const Req rq = w.reqs[r];
+        if (threadIdx.x == 0) {
+            Seg g;
+            g.start = rq.start; g.count = (uint32_t)rq.n; g.first_tile = rq.first_tile;
+            g.ntiles = rq.ntiles; g.done = 0; g.pos = 0; g.spos = kNoScatter; g.buf = 0;
+            g.jstar = 0; g.req = (uint16_t)r;
+            w.segs[0][r] = g;
+        }
+        for (uint32_t k = threadIdx.x; k < rq.ntiles; k += kWG) w.tile_seg[0][rq.first_tile + k] = r;
+        uint32_t *hs = w.hist[0] + (size_t)r * kNH * kRadix;
+        for (uint32_t i = threadIdx.x; i < kNH * kRadix; i += kWG) hs[i] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_extract: tuples + leading-digit histograms of every record
+
+template <int ITEMS>
+__global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
+    __shared__ uint32_t sh[kNH][kRadix];
+    const uint32_t ntiles = min(w.ctl->ntiles[0], w.max_tiles);
+    const uint32_t nreq = w.hdr->nreq;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        for (uint32_t i = threadIdx.x; i < kNH * kRadix; i += kWG) (&sh[0][0])[i] = 0;
+        w.status[(size_t)tile * kRadix + threadIdx.x] = 0;
+        const uint32_t s = w.tile_seg[0][tile];
+        if (s >= nreq || s >= w.max_seg) { if (threadIdx.x == 0) atomicOr(&w.ctl->guard, 8u); __syncthreads(); continue; }
+        const Seg sg = w.segs[0][s];
+        if (!seg_ok(w, sg, tile)) { if (threadIdx.x == 0) atomicOr(&w.ctl->guard, 8u); __syncthreads(); continue; }
+        const Req rq = w.reqs[sg.req];
+        const uint64_t local0 = (uint64_t)(tile - sg.first_tile) * tu.tile;
+        const uint32_t nvalid = (uint32_t)min<uint64_t>(tu.tile, sg.count - local0);
+        __syncthreads();
+        uint32_t a[ITEMS], b[ITEMS], c[ITEMS];
+#pragma unroll
+        for (int u = 0; u < ITEMS; u++) {
+            const uint32_t q = u * kWG + threadIdx.x;
+            if (q < nvalid) {
+                const uint32_t *p = reinterpret_cast<const uint32_t *>(rq.in + (local0 + q) * kRec);
+                a[u] = p[0]; b[u] = p[1]; c[u] = p[2];
+            }
+        }
+        uint64_t *H = w.H[0] + sg.start + local0;
+        uint64_t *L = w.L[0] + sg.start + local0;
+#pragma unroll
+        for (int u = 0; u < ITEMS; u++) {
+            const uint32_t q = u * kWG + threadIdx.x;
+            if (q < nvalid) {
+                const uint64_t h = __builtin_bswap64(((uint64_t)b[u] << 32) | a[u]);
+                const uint64_t k16 = __builtin_bswap16((uint16_t)(c[u] & 0xFFFFu));
+                H[q] = h;
+                L[q] = (k16 << 32) | (uint32_t)(local0 + q);
+#pragma unroll
+                for (int j = 0; j < kNH; j++) atomicAdd(&sh[j][(h >> (56 - 8 * j)) & 0xFF], 1u);
+            }
+        }
+        __syncthreads();
+        uint32_t *hs = w.hist[0] + (size_t)s * kNH * kRadix;
+#pragma unroll
+        for (int j = 0; j < kNH; j++) {
+            const uint32_t v = sh[j][threadIdx.x];
+            if (v) atomicAdd(&hs[j * kRadix + threadIdx.x], v);
+        }
+        finish_tile(w, tu, 0, s, sg.ntiles);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_hist: histograms of big buckets at level lev >= 1, then planning
+
+template <int ITEMS>
+__global__ __launch_bounds__(kWG) void k_hist(Work w, Tune tu, int lev) {
+    __shared__ uint32_t sh[kNH][kRadix];
+    const uint32_t ntiles = min(w.ctl->ntiles[lev], w.max_tiles);
+    const uint32_t nseg = min(w.ctl->nseg[lev], w.max_seg);
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        for (uint32_t i = threadIdx.x; i < kNH * kRadix; i += kWG) (&sh[0][0])[i] = 0;
+        w.status[(size_t)tile * kRadix + threadIdx.x] = 0;
+        const uint32_t s = w.tile_seg[lev & 1][tile];
+        if (s >= nseg) { if (threadIdx.x == 0) atomicOr(&w.ctl->guard, 8u); __syncthreads(); continue; }
+        const Seg sg = w.segs[lev & 1][s];
+        if (!seg_ok(w, sg, tile)) { if (threadIdx.x == 0) atomicOr(&w.ctl->guard, 8u); __syncthreads(); continue; }
+        const uint64_t local0 = (uint64_t)(tile - sg.first_tile) * tu.tile;
+        const uint32_t nvalid = (uint32_t)min<uint64_t>(tu.tile, sg.count - local0);
+        const uint64_t *H = w.H[sg.buf] + sg.start + local0;
+        const uint64_t *L = w.L[sg.buf] + sg.start + local0;
+        const bool needL = sg.pos + kNH * kRB > 64;
+        __syncthreads();
+        uint64_t h[ITEMS], l[ITEMS];
+#pragma unroll
+        for (int u = 0; u < ITEMS; u++) {
+            const uint32_t q = u * kWG + threadIdx.x;
+            h[u] = 0; l[u] = 0;
+            if (q < nvalid) {
+                h[u] = H[q];
+                if (needL) l[u] = L[q];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < ITEMS; u++) {
+            const uint32_t q = u * kWG + threadIdx.x;
+            if (q < nvalid) {
+#pragma unroll
+                for (int j = 0; j < kNH; j++) {
+                    const uint32_t p = sg.pos + j * kRB;
+                    if (p < kKeyBits) atomicAdd(&sh[j][digit_at(h[u], l[u], p)], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        uint32_t *hs = w.hist[lev & 1] + (size_t)s * kNH * kRadix;
+#pragma unroll
+        for (int j = 0; j < kNH; j++) {
+            const uint32_t v = sh[j][threadIdx.x];
+            if (v) atomicAdd(&hs[j * kRadix + threadIdx.x], v);
+        }
+        finish_tile(w, tu, lev, s, sg.ntiles);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_scatter: one device-wide stable partition pass of the big buckets of level lev
+
+template <int ITEMS>
+__global__ __launch_bounds__(kWG) void k_scatter(Work w, Tune tu, int lev) {
+    constexpr int TILE = kWG * ITEMS;
+    __shared__ uint64_t sH[TILE];
+    __shared__ uint64_t sL[TILE];
+    __shared__ uint32_t cnt[kWaves][kRadix];
+    __shared__ uint32_t lbase[kRadix];
+    __shared__ unsigned long long gbase[kRadix];
+    __shared__ uint32_t tmp[kWaves];
+    __shared__ uint32_t s_tile;
+
+    const uint32_t ntiles = min(w.ctl->ntiles[lev], w.max_tiles);
+    const uint32_t nseg = min(w.ctl->nseg[lev], w.max_seg);
+    const uint32_t tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_tile = atomicAdd(&w.ctl->tile_ctr[lev], 1u);
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        if (tile >= ntiles) break;
+        const uint32_t s = w.tile_seg[lev & 1][tile];
+        if (s >= nseg) continue;
+        const Seg sg = w.segs[lev & 1][s];
+        if (sg.spos == kNoScatter || !seg_ok(w, sg, tile) || sg.spos >= kKeyBits || sg.jstar >= kNH) continue;
+        const uint64_t seg_end = sg.start + sg.count;
+        const uint32_t k = tile - sg.first_tile;
+        const uint64_t local0 = (uint64_t)k * TILE;
+        const uint32_t nvalid = (uint32_t)min<uint64_t>(TILE, sg.count - local0);
+        const uint64_t *Hs = w.H[sg.buf] + sg.start + local0;
+        const uint64_t *Ls = w.L[sg.buf] + sg.start + local0;
+#pragma unroll
+        for (int j = 0; j < kWaves; j++) cnt[j][tid] = 0;
+        uint64_t h[ITEMS], l[ITEMS];
+        uint32_t dg[ITEMS], rk[ITEMS];
+#pragma unroll
+        for (int u = 0; u < ITEMS; u++) {
+            const uint32_t q = wv * (ITEMS * 64) + u * 64 + lane;
+            h[u] = 0; l[u] = 0;
+            if (q < nvalid) { h[u] = Hs[q]; l[u] = Ls[q]; }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < ITEMS; u++) {
+            const uint32_t q = wv * (ITEMS * 64) + u * 64 + lane;
+            const bool valid = q < nvalid;
+            dg[u] = valid ? digit_at(h[u], l[u], sg.spos) : 0u;
+            rk[u] = wave_rank(dg[u], valid, cnt[wv]);
+        }
+        __syncthreads();
+        // per-digit wave prefixes and the tile total
+        uint32_t tot = 0;
+#pragma unroll
+        for (int j = 0; j < kWaves; j++) {
+            const uint32_t cj = cnt[j][tid];
+            cnt[j][tid] = tot;
+            tot += cj;
+        }
+        // decoupled look-back over earlier tiles of the same bucket
+        unsigned long long *st = w.status + (size_t)tile * kRadix + tid;
+        unsigned long long excl = 0;
+        if (k == 0) {
+            st_agent(st, kFlagInc | tot);
+        } else {
+            st_agent(st, kFlagAgg | tot);
+            uint32_t spins = 0;
+            for (uint32_t tt = tile - 1; tt >= sg.first_tile; tt--) {
+                const unsigned long long *sp = w.status + (size_t)tt * kRadix + tid;
+                unsigned long long v;
+                while (((v = ld_agent(sp)) >> 62) == 0 && spins < kSpinLimit) {
+                    __builtin_amdgcn_s_sleep(1);
+                    spins++;
+                }
+                if (spins >= kSpinLimit) { atomicOr(&w.ctl->guard, 16u); break; }
+                excl += v & kCountMask;
+                if ((v & kFlagInc) || tt == sg.first_tile) break;
+            }
+            st_agent(st, kFlagInc | (excl + tot));
+        }
+        const uint32_t lb = block_excl_scan(tot, tmp);
+        const uint32_t bb = w.hist[lev & 1][(size_t)s * kNH * kRadix + sg.jstar * kRadix + tid];
+        lbase[tid] = lb;
+        gbase[tid] = sg.start + bb + excl - lb;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < ITEMS; u++) {
+            const uint32_t q = wv * (ITEMS * 64) + u * 64 + lane;
+            if (q < nvalid) {
+                const uint32_t pos = lbase[dg[u]] + cnt[wv][dg[u]] + rk[u];
+                sH[pos] = h[u];
+                sL[pos] = l[u];
+            }
+        }
+        __syncthreads();
+        uint64_t *Hd = w.H[sg.buf ^ 1];
+        uint64_t *Ld = w.L[sg.buf ^ 1];
+#pragma unroll
+        for (int u = 0; u < ITEMS; u++) {
+            const uint32_t q = u * kWG + tid;
+            if (q < nvalid) {
+                const uint64_t hh = sH[q], ll = sL[q];
+                const uint64_t dst = gbase[digit_at(hh, ll, sg.spos)] + q;
+                if (dst >= sg.start && dst < seg_end) {
+                    Hd[dst] = hh;
+                    Ld[dst] = ll;
+                } else {
+                    atomicOr(&w.ctl->guard, 32u);
+                }
+            }
+        }
+    }
+    // set up level lev + 1: tile map and zeroed histograms of its buckets
+    const uint32_t nn = min(w.ctl->nseg[lev + 1], w.max_seg);
+    for (uint32_t s2 = blockIdx.x; s2 < nn; s2 += gridDim.x) {
+        const Seg g = w.segs[(lev + 1) & 1][s2];
+        if ((uint64_t)g.first_tile + g.ntiles <= w.max_tiles)
+            for (uint32_t t = tid; t < g.ntiles; t += kWG) w.tile_seg[(lev + 1) & 1][g.first_tile + t] = s2;
+        uint32_t *hs = w.hist[(lev + 1) & 1] + (size_t)s2 * kNH * kRadix;
+        for (uint32_t i = tid; i < kNH * kRadix; i += kWG) hs[i] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_local: small buckets sorted inside one workgroup's LDS
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) v |= __shfl_xor(v, off);
+    return v;
+}
+__device__ __forceinline__ uint64_t wave_and64(uint64_t v) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) v &= __shfl_xor(v, off);
+    return v;
+}
+
+constexpr int kStack = kLocalCap / 2;
+
+__global__ __launch_bounds__(kWG) void k_local(Work w, Tune tu) {
+    __shared__ uint64_t sH[kLocalCap];
+    __shared__ uint64_t sL[kLocalCap];
+    __shared__ uint32_t segb[kLocalCap];   // per position: sub-bucket [lo, hi) packed lo | hi << 16
+    __shared__ uint32_t cnt[kWaves][kRadix];
+    __shared__ uint32_t lbase[kRadix];
+    __shared__ uint32_t ltot[kRadix];
+    __shared__ uint32_t stk[kStack];
+    __shared__ uint32_t tmp[kWaves];
+    __shared__ uint64_t orh[kWaves], andh[kWaves], orl[kWaves], andl[kWaves];
+    __shared__ int stk_n;
+    __shared__ uint32_t s_task;
+
+    const uint32_t ntask = min(w.ctl->ntask, w.max_tasks);
+    const uint32_t tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_task = atomicAdd(&w.ctl->task_ctr, 1u);
+        __syncthreads();
+        const uint32_t j = s_task;
+        if (j >= ntask) break;
+        const Task tk = w.tasks[j];
+        if (tk.start + tk.count > w.n || tk.buf > 1 || tk.count > kLocalCap) {
+            if (tid == 0) atomicOr(&w.ctl->guard, 64u);
+            continue;
+        }
+        const uint64_t *Hs = w.H[tk.buf] + tk.start;
+        const uint64_t *Ls = w.L[tk.buf] + tk.start;
+        uint32_t *out = w.idx + tk.start;
+        const uint32_t m = tk.count;
+        if ((tk.flags & kTaskSorted) || m <= 1) {
+            for (uint32_t q = tid; q < m; q += kWG) out[q] = (uint32_t)Ls[q];
+            continue;
+        }
+        for (uint32_t q = tid; q < m; q += kWG) {
+            sH[q] = Hs[q];
+            sL[q] = Ls[q];
+            segb[q] = q | ((q + 1) << 16);
+        }
+        if (tid == 0) { stk[0] = 0u | (m << 16); stk_n = 1; }
+        __syncthreads();
+        for (;;) {
+            const int nst = min(stk_n, kStack);
+            if (nst <= 0) break;
+            const uint32_t e = stk[nst - 1];
+            __syncthreads();
+            if (tid == 0) stk_n = nst - 1;
+            const uint32_t a = e & 0xFFFFu, len = e >> 16;
+            // which key bits vary over [a, a + len)
+            uint64_t oh = 0, ah = ~0ull, ol = 0, al = ~0ull;
+            for (uint32_t q = a + tid; q < a + len; q += kWG) {
+                const uint64_t hh = sH[q], kk = (sL[q] >> 32) & 0xFFFFu;
+                oh |= hh; ah &= hh; ol |= kk; al &= kk;
+            }
+            oh = wave_or64(oh); ah = wave_and64(ah);
+            ol = wave_or64(ol); al = wave_and64(al);
+            if (lane == 0) { orh[wv] = oh; andh[wv] = ah; orl[wv] = ol; andl[wv] = al; }
+            __syncthreads();
+            uint64_t OH = 0, AH = ~0ull, OL = 0, AL = ~0ull;
+#pragma unroll
+            for (int k2 = 0; k2 < kWaves; k2++) { OH |= orh[k2]; AH &= andh[k2]; OL |= orl[k2]; AL &= andl[k2]; }
+            const uint64_t vh = OH ^ AH, vl = (OL ^ AL) & 0xFFFFu;
+            if (vh == 0 && vl == 0) continue;  // equal keys: already in index order
+            const uint32_t f = vh ? (uint32_t)__clzll(vh) : 64u + ((uint32_t)__clz((uint32_t)vl) - 16u);
+            // stable partition of [a, a + len) by the digit at bit f
+            cnt[0][tid] = 0; cnt[1][tid] = 0; cnt[2][tid] = 0; cnt[3][tid] = 0;
+            __syncthreads();
+            uint64_t h[kLocalItems], l[kLocalItems];
+            uint32_t dg[kLocalItems], rk[kLocalItems];
+#pragma unroll
+            for (int u = 0; u < kLocalItems; u++) {
+                const uint32_t i = wv * (kLocalItems * 64) + u * 64 + lane;
+                const bool valid = i < len;
+                h[u] = valid ? sH[a + i] : 0ull;
+                l[u] = valid ? sL[a + i] : 0ull;
+                dg[u] = valid ? digit_at(h[u], l[u], f) : 0u;
+                rk[u] = wave_rank(dg[u], valid, cnt[wv]);
+            }
+            __syncthreads();
+            uint32_t tot = 0;
+#pragma unroll
+            for (int k2 = 0; k2 < kWaves; k2++) {
+                const uint32_t cj = cnt[k2][tid];
+                cnt[k2][tid] = tot;
+                tot += cj;
+            }
+            const uint32_t lb = block_excl_scan(tot, tmp);
+            lbase[tid] = lb;
+            ltot[tid] = tot;
+            if (tot > tu.tiny) {
+                const int slot = atomicAdd(&stk_n, 1);
+                if (slot < kStack) stk[slot] = (a + lb) | (tot << 16);
+                else atomicOr(&w.ctl->guard, 128u);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kLocalItems; u++) {
+                const uint32_t i = wv * (kLocalItems * 64) + u * 64 + lane;
+                if (i < len) {
+                    const uint32_t d = dg[u];
+                    const uint32_t np = a + lbase[d] + cnt[wv][d] + rk[u];
+                    sH[np] = h[u];
+                    sL[np] = l[u];
+                    const uint32_t c = ltot[d];
+                    const uint32_t lo = a + lbase[d];
+                    segb[np] = (c > tu.tiny) ? (np | ((np + 1) << 16)) : (lo | ((lo + c) << 16));
+                }
+            }
+            __syncthreads();
+        }
+        // tiny sub-buckets: position = sub-bucket start + number of smaller tuples
+        uint32_t fv[kLocalItems], iv[kLocalItems];
+#pragma unroll
+        for (int u = 0; u < kLocalItems; u++) {
+            const uint32_t q = u * kWG + tid;
+            fv[u] = q; iv[u] = 0;
+            if (q < m) {
+                const uint32_t sb = segb[q], lo = sb & 0xFFFFu, hi = min(sb >> 16, m);
+                const uint64_t kh = sH[q], kl = sL[q];
+                iv[u] = (uint32_t)kl;
+                if (hi > lo + 1) {
+                    uint32_t r = 0;
+                    for (uint32_t jj = lo; jj < hi; jj++) {
+                        const uint64_t oh2 = sH[jj], ol2 = sL[jj];
+                        r += (oh2 < kh) || (oh2 == kh && ol2 < kl);
+                    }
+                    fv[u] = lo + r;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kLocalItems; u++) {
+            const uint32_t q = u * kWG + tid;
+            if (q < m) segb[fv[u]] = iv[u];
+        }
+        __syncthreads();
+        for (uint32_t q = tid; q < m; q += kWG) out[q] = segb[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_gather: records in sorted order, out[j] = in[idx[j]] per request.  A
+// block copies 256 records with one dword per lane per step, so stores are
+// contiguous and each source record is read as whole 100-byte spans.
+
+__device__ __forceinline__ uint32_t find_req(const Req *reqs, uint32_t nreq, uint64_t g) {
+    uint32_t lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (reqs[mid].start <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kWG) void k_gather(const Req *reqs, const Hdr *hdr, const uint32_t *idx) {
+    __shared__ const uint32_t *ssrc[kWG];
+    __shared__ uint32_t *sdst[kWG];
+    const uint64_t n = hdr->n_total;
+    const uint32_t nreq = hdr->nreq;
+    for (uint64_t g0 = (uint64_t)blockIdx.x * kWG; g0 < n; g0 += (uint64_t)gridDim.x * kWG) {
+        const uint32_t nr = (uint32_t)min<uint64_t>(kWG, n - g0);
+        __syncthreads();
+        if (threadIdx.x < nr) {
+            const uint64_t g = g0 + threadIdx.x;
+            const uint32_t r = find_req(reqs, nreq, g);
+            const Req rq = reqs[r];
+            const uint32_t ix = idx[g];
+            // a sorted index is always inside its request; fall back to the
+            // record itself if a guard fired upstream
+            const uint64_t si = ix < rq.n ? ix : (g - rq.start);
+            ssrc[threadIdx.x] = reinterpret_cast<const uint32_t *>(rq.in + si * kRec);
+            sdst[threadIdx.x] = reinterpret_cast<uint32_t *>(rq.out + (g - rq.start) * kRec);
+        }
+        __syncthreads();
+        uint32_t v[25];
+#pragma unroll
+        for (int u = 0; u < 25; u++) {
+            const uint32_t q = threadIdx.x + kWG * u, r = q / 25u, kk = q - 25u * r;
+            if (r < nr) v[u] = ssrc[r][kk];
+        }
+#pragma unroll
+        for (int u = 0; u < 25; u++) {
+            const uint32_t q = threadIdx.x + kWG * u, r = q / 25u, kk = q - 25u * r;
+            if (r < nr) sdst[r][kk] = v[u];
+        }
+    }
+}
+
+// Plain gather for the step-level test entry point.
+__global__ __launch_bounds__(kWG) void k_gather_plain(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx,
+                                                      uint8_t *out, uint64_t n) {
+    __shared__ uint32_t sidx[kWG];
+    const uint64_t g0 = (uint64_t)blockIdx.x * kWG;
+    const uint32_t nr = (uint32_t)min<uint64_t>(kWG, n - g0);
+    if (threadIdx.x < nr) sidx[threadIdx.x] = idx[g0 + threadIdx.x];
+    __syncthreads();
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(rec);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(out) + g0 * 25;
+    uint32_t v[25];
+#pragma unroll
+    for (int u = 0; u < 25; u++) {
+        const uint32_t q = threadIdx.x + kWG * u, r = q / 25u, kk = q - 25u * r;
+        v[u] = 0;
+        if (r < nr && sidx[r] < n_rec) v[u] = src[(uint64_t)sidx[r] * 25 + kk];
+    }
+#pragma unroll
+    for (int u = 0; u < 25; u++) {
+        const uint32_t q = threadIdx.x + kWG * u, r = q / 25u;
+        if (r < nr) dst[q] = v[u];
+    }
+}
+
+// Extraction alone (tuples + byte-0 histogram) for the step-level test entry point.
+__global__ __launch_bounds__(kWG) void k_extract_plain(const uint8_t *rec, uint64_t n, uint64_t *H, uint64_t *L,
+                                                       uint32_t *hist) {
+    __shared__ uint32_t sh[kRadix];
+    sh[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i < n) {
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(rec + i * kRec);
+        const uint64_t h = __builtin_bswap64(((uint64_t)p[1] << 32) | p[0]);
+        const uint64_t k16 = __builtin_bswap16((uint16_t)(p[2] & 0xFFFFu));
+        H[i] = h;
+        L[i] = (k16 << 32) | (uint32_t)i;
+        atomicAdd(&sh[h >> 56], 1u);
+    }
+    __syncthreads();
+    if (sh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], sh[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+
+static int occupancy(const void *fn, int cus) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kWG, 0) != hipSuccess || per < 1) per = 1;
+    return per * cus;
+}
+
+template <int ITEMS>
+static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
+                                hipStream_t s, int cus) {
+    k_init<<<dim3(max(1u, min(nreq, 1024u))), dim3(kWG), 0, s>>>(w);
+    const int g_ext = (int)max(1u, min(tiles0, (uint32_t)(cus * 16)));
+    k_extract<ITEMS><<<dim3(g_ext), dim3(kWG), 0, s>>>(w, t);
+    static int g_sc = 0, g_hist = 0, g_loc = 0;
+    if (!g_sc) {
+        g_sc = occupancy(reinterpret_cast<const void *>(&k_scatter<ITEMS>), cus);
+        g_hist = occupancy(reinterpret_cast<const void *>(&k_hist<ITEMS>), cus);
+        g_loc = occupancy(reinterpret_cast<const void *>(&k_local), cus);
+    }
+    for (int lev = 0; lev < kMaxLev; lev++) {
+        if (lev > 0) k_hist<ITEMS><<<dim3(g_hist), dim3(kWG), 0, s>>>(w, t, lev);
+        k_scatter<ITEMS><<<dim3(g_sc), dim3(kWG), 0, s>>>(w, t, lev);
+    }
+    k_local<<<dim3(g_loc), dim3(kWG), 0, s>>>(w, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0, hipStream_t s,
+                            int cus) {
+    if (t.tile_items == 8) return launch_levels<8>(w, t, nreq, tiles0, s, cus);
+    return launch_levels<16>(w, t, nreq, tiles0, s, cus);
+}
+
+hipError_t launch_gather_batch(const Work &w, uint32_t nreq, hipStream_t s, int cus) {
+    (void)nreq;
+    const uint64_t blocks = (w.n + kWG - 1) / kWG;
+    const uint64_t cap = (uint64_t)cus * 64;
+    const uint32_t g = (uint32_t)(blocks < 1 ? 1 : (blocks < cap ? blocks : cap));
+    k_gather<<<dim3(g), dim3(kWG), 0, s>>>(w.reqs, w.hdr, w.idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,
+                                uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = (n + kWG - 1) / kWG;
+    k_gather_plain<<<dim3((uint32_t)blocks), dim3(kWG), 0, s>>>(rec, n_rec, idx, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_extract(const uint8_t *rec, uint64_t n, uint64_t *hi, uint64_t *lo, uint32_t *hist,
+                                hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = (n + kWG - 1) / kWG;
+    k_extract_plain<<<dim3((uint32_t)blocks), dim3(kWG), 0, s>>>(rec, n, hi, lo, hist);
+    return hipGetLastError();
+}
+
+}  // namespace ley

@@ -1,0 +1,189 @@
+"""Parity of the in-HBM GPU sort (leyenda_sort and its steps) with the CPU oracle.
+
+Every comparison is byte for byte: the output of a stable key sort is unique.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests.golden import pad_key, worked_example
+
+pytestmark = pytest.mark.gpu
+
+
+def run_sort(ley, rec: np.ndarray) -> np.ndarray:
+    import torch
+    dev = torch.from_numpy(np.ascontiguousarray(rec)).cuda()
+    out = ley.sort(dev)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def assert_same(got: np.ndarray, want: np.ndarray, what: str = ""):
+    if not np.array_equal(got, want):
+        diff = np.nonzero((got != want).any(axis=1))[0]
+        raise AssertionError(f"{what}: {diff.size} records differ, first at {int(diff[0])}")
+
+
+# ---- step-level parity ------------------------------------------------------------
+
+def test_extract_step(gpu):
+    import torch
+    rec = datagen.uniform(10007, 31)
+    hi, lo, hist = gpu.debug_extract(torch.from_numpy(rec).cuda())
+    torch.cuda.synchronize()
+    want_hi = np.zeros(rec.shape[0], dtype=np.uint64)
+    for b in range(8):
+        want_hi = (want_hi << np.uint64(8)) | rec[:, b].astype(np.uint64)
+    k16 = (rec[:, 8].astype(np.uint64) << np.uint64(8)) | rec[:, 9].astype(np.uint64)
+    want_lo = (k16 << np.uint64(32)) | np.arange(rec.shape[0], dtype=np.uint64)
+    np.testing.assert_array_equal(hi.cpu().numpy().view(np.uint64), want_hi)
+    np.testing.assert_array_equal(lo.cpu().numpy().view(np.uint64), want_lo)
+    np.testing.assert_array_equal(hist.cpu().numpy(), np.bincount(rec[:, 0], minlength=256))
+
+
+def test_extract_worked_example_histogram(gpu):
+    import torch
+    ex = worked_example()
+    rec = datagen.uniform(len(ex["keys"]), 5)
+    for i, k in enumerate(ex["keys"]):
+        rec[i, :10] = np.frombuffer(pad_key(k), dtype=np.uint8)
+    _, _, hist = gpu.debug_extract(torch.from_numpy(rec).cuda())
+    h = hist.cpu().numpy()
+    assert {b: int(c) for b, c in enumerate(h) if c} == ex["counts"]
+
+
+def test_gather_step(gpu):
+    import torch
+    rec = datagen.uniform(5000, 32)
+    idx = np.random.default_rng(1).permutation(5000).astype(np.int32)
+    out = gpu.debug_gather(torch.from_numpy(rec).cuda(), torch.from_numpy(idx).cuda())
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), rec[idx])
+
+
+# ---- end-to-end parity ------------------------------------------------------------
+
+SIZES = [1, 2, 3, 7, 255, 256, 257, 2047, 2048, 2049, 4095, 4096, 4097, 8193, 65537, 300_001]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_sort_uniform_sizes(gpu, n):
+    rec = datagen.uniform(n, 40 + n % 97)
+    assert_same(run_sort(gpu, rec), oracle.sort(rec), f"uniform n={n}")
+
+
+def _keys(n, seed):
+    return datagen.uniform(n, seed)
+
+
+def pattern(name: str, n: int) -> np.ndarray:
+    rec = datagen.uniform(n, 77)
+    rng = np.random.default_rng(5)
+    if name == "all_equal":
+        rec[:, :10] = 0x5A
+    elif name == "only_byte9":
+        rec[:, :9] = 0x11
+    elif name == "bytes_7_8_only":  # keys differ only across the hi/lo tuple split
+        rec[:, :7] = 0x22
+        rec[:, 9] = 0x33
+        rec[:, 7] = rng.integers(0, 3, n)
+        rec[:, 8] = rng.integers(0, 3, n)
+    elif name == "sorted":
+        rec = oracle.sort(rec)
+    elif name == "reverse":
+        rec = oracle.sort(rec)[::-1].copy()
+    elif name == "few_distinct":
+        vals = datagen.uniform(16, 3)[:, :10]
+        rec[:, :10] = vals[rng.integers(0, 16, n)]
+    elif name == "shared_prefix":  # first 5 bytes constant: constant digits are skipped
+        rec[:, :5] = 0xC3
+    elif name == "extremes":
+        rec[:, :10] = np.where(rng.integers(0, 2, (n, 10)) == 1, 0xFF, 0x00)
+    elif name == "skewed":
+        rec = datagen.skewed(n, 3)
+    elif name == "skewed_narrow":  # Zipf over 64 values: huge equal-prefix buckets + duplicates
+        rec = datagen.skewed(n, 8, nvals=64, dup_frac=0.2)
+    elif name == "one_big_bucket":  # 90% of keys share 8 bytes, differing in bytes 8..9
+        m = int(n * 0.9)
+        rec[:m, :8] = 0x7E
+    else:
+        raise KeyError(name)
+    return rec
+
+
+PATTERNS = ["all_equal", "only_byte9", "bytes_7_8_only", "sorted", "reverse", "few_distinct", "shared_prefix",
+            "extremes", "skewed", "skewed_narrow", "one_big_bucket"]
+
+
+@pytest.mark.parametrize("name", PATTERNS)
+def test_sort_patterns(gpu, name):
+    rec = pattern(name, 200_003)
+    assert_same(run_sort(gpu, rec), oracle.sort(rec), name)
+
+
+def test_sort_worked_example(gpu):
+    ex = worked_example()
+    rec = datagen.uniform(len(ex["keys"]), 9)
+    for i, k in enumerate(reversed(ex["keys"])):
+        rec[i, :10] = np.frombuffer(pad_key(k), dtype=np.uint8)
+    got = run_sort(gpu, rec)
+    assert [bytes(r[:10]).rstrip(b"\x00") for r in got] == ex["sorted"]
+    assert_same(got, oracle.sort(rec), "worked example")
+
+
+@pytest.mark.parametrize("params", [
+    dict(big_threshold=1), dict(big_threshold=64), dict(big_threshold=2048),
+    dict(tiny_threshold=1), dict(tiny_threshold=64), dict(tile_items=8),
+    dict(tile_items=8, big_threshold=300, tiny_threshold=5),
+])
+def test_params_do_not_change_output(gpu, params):
+    rec = pattern("skewed_narrow", 150_000)
+    want = oracle.sort(rec)
+    old = gpu.get_params()
+    try:
+        gpu.set_params(**params)
+        assert_same(run_sort(gpu, rec), want, str(params))
+    finally:
+        gpu.set_params(**old)
+
+
+def test_deterministic_repeats(gpu):
+    rec = datagen.skewed(400_000, 12)
+    a = run_sort(gpu, rec)
+    for _ in range(3):
+        assert_same(run_sort(gpu, rec), a, "repeat")
+
+
+def test_small_config_full_compare(gpu):
+    """1,000,000 uniform records (100 MB): the whole output against the oracle."""
+    rec = datagen.uniform(1_000_000, datagen.SEED_SMALL)
+    got = run_sort(gpu, rec)
+    assert_same(got, oracle.sort(rec), "1e6 uniform")
+
+
+def test_stats_uniform(gpu):
+    import torch
+    rec = datagen.uniform(1_000_000, 1)
+    run_sort(gpu, rec)
+    st = gpu.stats(torch.cuda.current_stream())
+    assert st["guard"] == 0
+    assert st["moved"][0] == 1_000_000  # the whole array is partitioned on byte 0
+    assert st["tasks"] > 0
+
+
+def test_error_codes(gpu):
+    import torch
+    lib = gpu.load()
+    a = torch.empty(1000 * 100, dtype=torch.uint8, device="cuda")
+    b = torch.empty(1000 * 100, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    assert lib.leyenda_sort(None, 10, b.data_ptr(), s) == -1
+    assert lib.leyenda_sort(a.data_ptr(), 10, a.data_ptr() + 500, s) == -1  # overlap
+    assert lib.leyenda_sort(a.data_ptr() + 1, 10, b.data_ptr(), s) == -1  # misaligned
+    assert lib.leyenda_sort(a.data_ptr(), 1 << 33, b.data_ptr(), s) == -5
+    assert lib.leyenda_sort(a.data_ptr(), 0, b.data_ptr(), s) == 0
+    with pytest.raises(gpu.LeyendaError):
+        gpu.set_params(big_threshold=0)
+    torch.cuda.synchronize()

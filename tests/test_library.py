@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every declared entry point (no GPU work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions() -> list[str]:
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(leyenda_\w+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["leyenda_sort", "leyenda_sort_runs", "leyenda_merge", "leyenda_sort_batch",
+                 "leyenda_load_params", "leyenda_workspace_bytes", "leyenda_status_string"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1909_08006_amd as ley
+    lib = ley.load()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_param_checks():
+    import paper_1909_08006_amd as ley
+    lib = ley.load()
+    assert lib.leyenda_status_string(-3) == b"does not fit the device budget"
+    assert lib.leyenda_status_string(0) == b"ok"
+    p = ley.get_params()
+    assert p["digit_bits"] == 8 and p["local_capacity"] == 2048
+    for bad in [dict(tile_items=3), dict(big_threshold=0), dict(big_threshold=4096), dict(tiny_threshold=0),
+                dict(tiny_threshold=65), dict(digit_bits=4)]:
+        with pytest.raises(ley.LeyendaError):
+            ley.set_params(**bad)
+    assert ley.get_params() == p
+
+
+def test_load_params_json(tmp_path):
+    import paper_1909_08006_amd as ley
+    old = ley.get_params()
+    try:
+        f = tmp_path / "params.json"
+        f.write_text('{"tile_items": 8, "big_threshold": 1000, "tiny_threshold": 16, "comment": "x"}')
+        p = ley.load_params(str(f))
+        assert p["tile_items"] == 8 and p["big_threshold"] == 1000 and p["tiny_threshold"] == 16
+    finally:
+        ley.set_params(**old)
+
+
+def test_workspace_bytes_grows_with_n():
+    import paper_1909_08006_amd as ley
+    a, b = ley.workspace_bytes(1000), ley.workspace_bytes(100_000_000)
+    assert 0 < a < b
+    assert b < 100_000_000 * 64  # tuples (32 B) + index (4 B) + tables: well under 64 B per record
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    import paper_1909_08006_amd as ley
+    monkeypatch.setattr(ley, "_lib", None)
+    monkeypatch.setattr(ley, "LIB_PATH", "/nonexistent/libleyenda.so")
+    with pytest.raises(RuntimeError, match="not built"):
+        ley.load()
