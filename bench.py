@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Throughput of the in-HBM record sort on one MI355X.
+
+Workload: 100,000,000 records x 100 bytes (10 GB), 10-byte keys of i.i.d.
+uniform bytes and 90-byte uniform payloads from seed 2 (synthetic stand-in for
+the paper's 10 GB internal-sort dataset, Section 4.1).  Input and output are
+resident in HBM before the timed region; one step = one full leyenda_sort
+(extraction, partition levels, local sorts, record gather).
+
+Prints one JSON line: GB/s of records sorted, the roofline of the dominant
+kernel (from HIP events recorded around each phase on the sort's stream),
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GB/s of 100-byte records sorted (10 GB, in-HBM); p50/p99 latency batched"
+HBM_PEAK_GBS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "gather_internal_1e8_pmc.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1909_08006_amd", "csrc", "sort_kernels.hip")
+
+# Algorithmic bytes per record of each phase (element granularity, no line overfetch):
+#   extract   reads the 10 key bytes, writes a 16-byte (key, index) tuple
+#   partition per level: reads + writes 16-byte tuples (32 B) for every moved key,
+#             and levels >= 1 first read 8 key bytes per key for their histograms
+#   local     reads 16-byte tuples, writes a 4-byte index
+#   gather    reads the 4-byte index and the 100-byte record, writes 100 bytes
+ALG_BYTES = {"extract": 26, "local": 20, "gather": 204}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pmc_traffic(n: int):
+    """HBM bytes per gather launch from the committed rocprofv3 counter summary,
+    or None if absent or taken on a different kernel source."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    fields = {}
+    for line in open(PMC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, _, v = line.strip().partition("=")
+            fields[k.strip()] = v.strip()
+    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    if fields.get("kernel_source_sha256_16") != src_hash or int(fields.get("n_records", -1)) != n:
+        return None
+    return int(float(fields["hbm_bytes_per_launch"]))
+
+
+def cpu_baseline(host_u8, n_sample: int) -> dict:
+    import oracle
+    rec = host_u8[: n_sample * 100].numpy().reshape(n_sample, 100)
+    log(f"cpu baseline: oracle sort of {n_sample} records ...")
+    t0 = time.perf_counter()
+    oracle.sort(rec)
+    dt = time.perf_counter() - t0
+    return {"value": round(n_sample * 100 / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_sample:,} records ({n_sample * 100 / 1e9:.1f} GB) of the same workload; "
+                      f"qsort of (key, index) by memcmp then record gather, one thread, {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=100_000_000, help="records (default: the 10 GB workload)")
+    ap.add_argument("--cpu-sample", type=int, default=4_000_000, help="records the oracle sorts for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 2 GB device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build sorts on one GPU only; multi-GPU runs are not part of it "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+    import datagen
+    import paper_1909_08006_amd as ley
+
+    ley.load()
+    n = args.n
+    log(f"generating {n:,} records ({n * 100 / 1e9:.1f} GB, seed {datagen.SEED_INTERNAL}) ...")
+    host = torch.empty(n * 100, dtype=torch.uint8, pin_memory=True)
+    datagen.fill_uniform(host.data_ptr(), n, datagen.SEED_INTERNAL)
+    dev = host.to("cuda:0", non_blocking=True)
+    out = torch.empty_like(dev)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    if args.calibrate_copy:
+        src = torch.empty(2_000_000_000, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy: 2,000,000,000 bytes read + written")
+
+    log(f"warmup {args.warmup} ...")
+    for _ in range(args.warmup):
+        ley.sort(dev, out, stream)
+    torch.cuda.synchronize()
+    st = ley.stats(stream)
+
+    log(f"timing {args.steps} steps ...")
+    ley.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ley.sort(dev, out, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases, calls = ley.profile_read()
+    ley.profile_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    gbs = n * 100 / (ms / 1e3) / 1e9
+    avg = {k: v / max(calls, 1) for k, v in phases.items()}
+
+    # output sanity: keys non-decreasing (device-side check of big-endian key words)
+    keys = out.view(n, 100)[:, :10].to(torch.int64)
+    hi = torch.zeros(n, dtype=torch.int64, device=out.device)
+    for b in range(7):
+        hi = hi * 256 + keys[:, b]
+    lo = (keys[:, 7] * 256 + keys[:, 8]) * 256 + keys[:, 9]
+    ordered = bool(((hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] >= lo[:-1]))).all().item())
+    del keys, hi, lo
+
+    moved = sum(st["moved"])
+    passes = moved / n
+    b_alg = 250 + 32 * passes
+    part_bytes = 32 * moved + 8 * sum(st["moved"][1:])
+    alg = {"extract": ALG_BYTES["extract"] * n, "partition": part_bytes, "local": ALG_BYTES["local"] * n,
+           "gather": ALG_BYTES["gather"] * n}
+    dom = max(avg, key=lambda k: avg[k])
+    achieved = alg[dom] / (avg[dom] / 1e3) / 1e9
+    traffic = pmc_traffic(n) if dom == "gather" else None
+
+    res = {
+        "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "internal sort, 100,000,000 x 100-byte records (10 GB) in HBM, uniform 10-byte keys",
+                   "n_records": n, "record_bytes": 100, "key_bytes": 10, "seed": datagen.SEED_INTERNAL,
+                   "params": ley.get_params()},
+        "roofline": {"bound": "hbm", "kernel": {"gather": "k_gather_plain", "extract": "k_extract",
+                                                "partition": "k_hist+k_scatter", "local": "k_local"}[dom],
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "phases_ms": {k: round(v, 4) for k, v in avg.items()},
+        "phase_alg_gbs": {k: round(alg[k] / (avg[k] / 1e3) / 1e9, 1) for k in avg if avg[k] > 0},
+        "partition_passes": round(passes, 4),
+        "b_alg_bytes_per_record": round(b_alg, 2),
+        "sort_roofline_frac": round(b_alg * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "floor_frac_210B": round(210 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "output_keys_ordered": ordered,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(host, min(args.cpu_sample, n))
+    print(json.dumps(res), flush=True)
+    return 0 if ordered else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -169,6 +169,18 @@ typedef struct {
 /* Synchronizes `stream` and reports the plan of the last leyenda_sort on it. */
 int leyenda_sort_stats(void *stream, leyenda_stats *out);
 
+/* Phase timing with HIP events recorded on each sort's own stream.  While
+ * enabled, every leyenda_sort records events between its phases; phase_ms
+ * receives the summed milliseconds since the last enable of
+ *   [0] tuple extraction (+ first-digit histograms),
+ *   [1] device-wide partition levels (histograms, planning, scatter passes),
+ *   [2] local sorts in LDS,
+ *   [3] record gather,
+ * and calls the number of sorts timed.  leyenda_profile_read synchronizes
+ * the events it reads. */
+int leyenda_profile_enable(int on);
+int leyenda_profile_read(double *phase_ms, uint64_t *calls);
+
 const char *leyenda_status_string(int status);
 const char *leyenda_last_error(void);
 /* Frees every cached workspace (synchronizes the device first). */

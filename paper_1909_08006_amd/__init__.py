@@ -75,6 +75,8 @@ def load():
         "leyenda_release_workspaces": ([], i32),
         "leyenda_debug_extract": ([vp, u64, vp, vp, vp, vp], i32),
         "leyenda_debug_gather": ([vp, u64, vp, u64, vp, vp], i32),
+        "leyenda_profile_enable": ([i32], i32),
+        "leyenda_profile_read": ([ctypes.POINTER(ctypes.c_double), P64], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -208,6 +210,21 @@ def stats(stream=None) -> dict:
     _check(load().leyenda_sort_stats(_stream_ptr(stream), ctypes.byref(s)), "leyenda_sort_stats")
     return {"levels": int(s.levels), "segments": list(s.segments), "moved": [int(x) for x in s.moved],
             "tasks": int(s.tasks), "guard": int(s.guard)}
+
+
+PHASES = ("extract", "partition", "local", "gather")
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(load().leyenda_profile_enable(1 if on else 0), "leyenda_profile_enable")
+
+
+def profile_read() -> tuple[dict, int]:
+    """Summed per-phase milliseconds (HIP events) and the number of sorts timed."""
+    ms = (ctypes.c_double * 4)()
+    calls = ctypes.c_uint64(0)
+    _check(load().leyenda_profile_read(ms, ctypes.byref(calls)), "leyenda_profile_read")
+    return {k: float(ms[i]) for i, k in enumerate(PHASES)}, int(calls.value)
 
 
 def release_workspaces() -> None:

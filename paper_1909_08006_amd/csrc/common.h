@@ -11,7 +11,8 @@ constexpr int kRB = 8;             // digit width: 256-way buckets per pass (Alg
 constexpr int kRadix = 1 << kRB;
 constexpr int kWG = 256;           // threads per workgroup, all kernels (4 wave64)
 constexpr int kWaves = kWG / 64;
-constexpr int kNH = 4;             // digit windows histogrammed per read (constant windows are skipped)
+constexpr int kMaxRep = 64;        // histogram replicas per bucket (spreads the tiles' atomics)
+constexpr int kRepWords = kRadix + 8;  // replica: 256 counts + OR / OR-of-complement masks (4 x u64)
 constexpr int kMaxLev = (kKeyBits + kRB - 1) / kRB;  // device-wide partition levels at most
 constexpr int kLocalCap = 2048;    // keys per local (LDS) sort task
 constexpr int kLocalItems = kLocalCap / kWG;
@@ -29,11 +30,11 @@ struct Seg {
     uint32_t count;
     uint32_t first_tile;  // its tiles at this level are [first_tile, first_tile + ntiles)
     uint32_t ntiles;
-    uint32_t done;        // histogram tiles finished (the last one plans the segment)
-    uint16_t pos;         // key bit where histogram window 0 starts
+    uint32_t rep_first;   // its histogram replicas are [rep_first, rep_first + nrep)
+    uint16_t pos;         // key bit where the histogram digit starts
     uint16_t spos;        // key bit of the partition digit, or kNoScatter
     uint8_t buf;          // tuple buffer holding the segment
-    uint8_t jstar;        // histogram window turned into bucket offsets
+    uint8_t nrep;
     uint16_t req;         // batch request the segment belongs to
 };
 static_assert(sizeof(Seg) == 32, "Seg layout");
@@ -54,6 +55,7 @@ struct Ctl {
     uint32_t nseg[kMaxLev + 2];
     uint32_t ntiles[kMaxLev + 2];
     uint32_t tile_ctr[kMaxLev + 2];
+    uint32_t rep_ctr[kMaxLev + 2];
     uint32_t ntask;
     uint32_t task_ctr;
     uint32_t guard;
@@ -69,6 +71,8 @@ struct Req {
     uint64_t n;
     uint32_t first_tile;  // its level-0 tiles
     uint32_t ntiles;
+    uint32_t rep_first;   // its level-0 histogram replicas
+    uint32_t nrep;
 };
 
 // Batch header: sizes the kernels read from device memory, so a captured
@@ -94,29 +98,31 @@ struct Work {
     uint32_t *idx;       // sorted record index per output position
     Ctl *ctl;
     Seg *segs[2];        // by level parity
-    uint32_t *hist[2];   // [seg][kNH][kRadix], by level parity
+    uint32_t *rep[2];    // histogram replicas [rep][kRepWords], by level parity
     uint32_t *tile_seg[2];
     unsigned long long *status;  // [tile][kRadix]
     Task *tasks;
     Req *reqs;
     Hdr *hdr;
     uint64_t n;          // keys in the tuple space
-    uint32_t max_seg, max_tiles, max_tasks, max_reqs;
+    uint32_t max_seg, max_tiles, max_tasks, max_reqs, max_reps;
 };
 
 // Workspace sizing for a tuple space of n keys and up to `reqs` requests.
 struct Layout {
     uint64_t n;
-    uint32_t max_seg, max_tiles, max_tasks, max_reqs;
-    size_t off_H0, off_H1, off_L0, off_L1, off_idx, off_ctl, off_seg0, off_seg1, off_hist0,
-        off_hist1, off_ts0, off_ts1, off_status, off_tasks, off_reqs, off_hdr, total;
+    uint32_t max_seg, max_tiles, max_tasks, max_reqs, max_reps;
+    size_t off_H0, off_H1, off_L0, off_L1, off_idx, off_ctl, off_seg0, off_seg1, off_rep0,
+        off_rep1, off_ts0, off_ts1, off_status, off_tasks, off_reqs, off_hdr, total;
 };
 Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t);
 Work bind_layout(const Layout &L, void *base);
 
 // Launch wrappers (sort_kernels.hip).  All return hipError_t of the launches.
+// ev (optional): three events recorded after extraction, after the
+// partition levels and after the local sorts.
 hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
-                            hipStream_t s, int cus);
+                            hipStream_t s, int cus, hipEvent_t *ev = nullptr);
 hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,
                                 uint64_t n, hipStream_t s);
 hipError_t launch_gather_batch(const Work &w, uint32_t nreq, hipStream_t s, int cus);

@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/leyenda.h"
 #include "common.h"
@@ -91,6 +92,7 @@ Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t) {
     L.max_tiles = (uint32_t)std::min<uint64_t>(tiles, 0xFFFFFFFFull);
     L.max_tasks = (uint32_t)std::min<uint64_t>(tasks, 0xFFFFFFFFull);
     L.max_reqs = std::max<uint32_t>(reqs, 1);
+    L.max_reps = L.max_tiles;  // a bucket has at most one replica per tile
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
     const size_t nn = std::max<uint64_t>(n, 1);
@@ -102,8 +104,8 @@ Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t) {
     L.off_ctl = take(sizeof(Ctl));
     L.off_seg0 = take((size_t)L.max_seg * sizeof(Seg));
     L.off_seg1 = take((size_t)L.max_seg * sizeof(Seg));
-    L.off_hist0 = take((size_t)L.max_seg * kNH * kRadix * 4);
-    L.off_hist1 = take((size_t)L.max_seg * kNH * kRadix * 4);
+    L.off_rep0 = take((size_t)L.max_reps * kRepWords * 4);
+    L.off_rep1 = take((size_t)L.max_reps * kRepWords * 4);
     L.off_ts0 = take((size_t)L.max_tiles * 4);
     L.off_ts1 = take((size_t)L.max_tiles * 4);
     L.off_status = take((size_t)L.max_tiles * kRadix * 8);
@@ -125,8 +127,8 @@ Work bind_layout(const Layout &L, void *base) {
     w.ctl = reinterpret_cast<Ctl *>(b + L.off_ctl);
     w.segs[0] = reinterpret_cast<Seg *>(b + L.off_seg0);
     w.segs[1] = reinterpret_cast<Seg *>(b + L.off_seg1);
-    w.hist[0] = reinterpret_cast<uint32_t *>(b + L.off_hist0);
-    w.hist[1] = reinterpret_cast<uint32_t *>(b + L.off_hist1);
+    w.rep[0] = reinterpret_cast<uint32_t *>(b + L.off_rep0);
+    w.rep[1] = reinterpret_cast<uint32_t *>(b + L.off_rep1);
     w.tile_seg[0] = reinterpret_cast<uint32_t *>(b + L.off_ts0);
     w.tile_seg[1] = reinterpret_cast<uint32_t *>(b + L.off_ts1);
     w.status = reinterpret_cast<unsigned long long *>(b + L.off_status);
@@ -138,6 +140,7 @@ Work bind_layout(const Layout &L, void *base) {
     w.max_tiles = L.max_tiles;
     w.max_tasks = L.max_tasks;
     w.max_reqs = L.max_reqs;
+    w.max_reps = L.max_reps;
     return w;
 }
 
@@ -234,10 +237,60 @@ __global__ void k_setup_single(Req *reqs, Hdr *hdr, const uint8_t *in, uint8_t *
                                uint32_t tiles) {
     Req r;
     r.in = in; r.out = out; r.start = 0; r.n = n; r.first_tile = 0; r.ntiles = tiles;
+    r.rep_first = 0; r.nrep = tiles < (uint32_t)kMaxRep ? tiles : (uint32_t)kMaxRep;
     reqs[0] = r;
     Hdr h;
     h.n_total = n; h.nreq = 1; h.tiles0 = tiles;
     *hdr = h;
+}
+
+// ---------------------------------------------------------------------------
+// phase timing with HIP events on the sort's own stream
+
+struct ProfCall {
+    hipEvent_t e[5];
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfCall> g_prof_pending;
+static double g_prof_ms[4] = {0, 0, 0, 0};
+static uint64_t g_prof_calls = 0;
+
+static bool prof_start(ProfCall *pc, hipStream_t s) {
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (!g_prof_on || g_prof_pending.size() >= 4096) return false;
+    }
+    for (int i = 0; i < 5; i++) {
+        if (hipEventCreate(&pc->e[i]) != hipSuccess) {
+            for (int k = 0; k < i; k++) (void)hipEventDestroy(pc->e[k]);
+            return false;
+        }
+    }
+    (void)hipEventRecord(pc->e[0], s);
+    return true;
+}
+
+static void prof_finish(const ProfCall &pc, hipStream_t s) {
+    (void)hipEventRecord(pc.e[4], s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back(pc);
+}
+
+static int prof_drain() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &pc : g_prof_pending) {
+        hipError_t e = hipEventSynchronize(pc.e[4]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        for (int i = 0; i < 4; i++) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, pc.e[i], pc.e[i + 1]) == hipSuccess) g_prof_ms[i] += ms;
+        }
+        g_prof_calls++;
+        for (int i = 0; i < 5; i++) (void)hipEventDestroy(pc.e[i]);
+    }
+    g_prof_pending.clear();
+    return LEYENDA_OK;
 }
 
 int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t) {
@@ -248,12 +301,15 @@ int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t 
     remember_layout(stream, L);
     const Work w = bind_layout(L, ws);
     const uint32_t tiles0 = (uint32_t)((n + t.tile - 1) / t.tile);
+    ProfCall pc;
+    const bool prof = prof_start(&pc, stream);
     k_setup_single<<<1, 1, 0, stream>>>(w.reqs, w.hdr, static_cast<const uint8_t *>(records_dev),
                                         static_cast<uint8_t *>(out_dev), n, tiles0);
-    hipError_t e = launch_sort_core(w, t, 1, tiles0, stream, device_cus());
+    hipError_t e = launch_sort_core(w, t, 1, tiles0, stream, device_cus(), prof ? pc.e + 1 : nullptr);
     if (e != hipSuccess) return hip_fail(e, "sort kernels");
     e = launch_gather_single(static_cast<const uint8_t *>(records_dev), n, w.idx, static_cast<uint8_t *>(out_dev),
                              n, stream);
+    if (prof) prof_finish(pc, stream);
     if (e != hipSuccess) return hip_fail(e, "gather kernel");
     return LEYENDA_OK;
 }
@@ -356,6 +412,26 @@ extern "C" const char *leyenda_status_string(int status) {
 extern "C" const char *leyenda_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" int leyenda_release_workspaces(void) { return release_all(); }
+
+extern "C" int leyenda_profile_enable(int on) {
+    int rc = prof_drain();
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    for (double &v : g_prof_ms) v = 0;
+    g_prof_calls = 0;
+    return LEYENDA_OK;
+}
+
+extern "C" int leyenda_profile_read(double *phase_ms, uint64_t *calls) {
+    if (!phase_ms || !calls) return fail(LEYENDA_EINVAL, "leyenda_profile_read: NULL");
+    int rc = prof_drain();
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (int i = 0; i < 4; i++) phase_ms[i] = g_prof_ms[i];
+    *calls = g_prof_calls;
+    return LEYENDA_OK;
+}
 
 extern "C" int leyenda_debug_extract(const void *records_dev, uint64_t n, uint64_t *hi_dev, uint64_t *lo_dev,
                                      uint32_t *hist_dev, void *stream) {

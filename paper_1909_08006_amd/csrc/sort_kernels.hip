@@ -4,10 +4,10 @@
 // Section 3.1) on the key-pointer tuples of Section 3.2:
 //
 //   k_init      request table -> level-0 buckets and tile map
-//   k_extract   (key, index) tuple per record + histograms of the leading
-//               digits (AlphaSort-style key-pointer extraction, Section 3.2);
-//               the workgroup finishing a bucket's last tile plans it
-//   k_hist      per level >= 1: histograms of big buckets, then planning
+//   k_extract   (key, index) tuple per record + first-digit histogram and key
+//               masks (AlphaSort-style key-pointer extraction, Section 3.2)
+//   k_hist      per level >= 1: digit histograms and key masks of big buckets
+//   k_plan      per level: bucket policy of Algorithm 1 for every big bucket
 //   k_scatter   per level: stable device-wide partition of big buckets by one
 //               digit (ParallelRadixSort, "cache aware scattering": tiles are
 //               ranked and staged in LDS, then written as runs), with tile
@@ -98,7 +98,8 @@ constexpr uint32_t kSpinLimit = 1u << 24;
 // the tile that points at it (defence against a fired capacity guard).
 __device__ __forceinline__ bool seg_ok(const Work &w, const Seg &sg, uint32_t tile) {
     return sg.count > 0 && sg.start + sg.count <= w.n && tile >= sg.first_tile &&
-           tile - sg.first_tile < sg.ntiles && sg.buf <= 1;
+           tile - sg.first_tile < sg.ntiles && sg.buf <= 1 && sg.nrep >= 1 && sg.nrep <= kMaxRep &&
+           (uint64_t)sg.rep_first + sg.nrep <= w.max_reps;
 }
 
 // ---------------------------------------------------------------------------
@@ -134,23 +135,51 @@ __device__ void new_segment(const Work &w, const Tune &tu, int lev, uint64_t sta
                             uint32_t pos, uint8_t buf, uint16_t req) {
     const uint32_t s = atomicAdd(&w.ctl->nseg[lev], 1u);
     const uint32_t nt = (count + tu.tile - 1) / tu.tile;
+    const uint32_t nr = min(nt, (uint32_t)kMaxRep);
     const uint32_t ft = atomicAdd(&w.ctl->ntiles[lev], nt);
-    if (s >= w.max_seg || (uint64_t)ft + nt > w.max_tiles) { atomicOr(&w.ctl->guard, 4u); return; }
+    const uint32_t rf = atomicAdd(&w.ctl->rep_ctr[lev], nr);
+    if (s >= w.max_seg || (uint64_t)ft + nt > w.max_tiles || (uint64_t)rf + nr > w.max_reps) {
+        atomicOr(&w.ctl->guard, 4u);
+        if (s < w.max_seg) {  // leave a harmless entry: no tiles, nothing to zero
+            Seg g{};
+            g.spos = kNoScatter;
+            w.segs[lev & 1][s] = g;
+        }
+        return;
+    }
     Seg g;
-    g.start = start; g.count = count; g.first_tile = ft; g.ntiles = nt; g.done = 0;
-    g.pos = (uint16_t)pos; g.spos = kNoScatter; g.buf = buf; g.jstar = 0; g.req = req;
+    g.start = start; g.count = count; g.first_tile = ft; g.ntiles = nt; g.rep_first = rf; g.nrep = (uint8_t)nr;
+    g.pos = (uint16_t)pos; g.spos = kNoScatter; g.buf = buf; g.req = req;
     w.segs[lev & 1][s] = g;
 }
 
+// First key bit that differs between keys of a bucket, from its OR and
+// OR-of-complement masks; kKeyBits if every key is equal.
+__device__ __forceinline__ uint32_t first_varying(uint64_t orh, uint64_t ornh, uint64_t orl, uint64_t ornl) {
+    const uint64_t vh = orh & ornh, vl = orl & ornl & 0xFFFFu;
+    if (vh) return (uint32_t)__clzll(vh);
+    if (vl) return 64u + ((uint32_t)__clz((uint32_t)vl) - 16u);
+    return kKeyBits;
+}
+
+// Planning of one big bucket (Algorithm 1): if its digit at `pos` splits it,
+// it gets a partition pass and its sub-buckets become either big buckets of
+// the next level, or local-sort tasks (consecutive small sub-buckets packed
+// together up to the local capacity); if the digit is constant, the bucket
+// moves to the next level unmoved, starting at its first varying key bit;
+// if no key bit varies, it is already in order.  Whole workgroup.
 __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s) {
     __shared__ uint32_t p_cnt[kRadix];
     __shared__ uint32_t p_base[kRadix];
     __shared__ uint32_t p_tmp[kWaves];
+    __shared__ unsigned long long p_mask[4];
+    __shared__ uint32_t p_tstart[kRadix];
+    __shared__ uint32_t p_tcnt[kRadix];
+    __shared__ uint32_t p_ntask, p_slot;
     const uint32_t d = threadIdx.x;
     Seg *sp = &w.segs[lev & 1][s];
     const Seg sg = *sp;
-    uint32_t *hs = w.hist[lev & 1] + (size_t)s * kNH * kRadix;
-
+    if (sg.count == 0 || sg.nrep == 0) return;  // placeholder left by a fired guard
     if (sg.count <= tu.big) {  // small bucket: one local-sort task as it is
         if (d == 0) {
             sp->spos = kNoScatter;
@@ -158,37 +187,32 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
         }
         return;
     }
-    uint32_t c[kNH];
-#pragma unroll
-    for (int j = 0; j < kNH; j++) c[j] = ld_agent32(&hs[j * kRadix + d]);
-    int jstar = -1;
-#pragma unroll
-    for (int j = 0; j < kNH; j++) {
-        if (jstar < 0 && sg.pos + j * kRB < kKeyBits) {
-            const int isconst = __syncthreads_or(c[j] == sg.count);
-            if (!isconst) jstar = j;
-        }
+    uint32_t *rp = w.rep[lev & 1] + (size_t)sg.rep_first * kRepWords;
+    uint32_t cnt = 0;
+    for (uint32_t r = 0; r < sg.nrep; r++) cnt += rp[(size_t)r * kRepWords + d];
+    if (d < 4) {
+        unsigned long long m = 0;
+        for (uint32_t r = 0; r < sg.nrep; r++)
+            m |= reinterpret_cast<const unsigned long long *>(rp + (size_t)r * kRepWords + kRadix)[d];
+        p_mask[d] = m;
     }
-    if (jstar < 0) {  // every window constant over the bucket: skip them without moving data
-        const uint32_t np = sg.pos + kNH * kRB;
+    const int isconst = __syncthreads_or(cnt == sg.count);
+    if (isconst) {  // digit at pos is constant over the bucket: skip ahead without moving data
         if (d == 0) {
             sp->spos = kNoScatter;
-            if (np >= kKeyBits) emit_sorted(w, sg.start, sg.count, sg.buf);
-            else new_segment(w, tu, lev + 1, sg.start, sg.count, np, sg.buf, sg.req);
+            const uint32_t f = first_varying(p_mask[0], p_mask[1], p_mask[2], p_mask[3]);
+            if (f >= kKeyBits) emit_sorted(w, sg.start, sg.count, sg.buf);
+            else new_segment(w, tu, lev + 1, sg.start, sg.count, max(f, (uint32_t)sg.pos + kRB), sg.buf, sg.req);
         }
         return;
     }
-    const uint32_t p = sg.pos + jstar * kRB;
-    uint32_t cnt = c[0];
-#pragma unroll
-    for (int j = 1; j < kNH; j++) if (j == jstar) cnt = c[j];
+    const uint32_t p = sg.pos;
     const uint32_t base = block_excl_scan(cnt, p_tmp);
-    hs[jstar * kRadix + d] = base;  // bucket offsets used by k_scatter
+    rp[d] = base;  // replica 0 now holds the bucket offsets used by k_scatter
     p_cnt[d] = cnt;
     p_base[d] = base;
     if (d == 0) {
         sp->spos = (uint16_t)p;
-        sp->jstar = (uint8_t)jstar;
         atomicAdd(&w.ctl->moved[lev], (unsigned long long)sg.count);
     }
     const uint8_t cbuf = sg.buf ^ 1;
@@ -199,44 +223,63 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
     }
     __syncthreads();
     if (d == 0) {  // pack consecutive small buckets into tasks of at most kLocalCap keys
-        uint64_t cur_start = 0;
-        uint32_t cur = 0;
+        uint32_t nt = 0, cur_start = 0, cur = 0;
         for (int e = 0; e < kRadix; e++) {
             const uint32_t ce = p_cnt[e];
             if (ce == 0) continue;
             if (ce > tu.big) {
-                if (cur) { emit_task(w, cur_start, cur, cbuf, 0, (uint16_t)p); cur = 0; }
+                if (cur) { p_tstart[nt] = cur_start; p_tcnt[nt++] = cur; cur = 0; }
                 continue;
             }
-            if (cur && cur + ce > (uint32_t)kLocalCap) { emit_task(w, cur_start, cur, cbuf, 0, (uint16_t)p); cur = 0; }
-            if (cur == 0) cur_start = sg.start + p_base[e];
+            if (cur && cur + ce > (uint32_t)kLocalCap) { p_tstart[nt] = cur_start; p_tcnt[nt++] = cur; cur = 0; }
+            if (cur == 0) cur_start = p_base[e];
             cur += ce;
         }
-        if (cur) emit_task(w, cur_start, cur, cbuf, 0, (uint16_t)p);
+        if (cur) { p_tstart[nt] = cur_start; p_tcnt[nt++] = cur; }
+        uint32_t slot = atomicAdd(&w.ctl->ntask, nt);
+        if ((uint64_t)slot + nt > w.max_tasks) { atomicOr(&w.ctl->guard, 1u); nt = 0; }
+        p_ntask = nt;
+        p_slot = slot;
+    }
+    __syncthreads();
+    for (uint32_t t = d; t < p_ntask; t += kWG) {
+        Task tk;
+        tk.start = sg.start + p_tstart[t]; tk.count = p_tcnt[t]; tk.buf = cbuf; tk.flags = 0; tk.pos = (uint16_t)p;
+        w.tasks[p_slot + t] = tk;
     }
     __syncthreads();
 }
 
-// The workgroup that finishes the last histogram tile of bucket s plans it.
-__device__ __forceinline__ void finish_tile(const Work &w, const Tune &tu, int lev, uint32_t s,
-                                            uint32_t ntiles_s) {
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t prev = atomicAdd(&w.segs[lev & 1][s].done, 1u);
-        s_last = (prev == ntiles_s - 1);
+// Adds a tile's LDS histogram and key masks into one replica of its bucket.
+__device__ __forceinline__ void flush_tile_hist(uint32_t *rep, const uint32_t *sh, const unsigned long long *smask) {
+    const uint32_t v = sh[threadIdx.x];
+    if (v) atomicAdd(&rep[threadIdx.x], v);
+    if (threadIdx.x < 4) {
+        const unsigned long long m = smask[threadIdx.x];
+        if (m) atomicOr(reinterpret_cast<unsigned long long *>(rep + kRadix) + threadIdx.x, m);
     }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        plan_segment(w, tu, lev, s);
+}
+
+// Reduces per-thread key masks (OR of h, OR of ~h, OR of k16, OR of ~k16) over the workgroup.
+__device__ __forceinline__ void block_masks(uint64_t oh, uint64_t onh, uint64_t ol, uint64_t onl,
+                                            unsigned long long *smask) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        oh |= __shfl_xor(oh, off);
+        onh |= __shfl_xor(onh, off);
+        ol |= __shfl_xor(ol, off);
+        onl |= __shfl_xor(onl, off);
     }
-    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        atomicOr(&smask[0], (unsigned long long)oh);
+        atomicOr(&smask[1], (unsigned long long)onh);
+        atomicOr(&smask[2], (unsigned long long)ol);
+        atomicOr(&smask[3], (unsigned long long)onl);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// k_init: level-0 buckets (one per request) and their tile map
+// k_init: level-0 buckets (one per request), their tile map and replicas
 
 __global__ __launch_bounds__(kWG) void k_init(Work w) {
     const Hdr hd = *w.hdr;
@@ -251,29 +294,35 @@ __global__ __launch_bounds__(kWG) void k_init(Work w) {
     }
     for (uint32_t r = blockIdx.x; r < hd.nreq; r += gridDim.x) {
         const Req rq = w.reqs[r];
+        const bool ok = (uint64_t)rq.first_tile + rq.ntiles <= w.max_tiles &&
+                        (uint64_t)rq.rep_first + rq.nrep <= w.max_reps && rq.nrep <= kMaxRep;
         if (threadIdx.x == 0) {
             Seg g;
-            g.start = rq.start; g.count = (uint32_t)rq.n; g.first_tile = rq.first_tile;
-            g.ntiles = rq.ntiles; g.done = 0; g.pos = 0; g.spos = kNoScatter; g.buf = 0;
-            g.jstar = 0; g.req = (uint16_t)r;
+            g.start = rq.start; g.count = ok ? (uint32_t)rq.n : 0; g.first_tile = rq.first_tile;
+            g.ntiles = rq.ntiles; g.rep_first = rq.rep_first; g.nrep = (uint8_t)rq.nrep; g.pos = 0;
+            g.spos = kNoScatter; g.buf = 0; g.req = (uint16_t)r;
             w.segs[0][r] = g;
+            if (!ok) atomicOr(&w.ctl->guard, 256u);
         }
+        if (!ok) continue;
         for (uint32_t k = threadIdx.x; k < rq.ntiles; k += kWG) w.tile_seg[0][rq.first_tile + k] = r;
-        uint32_t *hs = w.hist[0] + (size_t)r * kNH * kRadix;
-        for (uint32_t i = threadIdx.x; i < kNH * kRadix; i += kWG) hs[i] = 0;
+        uint32_t *rp = w.rep[0] + (size_t)rq.rep_first * kRepWords;
+        for (uint32_t i = threadIdx.x; i < rq.nrep * kRepWords; i += kWG) rp[i] = 0;
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_extract: tuples + leading-digit histograms of every record
+// k_extract: tuples + first-digit histogram and key masks of every record
 
 template <int ITEMS>
 __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
-    __shared__ uint32_t sh[kNH][kRadix];
+    __shared__ uint32_t sh[kRadix];
+    __shared__ unsigned long long smask[4];
     const uint32_t ntiles = min(w.ctl->ntiles[0], w.max_tiles);
     const uint32_t nreq = w.hdr->nreq;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        for (uint32_t i = threadIdx.x; i < kNH * kRadix; i += kWG) (&sh[0][0])[i] = 0;
+        sh[threadIdx.x] = 0;
+        if (threadIdx.x < 4) smask[threadIdx.x] = 0;
         w.status[(size_t)tile * kRadix + threadIdx.x] = 0;
         const uint32_t s = w.tile_seg[0][tile];
         if (s >= nreq || s >= w.max_seg) { if (threadIdx.x == 0) atomicOr(&w.ctl->guard, 8u); __syncthreads(); continue; }
@@ -294,6 +343,7 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
         }
         uint64_t *H = w.H[0] + sg.start + local0;
         uint64_t *L = w.L[0] + sg.start + local0;
+        uint64_t oh = 0, onh = 0, ol = 0, onl = 0;
 #pragma unroll
         for (int u = 0; u < ITEMS; u++) {
             const uint32_t q = u * kWG + threadIdx.x;
@@ -302,71 +352,76 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
                 const uint64_t k16 = __builtin_bswap16((uint16_t)(c[u] & 0xFFFFu));
                 H[q] = h;
                 L[q] = (k16 << 32) | (uint32_t)(local0 + q);
-#pragma unroll
-                for (int j = 0; j < kNH; j++) atomicAdd(&sh[j][(h >> (56 - 8 * j)) & 0xFF], 1u);
+                atomicAdd(&sh[h >> 56], 1u);
+                oh |= h; onh |= ~h; ol |= k16; onl |= (~k16) & 0xFFFFu;
             }
         }
+        block_masks(oh, onh, ol, onl, smask);
         __syncthreads();
-        uint32_t *hs = w.hist[0] + (size_t)s * kNH * kRadix;
-#pragma unroll
-        for (int j = 0; j < kNH; j++) {
-            const uint32_t v = sh[j][threadIdx.x];
-            if (v) atomicAdd(&hs[j * kRadix + threadIdx.x], v);
-        }
-        finish_tile(w, tu, 0, s, sg.ntiles);
+        flush_tile_hist(w.rep[0] + ((size_t)sg.rep_first + (tile - sg.first_tile) % sg.nrep) * kRepWords, sh, smask);
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_hist: histograms of big buckets at level lev >= 1, then planning
+// k_hist: digit histogram and key masks of the big buckets of level lev >= 1
 
 template <int ITEMS>
 __global__ __launch_bounds__(kWG) void k_hist(Work w, Tune tu, int lev) {
-    __shared__ uint32_t sh[kNH][kRadix];
+    __shared__ uint32_t sh[kRadix];
+    __shared__ unsigned long long smask[4];
     const uint32_t ntiles = min(w.ctl->ntiles[lev], w.max_tiles);
     const uint32_t nseg = min(w.ctl->nseg[lev], w.max_seg);
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        for (uint32_t i = threadIdx.x; i < kNH * kRadix; i += kWG) (&sh[0][0])[i] = 0;
+        sh[threadIdx.x] = 0;
+        if (threadIdx.x < 4) smask[threadIdx.x] = 0;
         w.status[(size_t)tile * kRadix + threadIdx.x] = 0;
         const uint32_t s = w.tile_seg[lev & 1][tile];
         if (s >= nseg) { if (threadIdx.x == 0) atomicOr(&w.ctl->guard, 8u); __syncthreads(); continue; }
         const Seg sg = w.segs[lev & 1][s];
-        if (!seg_ok(w, sg, tile)) { if (threadIdx.x == 0) atomicOr(&w.ctl->guard, 8u); __syncthreads(); continue; }
+        if (!seg_ok(w, sg, tile) || sg.pos >= kKeyBits) {
+            if (threadIdx.x == 0) atomicOr(&w.ctl->guard, 8u);
+            __syncthreads();
+            continue;
+        }
         const uint64_t local0 = (uint64_t)(tile - sg.first_tile) * tu.tile;
         const uint32_t nvalid = (uint32_t)min<uint64_t>(tu.tile, sg.count - local0);
         const uint64_t *H = w.H[sg.buf] + sg.start + local0;
         const uint64_t *L = w.L[sg.buf] + sg.start + local0;
-        const bool needL = sg.pos + kNH * kRB > 64;
         __syncthreads();
         uint64_t h[ITEMS], l[ITEMS];
 #pragma unroll
         for (int u = 0; u < ITEMS; u++) {
             const uint32_t q = u * kWG + threadIdx.x;
             h[u] = 0; l[u] = 0;
-            if (q < nvalid) {
-                h[u] = H[q];
-                if (needL) l[u] = L[q];
-            }
+            if (q < nvalid) { h[u] = H[q]; l[u] = L[q]; }
         }
+        uint64_t oh = 0, onh = 0, ol = 0, onl = 0;
 #pragma unroll
         for (int u = 0; u < ITEMS; u++) {
             const uint32_t q = u * kWG + threadIdx.x;
             if (q < nvalid) {
-#pragma unroll
-                for (int j = 0; j < kNH; j++) {
-                    const uint32_t p = sg.pos + j * kRB;
-                    if (p < kKeyBits) atomicAdd(&sh[j][digit_at(h[u], l[u], p)], 1u);
-                }
+                const uint64_t k16 = (l[u] >> 32) & 0xFFFFu;
+                atomicAdd(&sh[digit_at(h[u], l[u], sg.pos)], 1u);
+                oh |= h[u]; onh |= ~h[u]; ol |= k16; onl |= (~k16) & 0xFFFFu;
             }
         }
+        block_masks(oh, onh, ol, onl, smask);
         __syncthreads();
-        uint32_t *hs = w.hist[lev & 1] + (size_t)s * kNH * kRadix;
-#pragma unroll
-        for (int j = 0; j < kNH; j++) {
-            const uint32_t v = sh[j][threadIdx.x];
-            if (v) atomicAdd(&hs[j * kRadix + threadIdx.x], v);
-        }
-        finish_tile(w, tu, lev, s, sg.ntiles);
+        flush_tile_hist(w.rep[lev & 1] + ((size_t)sg.rep_first + (tile - sg.first_tile) % sg.nrep) * kRepWords, sh,
+                        smask);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_plan: plans every big bucket of level lev (after its histogram pass)
+
+__global__ __launch_bounds__(kWG) void k_plan(Work w, Tune tu, int lev) {
+    const uint32_t nseg = min(w.ctl->nseg[lev], w.max_seg);
+    for (uint32_t s = blockIdx.x; s < nseg; s += gridDim.x) {
+        plan_segment(w, tu, lev, s);
+        __syncthreads();
     }
 }
 
@@ -396,7 +451,7 @@ __global__ __launch_bounds__(kWG) void k_scatter(Work w, Tune tu, int lev) {
         const uint32_t s = w.tile_seg[lev & 1][tile];
         if (s >= nseg) continue;
         const Seg sg = w.segs[lev & 1][s];
-        if (sg.spos == kNoScatter || !seg_ok(w, sg, tile) || sg.spos >= kKeyBits || sg.jstar >= kNH) continue;
+        if (sg.spos == kNoScatter || !seg_ok(w, sg, tile) || sg.spos >= kKeyBits) continue;
         const uint64_t seg_end = sg.start + sg.count;
         const uint32_t k = tile - sg.first_tile;
         const uint64_t local0 = (uint64_t)k * TILE;
@@ -452,7 +507,7 @@ __global__ __launch_bounds__(kWG) void k_scatter(Work w, Tune tu, int lev) {
             st_agent(st, kFlagInc | (excl + tot));
         }
         const uint32_t lb = block_excl_scan(tot, tmp);
-        const uint32_t bb = w.hist[lev & 1][(size_t)s * kNH * kRadix + sg.jstar * kRadix + tid];
+        const uint32_t bb = w.rep[lev & 1][(size_t)sg.rep_first * kRepWords + tid];
         lbase[tid] = lb;
         gbase[tid] = sg.start + bb + excl - lb;
         __syncthreads();
@@ -483,14 +538,16 @@ __global__ __launch_bounds__(kWG) void k_scatter(Work w, Tune tu, int lev) {
             }
         }
     }
-    // set up level lev + 1: tile map and zeroed histograms of its buckets
+    // set up level lev + 1: tile map and zeroed histogram replicas of its buckets
     const uint32_t nn = min(w.ctl->nseg[lev + 1], w.max_seg);
     for (uint32_t s2 = blockIdx.x; s2 < nn; s2 += gridDim.x) {
         const Seg g = w.segs[(lev + 1) & 1][s2];
-        if ((uint64_t)g.first_tile + g.ntiles <= w.max_tiles)
-            for (uint32_t t = tid; t < g.ntiles; t += kWG) w.tile_seg[(lev + 1) & 1][g.first_tile + t] = s2;
-        uint32_t *hs = w.hist[(lev + 1) & 1] + (size_t)s2 * kNH * kRadix;
-        for (uint32_t i = tid; i < kNH * kRadix; i += kWG) hs[i] = 0;
+        if (g.count == 0 || (uint64_t)g.first_tile + g.ntiles > w.max_tiles ||
+            (uint64_t)g.rep_first + g.nrep > w.max_reps)
+            continue;
+        for (uint32_t t = tid; t < g.ntiles; t += kWG) w.tile_seg[(lev + 1) & 1][g.first_tile + t] = s2;
+        uint32_t *rp = w.rep[(lev + 1) & 1] + (size_t)g.rep_first * kRepWords;
+        for (uint32_t i = tid; i < g.nrep * kRepWords; i += kWG) rp[i] = 0;
     }
 }
 
@@ -753,28 +810,33 @@ static int occupancy(const void *fn, int cus) {
 
 template <int ITEMS>
 static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
-                                hipStream_t s, int cus) {
+                                hipStream_t s, int cus, hipEvent_t *ev) {
     k_init<<<dim3(max(1u, min(nreq, 1024u))), dim3(kWG), 0, s>>>(w);
     const int g_ext = (int)max(1u, min(tiles0, (uint32_t)(cus * 16)));
     k_extract<ITEMS><<<dim3(g_ext), dim3(kWG), 0, s>>>(w, t);
+    if (ev) (void)hipEventRecord(ev[0], s);
     static int g_sc = 0, g_hist = 0, g_loc = 0;
     if (!g_sc) {
         g_sc = occupancy(reinterpret_cast<const void *>(&k_scatter<ITEMS>), cus);
         g_hist = occupancy(reinterpret_cast<const void *>(&k_hist<ITEMS>), cus);
         g_loc = occupancy(reinterpret_cast<const void *>(&k_local), cus);
     }
+    const int g_plan = cus * 4;
     for (int lev = 0; lev < kMaxLev; lev++) {
         if (lev > 0) k_hist<ITEMS><<<dim3(g_hist), dim3(kWG), 0, s>>>(w, t, lev);
+        k_plan<<<dim3(g_plan), dim3(kWG), 0, s>>>(w, t, lev);
         k_scatter<ITEMS><<<dim3(g_sc), dim3(kWG), 0, s>>>(w, t, lev);
     }
+    if (ev) (void)hipEventRecord(ev[1], s);
     k_local<<<dim3(g_loc), dim3(kWG), 0, s>>>(w, t);
+    if (ev) (void)hipEventRecord(ev[2], s);
     return hipGetLastError();
 }
 
 hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0, hipStream_t s,
-                            int cus) {
-    if (t.tile_items == 8) return launch_levels<8>(w, t, nreq, tiles0, s, cus);
-    return launch_levels<16>(w, t, nreq, tiles0, s, cus);
+                            int cus, hipEvent_t *ev) {
+    if (t.tile_items == 8) return launch_levels<8>(w, t, nreq, tiles0, s, cus, ev);
+    return launch_levels<16>(w, t, nreq, tiles0, s, cus, ev);
 }
 
 hipError_t launch_gather_batch(const Work &w, uint32_t nreq, hipStream_t s, int cus) {
