@@ -1,0 +1,580 @@
+// Limited-memory (external) sort: sorted runs, then a k-way merge of the runs,
+// streamed between pinned host memory and a capped amount of device memory
+// (Section 3.2, "Overlapping Computation with I/O": a sort stage writes sorted
+// intermediate runs while reading and sorting the next chunk; a merge stage
+// merges the runs one output partition at a time with a K-way merge, with
+// reading, merging and writing overlapped).
+//
+// Run formation (leyenda_sort_runs): runs of R records go host -> device on
+// one copy stream, are sorted on a compute stream by the in-HBM sort, and go
+// back device -> host on a second copy stream, double-buffered so the three
+// overlap.
+//
+// Merge (leyenda_merge): the output is cut into chunks of C records at exact
+// ranks (merge-path partitioning): a co-rank kernel finds, for every chunk
+// boundary, how many records of each run precede it, reading keys straight
+// from the pinned runs.  Each chunk's k run slices then go host -> device, are
+// merged on the GPU by rounds of pairwise merge-path merges of (key, index)
+// tuples, gathered into output order and sent back, again double-buffered.
+// Ties between runs resolve to the lower run, which is input order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "runtime.h"
+
+namespace ley {
+
+constexpr int kMaxRuns = 256;       // merge fan-in: one co-rank thread per run
+constexpr uint32_t kMergeTile = 2048;
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+struct Key80 {
+    uint64_t h;
+    uint32_t l;  // key bytes 8..9, big-endian
+};
+
+__device__ __forceinline__ Key80 load_key(const uint8_t *rec) {
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(rec);
+    const uint32_t a = p[0], b = p[1], c = p[2];
+    Key80 k;
+    k.h = __builtin_bswap64(((uint64_t)b << 32) | a);
+    k.l = __builtin_bswap16((uint16_t)(c & 0xFFFFu));
+    return k;
+}
+
+// (key_a, run_a, pos_a) < (key_b, run_b, pos_b) in (key, run, position) order.
+__device__ __forceinline__ bool tuple_less(const Key80 &a, uint32_t ra, uint64_t pa, const Key80 &b, uint32_t rb,
+                                           uint64_t pb) {
+    if (a.h != b.h) return a.h < b.h;
+    if (a.l != b.l) return a.l < b.l;
+    if (ra != rb) return ra < rb;
+    return pa < pb;
+}
+
+// ---------------------------------------------------------------------------
+// k_corank: for output rank b (one workgroup per boundary), the number s_i of
+// records of each run i among the b first records of the merged output.
+// Multisequence selection: keep lo_i <= s_i <= hi_i; take the middle record v
+// of the widest interval, count the records below v in every run by binary
+// search, and move lo (v below the boundary) or hi (v above it).  Every step
+// halves one interval, so it ends after at most sum(log2 len_i) + k steps.
+
+__global__ __launch_bounds__(kWG) void k_corank(const uint8_t *runs, const uint64_t *run_off, uint32_t k,
+                                                const uint64_t *targets, uint64_t *splits, uint32_t *err) {
+    __shared__ uint64_t lo[kMaxRuns], hi[kMaxRuns];
+    __shared__ unsigned long long red_w[kWaves];
+    __shared__ uint32_t red_i[kWaves];
+    __shared__ unsigned long long sum_w[kWaves];
+    __shared__ Key80 s_v;
+    const uint32_t i = threadIdx.x, lane = i & 63, wv = i >> 6;
+    const uint64_t b = targets[blockIdx.x];
+    const uint64_t off_i = i < k ? run_off[i] : 0;
+    const uint64_t len_i = i < k ? run_off[i + 1] - run_off[i] : 0;
+    lo[i] = 0;
+    hi[i] = len_i;
+    const uint32_t max_steps = 64u * kMaxRuns + 64u;
+    uint32_t step = 0;
+    for (;; step++) {
+        __syncthreads();
+        // widest interval (ties to the lowest run)
+        unsigned long long wdt = hi[i] - lo[i];
+        uint32_t who = i;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const unsigned long long w2 = __shfl_xor(wdt, o);
+            const uint32_t i2 = __shfl_xor(who, o);
+            if (w2 > wdt || (w2 == wdt && i2 < who)) { wdt = w2; who = i2; }
+        }
+        if (lane == 0) { red_w[wv] = wdt; red_i[wv] = who; }
+        __syncthreads();
+        unsigned long long bw = red_w[0];
+        uint32_t j = red_i[0];
+#pragma unroll
+        for (int q = 1; q < kWaves; q++)
+            if (red_w[q] > bw || (red_w[q] == bw && red_i[q] < j)) { bw = red_w[q]; j = red_i[q]; }
+        if (bw == 0 || step >= max_steps) break;
+        const uint64_t mid = (lo[j] + hi[j]) >> 1;
+        if (i == 0) s_v = load_key(runs + (run_off[j] + mid) * kRec);
+        __syncthreads();
+        const Key80 v = s_v;
+        // records of run i below v, over the whole run
+        uint64_t r = 0;
+        if (i < k) {
+            if (i == j) {
+                r = mid;
+            } else {
+                uint64_t a = 0, c = len_i;
+                while (a < c) {
+                    const uint64_t m = (a + c) >> 1;
+                    const Key80 e = load_key(runs + (off_i + m) * kRec);
+                    if (tuple_less(e, i, m, v, j, mid)) a = m + 1; else c = m;
+                }
+                r = a;
+            }
+        }
+        unsigned long long sum = r;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
+        if (lane == 0) sum_w[wv] = sum;
+        __syncthreads();
+        unsigned long long R = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; q++) R += sum_w[q];
+        if (i < k) {
+            if (R < b) {  // v is among the first b records
+                if (i == j) lo[i] = mid + 1;
+                else if (r > lo[i]) lo[i] = r;
+            } else {      // v and everything above it come after the boundary
+                if (r < hi[i]) hi[i] = r;
+            }
+        }
+    }
+    __syncthreads();
+    if (step >= max_steps && i == 0) atomicOr(err, 1u);
+    if (i < k) splits[(size_t)blockIdx.x * k + i] = lo[i];
+}
+
+// ---------------------------------------------------------------------------
+// merge of one chunk: tuples of the staged records, pairwise merge-path
+// rounds, gather
+
+__global__ __launch_bounds__(kWG) void k_merge_extract(const uint8_t *stage, uint64_t n, uint64_t *H, uint64_t *L) {
+    const uint64_t q = (uint64_t)blockIdx.x * kWG + threadIdx.x;
+    if (q >= n) return;
+    const Key80 k = load_key(stage + q * kRec);
+    H[q] = k.h;
+    L[q] = ((uint64_t)k.l << 32) | (uint32_t)q;
+}
+
+struct MergePair {
+    uint32_t a_off, a_len, b_len, first_tile;  // sequence B starts at a_off + a_len; output covers the same range
+};
+
+__device__ __forceinline__ bool tl(uint64_t h1, uint64_t l1, uint64_t h2, uint64_t l2) {
+    return h1 < h2 || (h1 == h2 && l1 < l2);
+}
+
+// Elements of A taken among the first `diag` merged outputs (merge path).
+__device__ __forceinline__ uint32_t merge_path(const uint64_t *AH, const uint64_t *AL, uint32_t alen,
+                                               const uint64_t *BH, const uint64_t *BL, uint32_t blen,
+                                               uint32_t diag) {
+    uint32_t a = diag > blen ? diag - blen : 0u, c = min(diag, alen);
+    while (a < c) {
+        const uint32_t m = (a + c) >> 1;
+        const uint32_t bi = diag - m - 1;
+        if (tl(AH[m], AL[m], BH[bi], BL[bi])) a = m + 1; else c = m;
+    }
+    return a;
+}
+
+__global__ __launch_bounds__(kWG) void k_merge_pairs(const MergePair *pairs, uint32_t npairs, uint32_t ntiles,
+                                                     const uint64_t *SH, const uint64_t *SL, uint64_t *DH,
+                                                     uint64_t *DL) {
+    __shared__ uint64_t th[kMergeTile], tlo[kMergeTile];
+    __shared__ uint32_t s_i0, s_i1;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        uint32_t p = 0;
+        while (p + 1 < npairs && pairs[p + 1].first_tile <= t) p++;
+        const MergePair mp = pairs[p];
+        const uint32_t total = mp.a_len + mp.b_len;
+        const uint32_t d0 = (t - mp.first_tile) * kMergeTile, d1 = min(d0 + kMergeTile, total);
+        const uint64_t *AH = SH + mp.a_off, *AL = SL + mp.a_off;
+        const uint64_t *BH = AH + mp.a_len, *BL = AL + mp.a_len;
+        __syncthreads();
+        if (threadIdx.x == 0) s_i0 = merge_path(AH, AL, mp.a_len, BH, BL, mp.b_len, d0);
+        if (threadIdx.x == 64) s_i1 = merge_path(AH, AL, mp.a_len, BH, BL, mp.b_len, d1);
+        __syncthreads();
+        const uint32_t i0 = s_i0, i1 = s_i1, j0 = d0 - i0, j1 = d1 - i1;
+        const uint32_t na = i1 - i0, nb = j1 - j0;
+        for (uint32_t x = threadIdx.x; x < na; x += kWG) { th[x] = AH[i0 + x]; tlo[x] = AL[i0 + x]; }
+        for (uint32_t y = threadIdx.x; y < nb; y += kWG) { th[na + y] = BH[j0 + y]; tlo[na + y] = BL[j0 + y]; }
+        __syncthreads();
+        uint64_t *OH = DH + mp.a_off + d0, *OL = DL + mp.a_off + d0;
+        for (uint32_t x = threadIdx.x; x < na + nb; x += kWG) {
+            const uint64_t h = th[x], l = tlo[x];
+            // rank in the other list: elements below (h, l)
+            uint32_t a, c;
+            const uint32_t ob = x < na ? na : 0u, oe = x < na ? na + nb : na;
+            a = ob; c = oe;
+            while (a < c) {
+                const uint32_t m = (a + c) >> 1;
+                if (tl(th[m], tlo[m], h, l)) a = m + 1; else c = m;
+            }
+            const uint32_t pos = (x < na ? x : x - na) + (a - ob);
+            OH[pos] = h;
+            OL[pos] = l;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_gather_lo(const uint8_t *stage, const uint64_t *L, uint8_t *out, uint64_t n) {
+    __shared__ uint32_t sidx[kWG];
+    const uint64_t g0 = (uint64_t)blockIdx.x * kWG;
+    const uint32_t nr = (uint32_t)min<uint64_t>(kWG, n - g0);
+    if (threadIdx.x < nr) sidx[threadIdx.x] = (uint32_t)L[g0 + threadIdx.x];
+    __syncthreads();
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(stage);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(out) + g0 * 25;
+    uint32_t v[25];
+#pragma unroll
+    for (int u = 0; u < 25; u++) {
+        const uint32_t q = threadIdx.x + kWG * u, r = q / 25u, kk = q - 25u * r;
+        v[u] = 0;
+        if (r < nr && sidx[r] < n) v[u] = src[(uint64_t)sidx[r] * 25 + kk];
+    }
+#pragma unroll
+    for (int u = 0; u < 25; u++) {
+        const uint32_t q = threadIdx.x + kWG * u, r = q / 25u;
+        if (r < nr) dst[q] = v[u];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+namespace {
+
+// Device address of pinned host memory, or nullptr if p is not pinned host memory.
+void *pinned_device_ptr(const void *p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (a.type != hipMemoryTypeHost || !a.devicePointer) return nullptr;
+    if (a.hostPointer) return static_cast<char *>(a.devicePointer) + (static_cast<const char *>(p) -
+                                                                      static_cast<const char *>(a.hostPointer));
+    return a.devicePointer;
+}
+
+struct Pipe {
+    hipStream_t cs = nullptr, h2d = nullptr, d2h = nullptr;
+    hipEvent_t ev[3][2] = {};  // [h2d_done, compute_done, d2h_done][buffer]
+    void *arena = nullptr;
+    int init(hipStream_t caller) {
+        hipError_t e;
+        if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+        if ((e = hipStreamCreateWithFlags(&h2d, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+        if ((e = hipStreamCreateWithFlags(&d2h, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+        for (auto &row : ev)
+            for (auto &x : row)
+                if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+        // start after the caller's earlier work on its stream
+        hipEvent_t start;
+        if ((e = hipEventCreateWithFlags(&start, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+        (void)hipEventRecord(start, caller);
+        (void)hipStreamWaitEvent(cs, start, 0);
+        (void)hipStreamWaitEvent(h2d, start, 0);
+        (void)hipStreamWaitEvent(d2h, start, 0);
+        (void)hipEventDestroy(start);
+        return LEYENDA_OK;
+    }
+    int alloc(size_t bytes) {
+        hipError_t e = hipMalloc(&arena, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            arena = nullptr;
+            return fail(LEYENDA_ENOMEM, "hipMalloc(%zu) for the external sort failed", bytes);
+        }
+        return LEYENDA_OK;
+    }
+    int finish() {
+        hipError_t e1 = cs ? hipStreamSynchronize(cs) : hipSuccess;
+        hipError_t e2 = h2d ? hipStreamSynchronize(h2d) : hipSuccess;
+        hipError_t e3 = d2h ? hipStreamSynchronize(d2h) : hipSuccess;
+        if (e1 != hipSuccess) return hip_fail(e1, "compute stream");
+        if (e2 != hipSuccess) return hip_fail(e2, "copy stream");
+        if (e3 != hipSuccess) return hip_fail(e3, "copy stream");
+        return LEYENDA_OK;
+    }
+    ~Pipe() {
+        if (cs) (void)hipStreamSynchronize(cs);
+        if (h2d) (void)hipStreamSynchronize(h2d);
+        if (d2h) (void)hipStreamSynchronize(d2h);
+        if (arena) (void)hipFree(arena);
+        for (auto &row : ev)
+            for (auto &x : row)
+                if (x) (void)hipEventDestroy(x);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (h2d) (void)hipStreamDestroy(h2d);
+        if (d2h) (void)hipStreamDestroy(d2h);
+    }
+};
+
+size_t a256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Device bytes one run of r records needs: two input and two output buffers
+// (so upload, sort and download overlap) plus the sort's workspace.
+uint64_t run_bytes(uint64_t r, const Tune &t) { return 4 * a256(r * kRec) + plan_layout(r, 1, t).total + 4096; }
+
+// Device bytes per merge chunk of c records: two staging and two output
+// buffers plus two tuple buffers (16 bytes per record each).
+uint64_t chunk_bytes(uint64_t c) { return 4 * a256(c * kRec) + 4 * a256(c * 8) + 4096; }
+
+int plan_runs_t(uint64_t n, uint64_t budget, const Tune &t, uint64_t *R, uint64_t *K) {
+    if (n == 0) { *R = 0; *K = 0; return LEYENDA_OK; }
+    uint64_t lo = 1, hi = std::min<uint64_t>(n, LEYENDA_MAX_RECORDS);
+    if (run_bytes(1, t) > budget) return fail(LEYENDA_EBUDGET, "budget of %llu bytes is below one run's footprint",
+                                              (unsigned long long)budget);
+    while (lo < hi) {
+        const uint64_t m = lo + (hi - lo + 1) / 2;
+        if (run_bytes(m, t) <= budget) lo = m; else hi = m - 1;
+    }
+    const uint64_t k = (n + lo - 1) / lo;
+    *K = k;
+    *R = (n + k - 1) / k;  // equal runs
+    return LEYENDA_OK;
+}
+
+}  // namespace
+
+}  // namespace ley
+
+using namespace ley;
+
+extern "C" int leyenda_plan_runs(uint64_t n, uint64_t device_budget_bytes, uint64_t *run_records, uint64_t *num_runs) {
+    if (!run_records || !num_runs) return fail(LEYENDA_EINVAL, "leyenda_plan_runs: NULL");
+    return plan_runs_t(n, device_budget_bytes, tune_of(current_params()), run_records, num_runs);
+}
+
+extern "C" int leyenda_sort_runs(const void *host_records, uint64_t n, uint64_t device_budget_bytes, void *host_runs,
+                                 uint64_t *run_bounds, uint64_t k_max, uint64_t *k_out, void *stream) {
+    if (!run_bounds || !k_out) return fail(LEYENDA_EINVAL, "leyenda_sort_runs: NULL run_bounds or k_out");
+    *k_out = 0;
+    if (n == 0) { run_bounds[0] = 0; return LEYENDA_OK; }
+    if (!host_records || !host_runs) return fail(LEYENDA_EINVAL, "leyenda_sort_runs: NULL buffer");
+    if ((reinterpret_cast<uintptr_t>(host_records) | reinterpret_cast<uintptr_t>(host_runs)) & 3u)
+        return fail(LEYENDA_EINVAL, "leyenda_sort_runs: buffers must be 4-byte aligned");
+    if (host_records != host_runs && overlaps(host_records, n * kRec, host_runs, n * kRec))
+        return fail(LEYENDA_EINVAL, "leyenda_sort_runs: host_runs partly overlaps host_records");
+    if (!pinned_device_ptr(host_records) || !pinned_device_ptr(host_runs))
+        return fail(LEYENDA_EINVAL, "leyenda_sort_runs: host buffers must be pinned (hipHostMalloc / pin_memory)");
+    const Tune t = tune_of(current_params());
+    uint64_t R = 0, K = 0;
+    int rc = plan_runs_t(n, device_budget_bytes, t, &R, &K);
+    if (rc) return rc;
+    if (K > k_max) return fail(LEYENDA_EBUDGET, "leyenda_sort_runs: %llu runs needed, k_max is %llu",
+                               (unsigned long long)K, (unsigned long long)k_max);
+    Pipe P;
+    if ((rc = P.init(static_cast<hipStream_t>(stream)))) return rc;
+    const size_t rb = a256(R * kRec);
+    const size_t ws_bytes = plan_layout(R, 1, t).total;
+    if ((rc = P.alloc(4 * rb + ws_bytes))) return rc;
+    char *base = static_cast<char *>(P.arena);
+    uint8_t *in[2] = {reinterpret_cast<uint8_t *>(base), reinterpret_cast<uint8_t *>(base + rb)};
+    uint8_t *out[2] = {reinterpret_cast<uint8_t *>(base + 2 * rb), reinterpret_cast<uint8_t *>(base + 3 * rb)};
+    void *ws = base + 4 * rb;
+    const uint8_t *src = static_cast<const uint8_t *>(host_records);
+    uint8_t *dst = static_cast<uint8_t *>(host_runs);
+    hipError_t e = hipSuccess;
+    for (uint64_t r = 0; r < K; r++) {
+        const int b = (int)(r & 1);
+        const uint64_t off = r * R, len = std::min<uint64_t>(R, n - off);
+        run_bounds[r] = off;
+        // upload after the sort that last read in[b]
+        if (r >= 2) e = hipStreamWaitEvent(P.h2d, P.ev[1][b], 0);
+        if (e == hipSuccess) e = hipMemcpyAsync(in[b], src + off * kRec, len * kRec, hipMemcpyHostToDevice, P.h2d);
+        if (e == hipSuccess) e = hipEventRecord(P.ev[0][b], P.h2d);
+        // sort after the upload, and after the download that last read out[b]
+        if (e == hipSuccess) e = hipStreamWaitEvent(P.cs, P.ev[0][b], 0);
+        if (e == hipSuccess && r >= 2) e = hipStreamWaitEvent(P.cs, P.ev[2][b], 0);
+        if (e != hipSuccess) return hip_fail(e, "leyenda_sort_runs: enqueue");
+        if ((rc = sort_device_ws(in[b], len, out[b], P.cs, t, ws))) return rc;
+        e = hipEventRecord(P.ev[1][b], P.cs);
+        // download the sorted run over its own input range
+        if (e == hipSuccess) e = hipStreamWaitEvent(P.d2h, P.ev[1][b], 0);
+        if (e == hipSuccess) e = hipMemcpyAsync(dst + off * kRec, out[b], len * kRec, hipMemcpyDeviceToHost, P.d2h);
+        if (e == hipSuccess) e = hipEventRecord(P.ev[2][b], P.d2h);
+        if (e != hipSuccess) return hip_fail(e, "leyenda_sort_runs: enqueue");
+    }
+    run_bounds[K] = n;
+    if ((rc = P.finish())) return rc;
+    *k_out = K;
+    return LEYENDA_OK;
+}
+
+extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, uint64_t k, void *host_out,
+                             uint64_t device_budget_bytes, void *stream) {
+    if (!run_bounds) return fail(LEYENDA_EINVAL, "leyenda_merge: NULL run_bounds");
+    if (k == 0) return LEYENDA_OK;
+    if (k > (uint64_t)kMaxRuns) return fail(LEYENDA_EINVAL, "leyenda_merge: at most %d runs", kMaxRuns);
+    if (run_bounds[0] != 0) return fail(LEYENDA_EINVAL, "leyenda_merge: run_bounds[0] must be 0");
+    for (uint64_t i = 0; i < k; i++)
+        if (run_bounds[i + 1] < run_bounds[i]) return fail(LEYENDA_EINVAL, "leyenda_merge: run_bounds decrease");
+    const uint64_t n = run_bounds[k];
+    if (n == 0) return LEYENDA_OK;
+    if (!host_runs || !host_out) return fail(LEYENDA_EINVAL, "leyenda_merge: NULL buffer");
+    if ((reinterpret_cast<uintptr_t>(host_runs) | reinterpret_cast<uintptr_t>(host_out)) & 3u)
+        return fail(LEYENDA_EINVAL, "leyenda_merge: buffers must be 4-byte aligned");
+    if (overlaps(host_runs, n * kRec, host_out, n * kRec))
+        return fail(LEYENDA_EINVAL, "leyenda_merge: host_out overlaps host_runs");
+    const uint8_t *runs_dev = static_cast<const uint8_t *>(pinned_device_ptr(host_runs));
+    if (!runs_dev || !pinned_device_ptr(host_out))
+        return fail(LEYENDA_EINVAL, "leyenda_merge: host buffers must be pinned (hipHostMalloc / pin_memory)");
+    for (uint64_t i = 0; i < k; i++)
+        if (run_bounds[i + 1] - run_bounds[i] > LEYENDA_MAX_RECORDS)
+            return fail(LEYENDA_ETOOBIG, "leyenda_merge: run %llu too long", (unsigned long long)i);
+
+    // chunk size from the budget: staging, output and tuple buffers plus the
+    // tables (run offsets, boundaries, co-rank splits, merge pair lists)
+    const uint32_t rounds = [&] { uint32_t r = 0; while ((1ull << r) < k) r++; return r; }();
+    auto tables_for = [&](uint64_t chunks) -> uint64_t {
+        return a256((k + 1) * 8) + a256(chunks * 8) + a256((chunks + 1) * k * 8) +
+               a256(chunks * (rounds + 1) * ((k + 1) / 2 + 1) * sizeof(MergePair)) + 256;
+    };
+    auto merge_bytes = [&](uint64_t m) -> uint64_t {
+        return 4 * a256(m * kRec) + 4 * a256(m * 8) + tables_for((n + m - 1) / m);
+    };
+    if (merge_bytes(std::min<uint64_t>(n, 1)) > device_budget_bytes)
+        return fail(LEYENDA_EBUDGET, "leyenda_merge: budget too small");
+    uint64_t lo = 1, hi = std::min<uint64_t>(n, LEYENDA_MAX_RECORDS);
+    while (lo < hi) {
+        const uint64_t m = lo + (hi - lo + 1) / 2;
+        if (merge_bytes(m) <= device_budget_bytes) lo = m; else hi = m - 1;
+    }
+    const uint64_t nch = (n + lo - 1) / lo;
+    const uint64_t C = (n + nch - 1) / nch;  // equal chunks
+
+    Pipe P;
+    int rc = P.init(static_cast<hipStream_t>(stream));
+    if (rc) return rc;
+    const size_t sb = a256(C * kRec), tb = a256(C * 8);
+    const size_t n_tab = (size_t)(nch + 1) * k;
+    const size_t pair_cap = (size_t)nch * (rounds + 1) * ((k + 1) / 2 + 1);
+    if ((rc = P.alloc(4 * sb + 4 * tb + tables_for(nch)))) return rc;
+    char *base = static_cast<char *>(P.arena);
+    uint8_t *stage[2] = {reinterpret_cast<uint8_t *>(base), reinterpret_cast<uint8_t *>(base + sb)};
+    uint8_t *outb[2] = {reinterpret_cast<uint8_t *>(base + 2 * sb), reinterpret_cast<uint8_t *>(base + 3 * sb)};
+    uint64_t *TH[2] = {reinterpret_cast<uint64_t *>(base + 4 * sb), reinterpret_cast<uint64_t *>(base + 4 * sb + tb)};
+    uint64_t *TL[2] = {reinterpret_cast<uint64_t *>(base + 4 * sb + 2 * tb),
+                       reinterpret_cast<uint64_t *>(base + 4 * sb + 3 * tb)};
+    char *tp = base + 4 * sb + 4 * tb;
+    uint64_t *d_off = reinterpret_cast<uint64_t *>(tp); tp += a256((k + 1) * 8);
+    uint64_t *d_tgt = reinterpret_cast<uint64_t *>(tp); tp += a256(nch * 8);
+    uint64_t *d_split = reinterpret_cast<uint64_t *>(tp); tp += a256(n_tab * 8);
+    MergePair *d_pairs = reinterpret_cast<MergePair *>(tp); tp += a256(pair_cap * sizeof(MergePair));
+    uint32_t *d_err = reinterpret_cast<uint32_t *>(tp);
+
+    // 1. exact chunk boundaries (co-rank of ranks C, 2C, ...)
+    std::vector<uint64_t> split((nch + 1) * k, 0);
+    for (uint64_t i = 0; i < k; i++) split[nch * k + i] = run_bounds[i + 1] - run_bounds[i];
+    hipError_t e = hipSuccess;
+    if (nch > 1) {
+        std::vector<uint64_t> tgt(nch - 1);
+        for (uint64_t c = 1; c < nch; c++) tgt[c - 1] = c * C;
+        e = hipMemcpyAsync(d_off, run_bounds, (k + 1) * 8, hipMemcpyHostToDevice, P.cs);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_tgt, tgt.data(), (nch - 1) * 8, hipMemcpyHostToDevice, P.cs);
+        if (e == hipSuccess) e = hipMemsetAsync(d_err, 0, 4, P.cs);
+        if (e != hipSuccess) return hip_fail(e, "leyenda_merge: tables");
+        k_corank<<<dim3((uint32_t)(nch - 1)), dim3(kWG), 0, P.cs>>>(runs_dev, d_off, (uint32_t)k, d_tgt, d_split,
+                                                                   d_err);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "co-rank kernel");
+        uint32_t err = 0;
+        e = hipMemcpyAsync(split.data() + k, d_split, (nch - 1) * k * 8, hipMemcpyDeviceToHost, P.cs);
+        if (e == hipSuccess) e = hipMemcpyAsync(&err, d_err, 4, hipMemcpyDeviceToHost, P.cs);
+        if (e == hipSuccess) e = hipStreamSynchronize(P.cs);
+        if (e != hipSuccess) return hip_fail(e, "leyenda_merge: co-rank");
+        if (err) return fail(LEYENDA_EINTERNAL, "leyenda_merge: co-rank did not converge");
+        for (uint64_t c = 1; c < nch; c++) {
+            uint64_t s = 0;
+            for (uint64_t i = 0; i < k; i++) {
+                const uint64_t a = split[c * k + i], b0 = split[(c - 1) * k + i];
+                if (a < b0 || a > run_bounds[i + 1] - run_bounds[i])
+                    return fail(LEYENDA_EINTERNAL, "leyenda_merge: co-rank out of order");
+                s += a;
+            }
+            if (s != c * C) return fail(LEYENDA_EINTERNAL, "leyenda_merge: co-rank sums to the wrong rank");
+        }
+    }
+
+    // 2. per chunk: slices, pairwise merge rounds
+    struct Round {
+        uint32_t pair_first, npairs, ntiles, in_buf;
+    };
+    std::vector<MergePair> pairs;
+    std::vector<std::vector<Round>> plan(nch);
+    std::vector<std::vector<uint64_t>> slice_off(nch), slice_len(nch);
+    std::vector<uint32_t> final_buf(nch, 0);
+    for (uint64_t c = 0; c < nch; c++) {
+        std::vector<uint64_t> seq_off, seq_len;
+        uint64_t o = 0;
+        for (uint64_t i = 0; i < k; i++) {
+            const uint64_t len = split[(c + 1) * k + i] - split[c * k + i];
+            slice_off[c].push_back(o);
+            slice_len[c].push_back(len);
+            if (len) { seq_off.push_back(o); seq_len.push_back(len); }
+            o += len;
+        }
+        uint32_t buf = 0;
+        while (seq_off.size() > 1) {
+            Round rd{(uint32_t)pairs.size(), 0, 0, buf};
+            std::vector<uint64_t> no, nl;
+            for (size_t s = 0; s < seq_off.size(); s += 2) {
+                MergePair mp;
+                mp.a_off = (uint32_t)seq_off[s];
+                mp.a_len = (uint32_t)seq_len[s];
+                mp.b_len = s + 1 < seq_off.size() ? (uint32_t)seq_len[s + 1] : 0u;
+                mp.first_tile = rd.ntiles;
+                rd.ntiles += (mp.a_len + mp.b_len + kMergeTile - 1) / kMergeTile;
+                pairs.push_back(mp);
+                rd.npairs++;
+                no.push_back(seq_off[s]);
+                nl.push_back(seq_len[s] + (s + 1 < seq_off.size() ? seq_len[s + 1] : 0));
+            }
+            plan[c].push_back(rd);
+            seq_off.swap(no);
+            seq_len.swap(nl);
+            buf ^= 1;
+        }
+        final_buf[c] = buf;
+    }
+    if (pairs.size() > pair_cap) return fail(LEYENDA_EINTERNAL, "leyenda_merge: pair table overflow");
+    if (!pairs.empty()) {
+        e = hipMemcpyAsync(d_pairs, pairs.data(), pairs.size() * sizeof(MergePair), hipMemcpyHostToDevice, P.cs);
+        if (e == hipSuccess) e = hipStreamSynchronize(P.cs);
+        if (e != hipSuccess) return hip_fail(e, "leyenda_merge: pair table");
+    }
+
+    // 3. stream the chunks: upload slices | merge + gather | download
+    const uint8_t *runs_h = static_cast<const uint8_t *>(host_runs);
+    uint8_t *out_h = static_cast<uint8_t *>(host_out);
+    const int cus = device_cus();
+    for (uint64_t c = 0; c < nch; c++) {
+        const int b = (int)(c & 1);
+        const uint64_t out_first = c * C;
+        uint64_t clen = 0;
+        for (uint64_t i = 0; i < k; i++) clen += slice_len[c][i];
+        if (c >= 2) e = hipStreamWaitEvent(P.h2d, P.ev[1][b], 0);
+        for (uint64_t i = 0; i < k && e == hipSuccess; i++) {
+            const uint64_t len = slice_len[c][i];
+            if (!len) continue;
+            e = hipMemcpyAsync(stage[b] + slice_off[c][i] * kRec, runs_h + (run_bounds[i] + split[c * k + i]) * kRec,
+                               len * kRec, hipMemcpyHostToDevice, P.h2d);
+        }
+        if (e == hipSuccess) e = hipEventRecord(P.ev[0][b], P.h2d);
+        if (e == hipSuccess) e = hipStreamWaitEvent(P.cs, P.ev[0][b], 0);
+        if (e == hipSuccess && c >= 2) e = hipStreamWaitEvent(P.cs, P.ev[2][b], 0);
+        if (e != hipSuccess) return hip_fail(e, "leyenda_merge: enqueue");
+        k_merge_extract<<<dim3((uint32_t)((clen + kWG - 1) / kWG)), dim3(kWG), 0, P.cs>>>(stage[b], clen, TH[0], TL[0]);
+        for (const Round &rd : plan[c]) {
+            const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>(rd.ntiles, (uint32_t)cus * 8));
+            k_merge_pairs<<<dim3(g), dim3(kWG), 0, P.cs>>>(d_pairs + rd.pair_first, rd.npairs, rd.ntiles,
+                                                            TH[rd.in_buf], TL[rd.in_buf], TH[rd.in_buf ^ 1],
+                                                            TL[rd.in_buf ^ 1]);
+        }
+        k_gather_lo<<<dim3((uint32_t)((clen + kWG - 1) / kWG)), dim3(kWG), 0, P.cs>>>(stage[b], TL[final_buf[c]],
+                                                                                   outb[b], clen);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "merge kernels");
+        e = hipEventRecord(P.ev[1][b], P.cs);
+        if (e == hipSuccess) e = hipStreamWaitEvent(P.d2h, P.ev[1][b], 0);
+        if (e == hipSuccess) e = hipMemcpyAsync(out_h + out_first * kRec, outb[b], clen * kRec, hipMemcpyDeviceToHost,
+                                                P.d2h);
+        if (e == hipSuccess) e = hipEventRecord(P.ev[2][b], P.d2h);
+        if (e != hipSuccess) return hip_fail(e, "leyenda_merge: enqueue");
+    }
+    return P.finish();
+}

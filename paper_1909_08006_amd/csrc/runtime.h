@@ -18,5 +18,7 @@ int remember_layout(hipStream_t stream, const Layout &L);
 bool overlaps(const void *a, uint64_t abytes, const void *b, uint64_t bbytes);
 int check_records(const void *in, const void *out, uint64_t n, const char *who);
 int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t);
+// Same sort with a caller-provided workspace of plan_layout(n, 1, t).total bytes.
+int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t, void *ws);
 
 }  // namespace ley

@@ -299,6 +299,11 @@ int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t 
     int rc = get_workspace(stream, L.total, &ws);
     if (rc) return rc;
     remember_layout(stream, L);
+    return sort_device_ws(records_dev, n, out_dev, stream, t, ws);
+}
+
+int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t, void *ws) {
+    const Layout L = plan_layout(n, 1, t);
     const Work w = bind_layout(L, ws);
     const uint32_t tiles0 = (uint32_t)((n + t.tile - 1) / t.tile);
     ProfCall pc;

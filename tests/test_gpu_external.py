@@ -1,0 +1,100 @@
+"""Parity of the limited-memory path (sorted runs + k-way merge) with the CPU oracle."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def pinned(a: np.ndarray):
+    import torch
+    t = torch.empty(a.size, dtype=torch.uint8, pin_memory=True)
+    t.numpy()[:] = a.reshape(-1)
+    return t
+
+
+def budget_for_runs(gpu, n, k):
+    """Smallest budget giving at most k runs (found with the library's own planner)."""
+    lo, hi = 1 << 16, 1 << 40
+    while lo < hi:
+        m = (lo + hi) // 2
+        try:
+            _, kk = gpu.plan_runs(n, m)
+            ok = kk <= k
+        except gpu.LeyendaError:
+            ok = False
+        if ok:
+            hi = m
+        else:
+            lo = m + 1
+    return lo
+
+
+@pytest.mark.parametrize("runs", [1, 3, 10])
+def test_runs_then_merge_uniform(gpu, runs):
+    n = 150_001
+    rec = datagen.uniform(n, 60 + runs)
+    host = pinned(rec)
+    budget = budget_for_runs(gpu, n, runs)
+    out_runs, bounds = gpu.sort_runs(host, budget)
+    assert bounds[0] == 0 and bounds[-1] == n and len(bounds) - 1 == runs
+    got_runs = out_runs.numpy().reshape(n, 100)
+    for a, b in zip(bounds, bounds[1:]):
+        np.testing.assert_array_equal(got_runs[a:b], oracle.sort(rec[a:b]))
+    merged = gpu.merge(out_runs, bounds, budget_bytes=3_000_000)  # forces many chunks
+    np.testing.assert_array_equal(merged.numpy().reshape(n, 100), oracle.sort(rec))
+
+
+def test_ties_straddle_runs_in_place(gpu):
+    """Many exact-duplicate keys spread over every run; runs written over their input."""
+    n = 120_000
+    rec = datagen.skewed(n, 9, nvals=40, dup_frac=0.3)
+    host = pinned(rec)
+    budget = budget_for_runs(gpu, n, 7)
+    runs, bounds = gpu.sort_runs(host, budget, host_runs=host)  # in place
+    assert len(bounds) - 1 == 7
+    merged = gpu.merge(runs, bounds, budget_bytes=2_000_000)
+    np.testing.assert_array_equal(merged.numpy().reshape(n, 100), oracle.sort(rec))
+
+
+@pytest.mark.parametrize("k", [2, 5, 33])
+def test_merge_of_given_runs(gpu, k):
+    """Merge of runs cut at uneven bounds (including empty runs), sorted by the oracle."""
+    n = 90_000
+    rec = datagen.skewed(n, 11 + k, nvals=300)
+    rng = np.random.default_rng(k)
+    cuts = np.sort(rng.integers(0, n, k - 1))
+    bounds = [0] + [int(c) for c in cuts] + [n]
+    if k > 2:
+        bounds[2] = bounds[1]  # one empty run
+    runs = np.concatenate([oracle.sort(rec[a:b]) for a, b in zip(bounds, bounds[1:])])
+    merged = gpu.merge(pinned(runs), bounds, budget_bytes=1_500_000)
+    # stable merge of runs = stable sort of the original input (runs are input ranges)
+    np.testing.assert_array_equal(merged.numpy().reshape(n, 100), oracle.sort(rec))
+
+
+def test_tiny_and_single(gpu):
+    for n in (1, 2, 37):
+        rec = datagen.uniform(n, 3)
+        runs, bounds = gpu.sort_runs(pinned(rec), 64 << 20)
+        merged = gpu.merge(runs, bounds, budget_bytes=64 << 20)
+        np.testing.assert_array_equal(merged.numpy().reshape(n, 100), oracle.sort(rec))
+
+
+def test_external_errors(gpu):
+    import torch
+    lib = gpu.load()
+    rec = datagen.uniform(1000, 4)
+    pageable = torch.from_numpy(rec.reshape(-1).copy())
+    with pytest.raises(gpu.LeyendaError) as ei:
+        gpu.sort_runs(pageable, 64 << 20)
+    assert ei.value.status == -1
+    with pytest.raises(gpu.LeyendaError) as ei:
+        gpu.sort_runs(pinned(rec), 1000)  # far below one run's footprint
+    assert ei.value.status == -3
+    with pytest.raises(gpu.LeyendaError) as ei:
+        gpu.sort_runs(pinned(rec), budget_for_runs(gpu, 1000, 9), k_max=3)
+    assert ei.value.status == -3
+    assert lib is not None

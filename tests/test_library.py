@@ -71,3 +71,18 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(ley, "LIB_PATH", "/nonexistent/libleyenda.so")
     with pytest.raises(RuntimeError, match="not built"):
         ley.load()
+
+
+def test_plan_runs_budget_math():
+    """Run planning is host arithmetic: equal runs covering n, fewer runs for more memory."""
+    import paper_1909_08006_amd as ley
+    for n, budget in [(600_000_000, 30 * 10**9), (10**6, 50 << 20), (5, 1 << 30)]:
+        r, k = ley.plan_runs(n, budget)
+        assert r * k >= n and r * (k - 1) < n
+        assert ley.plan_runs(n, budget * 2)[1] <= k
+    r, k = ley.plan_runs(600_000_000, 30 * 10**9)
+    assert 5 <= k <= 20  # 60 GB of records through a 30 GB device budget
+    with pytest.raises(ley.LeyendaError) as ei:
+        ley.plan_runs(10**6, 1000)
+    assert ei.value.status == -3
+    assert ley.plan_runs(0, 1000) == (0, 0)
