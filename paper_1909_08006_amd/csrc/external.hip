@@ -426,16 +426,21 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
         return a256((k + 1) * 8) + a256(chunks * 8) + a256((chunks + 1) * k * 8) +
                a256(chunks * (rounds + 1) * ((k + 1) / 2 + 1) * sizeof(MergePair)) + 256;
     };
-    auto merge_bytes = [&](uint64_t m) -> uint64_t {
-        return 4 * a256(m * kRec) + 4 * a256(m * 8) + tables_for((n + m - 1) / m);
-    };
-    if (merge_bytes(std::min<uint64_t>(n, 1)) > device_budget_bytes)
-        return fail(LEYENDA_EBUDGET, "leyenda_merge: budget too small");
-    uint64_t lo = 1, hi = std::min<uint64_t>(n, LEYENDA_MAX_RECORDS);
-    while (lo < hi) {
-        const uint64_t m = lo + (hi - lo + 1) / 2;
-        if (merge_bytes(m) <= device_budget_bytes) lo = m; else hi = m - 1;
+    auto buf_bytes = [&](uint64_t m) -> uint64_t { return 4 * a256(m * kRec) + 4 * a256(m * 8); };
+    // largest chunk whose buffers fit next to the tables its chunk count needs
+    uint64_t lo = 0, tab = tables_for(1);
+    for (int it = 0; it < 64; it++) {
+        if (tab + buf_bytes(1) > device_budget_bytes) break;
+        uint64_t a = 1, c = std::min<uint64_t>(n, LEYENDA_MAX_RECORDS);
+        while (a < c) {
+            const uint64_t m = a + (c - a + 1) / 2;
+            if (buf_bytes(m) + tab <= device_budget_bytes) a = m; else c = m - 1;
+        }
+        const uint64_t t2 = tables_for((n + a - 1) / a);
+        if (t2 <= tab) { lo = a; break; }
+        tab = t2;
     }
+    if (lo == 0) return fail(LEYENDA_EBUDGET, "leyenda_merge: budget too small");
     const uint64_t nch = (n + lo - 1) / lo;
     const uint64_t C = (n + nch - 1) / nch;  // equal chunks
 
