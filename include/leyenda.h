@@ -129,6 +129,59 @@ typedef struct {
 int leyenda_sort_batch(const leyenda_segment *segs, uint64_t count, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Serving engine (continuous batching).  Sort requests arrive over time; a
+ * dispatcher thread admits them in arrival order while their output buffers
+ * fit the device budget, groups the admitted ones into batches (at most
+ * max_batch requests and max_batch_records records per batch) and runs each
+ * batch as one batched sort on one of `slots` streams, so batches overlap on
+ * the GPU and requests arriving meanwhile join the next free slot.  Output
+ * buffers are owned by the engine and stay resident until released.
+ * With batched == 0 the engine runs one plain leyenda_sort per request, in
+ * arrival order, on one stream (the comparison baseline).
+ *
+ * budget_bytes covers every device byte the engine allocates: one sort
+ * workspace per slot plus the arena holding admitted requests' outputs
+ * (100 bytes per record).  LEYENDA_EBUDGET if it cannot hold the workspaces
+ * and one full batch.
+ * ------------------------------------------------------------------------- */
+typedef struct leyenda_server leyenda_server;
+
+typedef struct {
+    uint64_t budget_bytes;
+    uint32_t slots;
+    uint32_t max_batch;
+    uint64_t max_batch_records;  /* also the largest request accepted */
+    int32_t batched;
+} leyenda_server_config;
+
+typedef struct {
+    uint64_t tag;
+    void *out_dev;     /* the sorted records, valid until leyenda_server_release(tag) */
+    uint64_t n;
+    double submit_s;   /* steady-clock seconds: submitted, launched, seen complete */
+    double start_s;
+    double done_s;
+    int32_t status;
+} leyenda_done;
+
+int leyenda_server_create(const leyenda_server_config *cfg, leyenda_server **out);
+/* Queues a request: n records at in_dev (device memory the caller keeps
+ * unchanged until the request completes); tag must be unused. */
+int leyenda_server_submit(leyenda_server *s, const void *in_dev, uint64_t n, uint64_t tag);
+/* Completed requests (up to cap), waiting up to timeout_s seconds for one. */
+int leyenda_server_poll(leyenda_server *s, leyenda_done *out, uint64_t cap, uint64_t *count, double timeout_s);
+/* Frees a completed request's output buffer. */
+int leyenda_server_release(leyenda_server *s, uint64_t tag);
+int leyenda_server_destroy(leyenda_server *s);
+
+/* Replays an arrival stream against a fresh engine: request i (n[i] records
+ * at in_dev[i]) is submitted arrival_s[i] seconds after the start (arrivals
+ * non-decreasing); latency_s[i] = completion - arrival, including queueing;
+ * makespan_s = last completion - start.  Outputs are released on completion. */
+int leyenda_serve_replay(const leyenda_server_config *cfg, uint64_t count, const void *const *in_dev,
+                         const uint64_t *n, const double *arrival_s, double *latency_s, double *makespan_s);
+
+/* ---------------------------------------------------------------------------
  * Tuning parameters.  They change speed only, never the output bytes.
  * digit_bits     radix digit width in bits (8: 256 buckets per pass, Algorithm 1).
  * tile_items     keys per thread in a device-wide partition tile (8 or 16; a

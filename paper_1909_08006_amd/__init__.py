@@ -49,6 +49,17 @@ class Segment(ctypes.Structure):
     _fields_ = [("inp", ctypes.c_void_p), ("out", ctypes.c_void_p), ("n", ctypes.c_uint64)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("max_batch_records", ctypes.c_uint64), ("batched", ctypes.c_int32)]
+
+
+class Done(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("out_dev", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("submit_s", ctypes.c_double), ("start_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("status", ctypes.c_int32)]
+
+
 def load():
     """Load the HIP library (built by ``build.py``); raise if it is not there."""
     global _lib
@@ -75,6 +86,14 @@ def load():
         "leyenda_release_workspaces": ([], i32),
         "leyenda_debug_extract": ([vp, u64, vp, vp, vp, vp], i32),
         "leyenda_debug_gather": ([vp, u64, vp, u64, vp, vp], i32),
+        "leyenda_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)], i32),
+        "leyenda_server_submit": ([vp, vp, u64, u64], i32),
+        "leyenda_server_poll": ([vp, ctypes.POINTER(Done), u64, P64, ctypes.c_double], i32),
+        "leyenda_server_release": ([vp, u64], i32),
+        "leyenda_server_destroy": ([vp], i32),
+        "leyenda_serve_replay": ([ctypes.POINTER(ServerConfig), u64, ctypes.POINTER(vp), P64,
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)], i32),
         "leyenda_profile_enable": ([i32], i32),
         "leyenda_profile_read": ([ctypes.POINTER(ctypes.c_double), P64], i32),
     }
@@ -179,6 +198,87 @@ def sort_batch(pairs: Iterable, stream=None) -> None:
     for i, (a, b, n) in enumerate(segs):
         arr[i].inp, arr[i].out, arr[i].n = a, b, n
     _check(load().leyenda_sort_batch(arr, len(segs), _stream_ptr(stream)), "leyenda_sort_batch")
+
+
+# ---- serving ------------------------------------------------------------------------
+
+def _config(budget_bytes: int, slots: int, max_batch: int, max_batch_records: int, batched: bool) -> ServerConfig:
+    return ServerConfig(budget_bytes, slots, max_batch, max_batch_records, 1 if batched else 0)
+
+
+class Server:
+    """Continuous-batching sort server on the current GPU (see leyenda_server_* in leyenda.h)."""
+
+    def __init__(self, budget_bytes: int, slots: int = 3, max_batch: int = 256,
+                 max_batch_records: int = 10_000_000, batched: bool = True):
+        self._h = ctypes.c_void_p(0)
+        cfg = _config(budget_bytes, slots, max_batch, max_batch_records, batched)
+        _check(load().leyenda_server_create(ctypes.byref(cfg), ctypes.byref(self._h)), "leyenda_server_create")
+
+    def submit(self, records, tag: int) -> None:
+        """Queue a device tensor of records; it must stay unchanged until the request completes."""
+        _check(load().leyenda_server_submit(self._h, records.data_ptr(), _nrec(records), tag),
+               "leyenda_server_submit")
+
+    def poll(self, timeout_s: float = 0.0, cap: int = 256) -> list:
+        buf = (Done * cap)()
+        k = ctypes.c_uint64(0)
+        _check(load().leyenda_server_poll(self._h, buf, cap, ctypes.byref(k), timeout_s), "leyenda_server_poll")
+        return [{"tag": int(d.tag), "out_dev": int(d.out_dev or 0), "n": int(d.n), "submit_s": d.submit_s,
+                 "start_s": d.start_s, "done_s": d.done_s, "status": int(d.status)} for d in buf[:k.value]]
+
+    def output(self, done: dict):
+        """Copy of a completed request's sorted records as a (n, 100) uint8 device tensor."""
+        import torch
+        out = torch.empty((done["n"], RECORD_BYTES), dtype=torch.uint8, device="cuda")
+        src = _DevView(done["out_dev"], done["n"] * RECORD_BYTES)
+        out.view(-1).copy_(torch.as_tensor(src, device="cuda"))
+        return out
+
+    def release(self, tag: int) -> None:
+        _check(load().leyenda_server_release(self._h, tag), "leyenda_server_release")
+
+    def close(self) -> None:
+        if self._h:
+            load().leyenda_server_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _DevView:
+    """__cuda_array_interface__ view of engine-owned device memory (uint8)."""
+
+    def __init__(self, ptr: int, nbytes: int):
+        self.__cuda_array_interface__ = {"shape": (nbytes,), "typestr": "|u1", "data": (ptr, False),
+                                         "version": 3, "strides": None}
+
+
+def serve_replay(inputs: Sequence, arrivals_s, budget_bytes: int, slots: int = 3, max_batch: int = 256,
+                 max_batch_records: int = 10_000_000, batched: bool = True):
+    """Replay an arrival stream natively; returns (latencies_s list, makespan_s).
+
+    ``inputs``: list of (device_ptr, n_records); ``arrivals_s``: non-decreasing seconds."""
+    cnt = len(inputs)
+    cfg = _config(budget_bytes, slots, max_batch, max_batch_records, batched)
+    ptrs = (ctypes.c_void_p * max(cnt, 1))(*[p for p, _ in inputs])
+    ns = (ctypes.c_uint64 * max(cnt, 1))(*[n for _, n in inputs])
+    arr = (ctypes.c_double * max(cnt, 1))(*[float(a) for a in arrivals_s])
+    lat = (ctypes.c_double * max(cnt, 1))()
+    mk = ctypes.c_double(0)
+    _check(load().leyenda_serve_replay(ctypes.byref(cfg), cnt, ptrs, ns, arr, lat, ctypes.byref(mk)),
+           "leyenda_serve_replay")
+    return [lat[i] for i in range(cnt)], mk.value
 
 
 # ---- parameters and diagnostics -----------------------------------------------------

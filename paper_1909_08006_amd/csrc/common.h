@@ -120,7 +120,8 @@ Work bind_layout(const Layout &L, void *base);
 
 // Launch wrappers (sort_kernels.hip).  All return hipError_t of the launches.
 // ev (optional): three events recorded after extraction, after the
-// partition levels and after the local sorts.
+// partition levels and after the local sorts.  nreq = tiles0 = 0 launches
+// fixed grids that read every size from the device (for graph capture).
 hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
                             hipStream_t s, int cus, hipEvent_t *ev = nullptr);
 hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,

@@ -15,10 +15,18 @@ Tune tune_of(const leyenda_params &p);
 int device_cus();
 int get_workspace(hipStream_t stream, size_t bytes, void **out);
 int remember_layout(hipStream_t stream, const Layout &L);
+void pool_forget(hipStream_t stream);
 bool overlaps(const void *a, uint64_t abytes, const void *b, uint64_t bbytes);
 int check_records(const void *in, const void *out, uint64_t n, const char *who);
 int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t);
 // Same sort with a caller-provided workspace of plan_layout(n, 1, t).total bytes.
 int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t, void *ws);
+
+// batch.hip
+int batch_sort(const leyenda_segment *segs, uint64_t count, hipStream_t s);
+int batch_reserve(hipStream_t s, uint64_t n, uint32_t r, size_t *bytes);
+uint64_t batch_bytes(uint64_t n, uint32_t r);
+void batch_forget(hipStream_t s);
+void batch_release_all();
 
 }  // namespace ley

@@ -201,10 +201,22 @@ static int find_workspace(hipStream_t stream, void **ptr, Layout *L) {
     return LEYENDA_OK;
 }
 
-int release_all() {
+void pool_forget(hipStream_t stream) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
     std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_pool.find({dev, stream});
+    if (it == g_pool.end()) return;
+    (void)hipStreamSynchronize(stream);
+    if (it->second.ptr) (void)hipFree(it->second.ptr);
+    g_pool.erase(it);
+}
+
+int release_all() {
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    batch_release_all();
+    std::lock_guard<std::mutex> lk(g_pool_mu);
     for (auto &kv : g_pool) {
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     }

@@ -811,8 +811,9 @@ static int occupancy(const void *fn, int cus) {
 template <int ITEMS>
 static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
                                 hipStream_t s, int cus, hipEvent_t *ev) {
-    k_init<<<dim3(max(1u, min(nreq, 1024u))), dim3(kWG), 0, s>>>(w);
-    const int g_ext = (int)max(1u, min(tiles0, (uint32_t)(cus * 16)));
+    // nreq / tiles0 == 0: sizes known only on the device (captured sequences)
+    k_init<<<dim3(nreq ? max(1u, min(nreq, 1024u)) : 1024u), dim3(kWG), 0, s>>>(w);
+    const int g_ext = tiles0 ? (int)max(1u, min(tiles0, (uint32_t)(cus * 16))) : cus * 16;
     k_extract<ITEMS><<<dim3(g_ext), dim3(kWG), 0, s>>>(w, t);
     if (ev) (void)hipEventRecord(ev[0], s);
     static int g_sc = 0, g_hist = 0, g_loc = 0;
