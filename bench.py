@@ -69,6 +69,56 @@ def cpu_baseline(host_u8, n_sample: int) -> dict:
                       f"qsort of (key, index) by memcmp then record gather, one thread, {dt:.1f} s"}
 
 
+def serving(ley, count: int, warm: int, budget: int) -> dict:
+    """Serving workload: Poisson arrivals of sort requests, sizes log-uniform in
+    [1e3, 1e7] records, device admission budget 32 GB.  The same request stream
+    is replayed natively against the continuous-batching engine and against one
+    plain leyenda_sort per request (one stream, arrival order); latency =
+    completion - arrival, including queueing; the first `warm` requests are
+    excluded from the statistics."""
+    import numpy as np
+    import torch
+    import datagen
+
+    pool_n = 10_000_000
+    host = torch.empty(pool_n * 100, dtype=torch.uint8, pin_memory=True)
+    datagen.fill_uniform(host.data_ptr(), pool_n, datagen.SEED_REQUEST_BASE)
+    d = host.to("cuda:0")
+    torch.cuda.synchronize()
+    sizes = datagen.request_sizes(count)
+    offs = (datagen.words(datagen.SEED_REQUEST_BASE + 1, count) % np.uint64(pool_n)).astype(np.int64)
+    offs = np.minimum(offs, pool_n - sizes)
+    inputs = [(d.data_ptr() + int(o) * 100, int(n)) for o, n in zip(offs, sizes)]
+    total_bytes = float(sizes[warm:].sum()) * 100
+    cfg = dict(budget_bytes=budget, slots=3, max_batch=256, max_batch_records=10_000_000)
+
+    def stats(lat, mk):
+        L = np.asarray(lat[warm:]) * 1e3
+        return {"p50_ms": round(float(np.percentile(L, 50)), 3), "p99_ms": round(float(np.percentile(L, 99)), 3),
+                "mean_ms": round(float(L.mean()), 3), "gbs": round(total_bytes / mk / 1e9, 2)}
+
+    log(f"serving: {count} requests, closed-loop capacity of both engines ...")
+    zero = [0.0] * count
+    lat, mk_plain = ley.serve_replay(inputs, zero, batched=False, **cfg)
+    lat_b, mk_b = ley.serve_replay(inputs, zero, batched=True, **cfg)
+    mu = count / mk_plain
+    res = {"requests": count, "warmup_requests": warm, "size_records": "log-uniform [1e3, 1e7]",
+           "budget_bytes": budget, "slots": cfg["slots"], "max_batch": cfg["max_batch"],
+           "capacity_rps": {"per_request": round(mu, 1), "batched": round(count / mk_b, 1)},
+           "closed_loop": {"per_request": stats(lat, mk_plain), "batched": stats(lat_b, mk_b)}, "loads": []}
+    for rho in (0.5, 0.8, 0.95):
+        arr = datagen.arrival_times(count, rho * mu, seed=datagen.SEED_ARRIVALS)
+        row = {"rho": rho, "rate_rps": round(rho * mu, 1)}
+        for name, batched in (("batched", True), ("per_request", False)):
+            log(f"serving: rho={rho} {name} ...")
+            lat, mk = ley.serve_replay(inputs, arr, batched=batched, **cfg)
+            row[name] = stats(lat, mk)
+        res["loads"].append(row)
+    del d, host
+    torch.cuda.empty_cache()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +127,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=100_000_000, help="records (default: the 10 GB workload)")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000, help="records the oracle sorts for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving (batched vs per-request) comparison")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 2 GB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -167,6 +219,10 @@ def main() -> int:
         "floor_frac_210B": round(210 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "output_keys_ordered": ordered,
     }
+    if not args.no_serve:
+        del out
+        torch.cuda.empty_cache()
+        res["serving"] = serving(ley, args.serve_requests, 50, 32 * 10**9)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(host, min(args.cpu_sample, n))
     print(json.dumps(res), flush=True)

@@ -55,6 +55,9 @@ def _load():
     lib.oracle_multiset_hash.argtypes = [vp, u64, vp]
     lib.oracle_ties_in_order.argtypes = [vp, vp, u64]
     lib.oracle_ties_in_order.restype = ctypes.c_int
+    lib.oracle_count_less.argtypes = [vp, u64, vp, u64, vp]
+    lib.oracle_equal_neighbours.argtypes = [vp, u64]
+    lib.oracle_equal_neighbours.restype = ctypes.c_uint64
     _lib = lib
     return lib
 
@@ -93,6 +96,21 @@ def output_rank(records, samples) -> np.ndarray:
     if s.size:
         _load().oracle_output_rank(_ptr(rec), rec.shape[0], _ptr(s), s.size, _ptr(ranks))
     return ranks
+
+
+def count_less(records, probes) -> np.ndarray:
+    """For each probe record, the number of records whose key is below the probe's key."""
+    rec, pr = _as_records(records), _as_records(probes)
+    out = np.zeros(pr.shape[0], dtype=np.uint64)
+    if pr.shape[0]:
+        _load().oracle_count_less(_ptr(rec), rec.shape[0], _ptr(pr), pr.shape[0], _ptr(out))
+    return out
+
+
+def equal_neighbours(records) -> int:
+    """Adjacent pairs with equal keys (zero: stability is vacuous for this output)."""
+    rec = _as_records(records)
+    return int(_load().oracle_equal_neighbours(_ptr(rec), rec.shape[0]))
 
 
 def first_unsorted(records) -> int:

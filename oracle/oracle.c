@@ -19,6 +19,9 @@
  * Functions:
  *   oracle_sort           stable sort by memcmp on the key, then gather records
  *   oracle_output_rank    output position of chosen input records, one by one
+ *   oracle_count_less     keys below given probe keys (sorted position of a
+ *                         probe whose key is unique)
+ *   oracle_equal_neighbours  adjacent equal keys in an output
  *   oracle_first_unsorted first adjacent pair out of key order
  *   oracle_multiset_hash  order-independent hash of a record multiset
  *   oracle_ties_in_order  equal-key runs of an output hold their records in
@@ -95,6 +98,39 @@ void oracle_output_rank(const uint8_t *rec, uint64_t n, const uint64_t *samples,
         for (uint64_t s = 0; s < m; s++) ranks[s] += local[s];
         free(local);
     }
+}
+
+/* ---- oracle_count_less ------------------------------------------------------ */
+
+/* counts[s] = #{ j : key_j < key of probe s } over n records, for m probe
+ * records (given as records of their own, so the array may be any permutation
+ * of the input).  When the probe's key occurs once, this is its position in
+ * the sorted output. */
+void oracle_count_less(const uint8_t *rec, uint64_t n, const uint8_t *probes, uint64_t m, uint64_t *counts) {
+    for (uint64_t s = 0; s < m; s++) counts[s] = 0;
+#pragma omp parallel
+    {
+        uint64_t *local = (uint64_t *)calloc(m ? m : 1, sizeof(uint64_t));
+#pragma omp for schedule(static)
+        for (int64_t jj = 0; jj < (int64_t)n; jj++) {
+            const uint8_t *kj = rec + (uint64_t)jj * REC;
+            for (uint64_t s = 0; s < m; s++)
+                if (memcmp(kj, probes + s * REC, KEY) < 0) local[s]++;
+        }
+#pragma omp critical
+        for (uint64_t s = 0; s < m; s++) counts[s] += local[s];
+        free(local);
+    }
+}
+
+/* Number of adjacent output pairs with equal keys. */
+uint64_t oracle_equal_neighbours(const uint8_t *out, uint64_t n) {
+    uint64_t c = 0;
+    if (n < 2) return 0;
+#pragma omp parallel for schedule(static) reduction(+ : c)
+    for (int64_t j = 0; j < (int64_t)n - 1; j++)
+        if (memcmp(out + (uint64_t)j * REC, out + (uint64_t)(j + 1) * REC, KEY) == 0) c++;
+    return c;
 }
 
 /* ---- oracle_first_unsorted -------------------------------------------------- */

@@ -1,0 +1,141 @@
+"""Parity at the full sizes of the five workload configurations, in the launch
+configuration bench.py times (default parameters).
+
+Outputs this large are checked through properties that fix a stable sort's
+output uniquely -- keys non-decreasing, the same record multiset (order-free
+hash), equal keys in input order -- plus output positions of sampled input
+records computed one by one by the oracle.
+"""
+import gc
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _free_pinned():
+    import torch
+    gc.collect()
+    fn = getattr(torch._C, "_host_emptyCache", None)
+    if fn:
+        fn()
+
+
+def _pinned(nbytes):
+    import torch
+    return torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+
+
+def _check_big(rec: np.ndarray, out: np.ndarray, n_samples: int, seed: int, with_ties: bool):
+    assert oracle.first_unsorted(out) == -1, "keys out of order"
+    assert oracle.multiset_hash(rec) == oracle.multiset_hash(out), "record multiset differs"
+    if with_ties:
+        assert oracle.ties_in_order(rec, out), "equal keys out of input order"
+    else:
+        assert oracle.equal_neighbours(out) == 0 or oracle.ties_in_order(rec, out)
+    samples = np.random.default_rng(seed).integers(0, rec.shape[0], n_samples).astype(np.uint64)
+    ranks = oracle.output_rank(rec, samples)
+    for s, r in zip(samples, ranks):
+        np.testing.assert_array_equal(out[int(r)], rec[int(s)])
+
+
+def _internal(gpu, n, fill, seed, with_ties):
+    import torch
+    host = _pinned(n * 100)
+    fill(host.data_ptr(), n, seed)
+    dev = host.to("cuda:0", non_blocking=True)
+    out = gpu.sort(dev)
+    torch.cuda.synchronize()
+    st = gpu.stats(torch.cuda.current_stream())
+    assert st["guard"] == 0
+    del dev
+    got = out.cpu().numpy().reshape(n, 100)
+    del out
+    torch.cuda.empty_cache()
+    rec = host.numpy().reshape(n, 100)
+    _check_big(rec, got, 32, seed, with_ties)
+    del host, rec, got
+    _free_pinned()
+    return st
+
+
+@pytest.mark.timeout(900)
+def test_internal_10gb_uniform(gpu):
+    """100,000,000 x 100-byte records (10 GB), uniform keys, seed 2."""
+    st = _internal(gpu, 100_000_000, datagen.fill_uniform, datagen.SEED_INTERNAL, with_ties=False)
+    assert st["moved"][0] == 100_000_000
+
+
+@pytest.mark.timeout(1200)
+def test_internal_20gb_skewed(gpu):
+    """200,000,000 records (20 GB): Zipf(1.2) 4-byte prefixes over 65,536 values, 5% duplicate keys."""
+    _internal(gpu, 200_000_000, datagen.fill_skewed, datagen.SEED_SKEWED, with_ties=True)
+
+
+@pytest.mark.timeout(1500)
+def test_external_60gb_30gb_budget(gpu):
+    """600,000,000 records (60 GB) in pinned host memory, device budget 30 GB: runs + merge."""
+    import torch
+    n = 600_000_000
+    budget = 30 * 10**9
+    a = _pinned(n * 100)
+    datagen.fill_uniform(a.data_ptr(), n, datagen.SEED_EXTERNAL)
+    rec = a.numpy().reshape(n, 100)
+    h_in = oracle.multiset_hash(rec)
+    probes_idx = np.random.default_rng(4).integers(0, n, 32)
+    probes = rec[probes_idx].copy()
+    _, k = gpu.plan_runs(n, budget)
+    runs, bounds = gpu.sort_runs(a, budget, host_runs=a)  # runs written over the input
+    assert len(bounds) - 1 == k and k > 1
+    b = _pinned(n * 100)
+    gpu.merge(runs, bounds, budget, host_out=b)
+    torch.cuda.synchronize()
+    out = b.numpy().reshape(n, 100)
+    assert oracle.first_unsorted(out) == -1
+    assert oracle.multiset_hash(out) == h_in
+    # 10-byte uniform keys: equal keys are not expected among 6e8 (about 1.5e-7
+    # pairs), so stability is vacuous and a probe's position is its count of smaller keys
+    assert oracle.equal_neighbours(out) == 0
+    pos = oracle.count_less(out, probes)
+    for p, r in zip(pos, probes):
+        np.testing.assert_array_equal(out[int(p)], r)
+    del a, b, runs, rec, out
+    _free_pinned()
+
+
+@pytest.mark.timeout(900)
+def test_serving_stream_config(gpu):
+    """Requests log-uniform in [1e3, 1e7] records from the serving workload, 32 GB budget,
+    batched server: each output equals its oracle sort, and equals the request sorted alone."""
+    import torch
+    pool_n = 10_000_000
+    pool = datagen.uniform(pool_n, datagen.SEED_REQUEST_BASE)
+    d = torch.from_numpy(pool).cuda().view(-1)
+    count = 40
+    sizes = datagen.request_sizes(count)
+    offs = (datagen.words(datagen.SEED_REQUEST_BASE + 1, count) % np.uint64(pool_n)).astype(np.int64)
+    offs = np.minimum(offs, pool_n - sizes)
+    srv = gpu.Server(budget_bytes=32 * 10**9, slots=3, max_batch=256, max_batch_records=10_000_000)
+    got = {}
+    try:
+        for t in range(count):
+            srv.submit(d[int(offs[t]) * 100:(int(offs[t]) + int(sizes[t])) * 100], t)
+        while len(got) < count:
+            for dn in srv.poll(timeout_s=2.0):
+                assert dn["status"] == 0
+                got[dn["tag"]] = srv.output(dn).cpu().numpy()
+                srv.release(dn["tag"])
+    finally:
+        srv.close()
+    for t in range(count):
+        o, n = int(offs[t]), int(sizes[t])
+        np.testing.assert_array_equal(got[t], oracle.sort(pool[o:o + n]))
+    for t in np.argsort(sizes)[-3:]:
+        o, n = int(offs[t]), int(sizes[t])
+        alone = gpu.sort(d[o * 100:(o + n) * 100])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(alone.cpu().numpy().reshape(-1, 100), got[int(t)])

@@ -15,7 +15,7 @@ POOL = 300_000
 def pool(gpu):
     import torch
     rec = datagen.uniform(POOL, 4242)
-    return rec, torch.from_numpy(rec).cuda()
+    return rec, torch.from_numpy(rec).cuda().view(-1)
 
 
 def request_plan(count, seed, hi=60_000):

@@ -126,6 +126,26 @@ def test_output_rank_matches_full_sort():
     np.testing.assert_array_equal(oracle.output_rank(rec, samples), inv[samples].astype(np.uint64))
 
 
+def test_count_less_is_position_of_unique_keys():
+    rec = datagen.uniform(3000, 13)
+    out = oracle.sort(rec)
+    probes = rec[[0, 17, 2999, 1500]]
+    pos = oracle.count_less(rec[::-1].copy(), probes)  # any permutation of the input
+    for p, r in zip(pos, probes):
+        np.testing.assert_array_equal(out[int(p)], r)
+    # brute force on a tiny input with ties: strict "less" count
+    keys = [b"b", b"a", b"b", b"c"]
+    tiny = records_from_keys(keys)
+    assert list(oracle.count_less(tiny, tiny)) == [1, 0, 1, 3]
+
+
+def test_equal_neighbours():
+    rec = datagen.uniform(1000, 14)
+    assert oracle.equal_neighbours(oracle.sort(rec)) == 0
+    rec[[3, 9, 700], :10] = rec[3, :10]
+    assert oracle.equal_neighbours(oracle.sort(rec)) == 2
+
+
 # ---- checkers catch planted mistakes ------------------------------------------------
 
 def test_checkers_accept_oracle_output():
