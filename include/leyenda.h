@@ -77,9 +77,12 @@ uint64_t leyenda_workspace_bytes(uint64_t n);
  * Limited-memory (external) sort -- Section 3.2, "Overlapping Computation with
  * I/O": a sort stage that sorts chunks into sorted intermediate runs, then a
  * merge stage that merges the runs with a K-way merge, partition by
- * partition.  Host buffers must be pinned (hipHostMalloc, or torch
- * pin_memory()).  Both calls are synchronous: they return when the host
- * output is complete.
+ * partition.  host_records and host_runs must be pinned (hipHostMalloc,
+ * leyenda_host_alloc, or torch pin_memory()): the copy engines read them and
+ * the merge's co-rank kernel reads run keys from them directly.  host_out may
+ * be pinned (written by the copy engine) or pageable (written through two
+ * pinned bounce buffers by host threads).  Both calls are synchronous: they
+ * return when the host output is complete.
  *
  * leyenda_sort_runs:
  *   host_records: n records in pinned host memory (read only unless aliased).
@@ -97,14 +100,19 @@ uint64_t leyenda_workspace_bytes(uint64_t n);
  * leyenda_merge:
  *   host_runs, run_bounds, k: k sorted runs (as produced above; ties between
  *              runs are ordered by run, which is input order).
- *   host_out: n = run_bounds[k] records of pinned host memory; receives the
- *              merged output.  Must not overlap host_runs.
+ *   host_out: n = run_bounds[k] records of host memory (pinned or pageable);
+ *              receives the merged output.  Must not overlap host_runs.
  * ------------------------------------------------------------------------- */
 int leyenda_sort_runs(const void *host_records, uint64_t n, uint64_t device_budget_bytes,
                       void *host_runs, uint64_t *run_bounds, uint64_t k_max, uint64_t *k_out,
                       void *stream);
 int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, uint64_t k, void *host_out,
                   uint64_t device_budget_bytes, void *stream);
+
+/* Pinned host memory for the external path (hipHostMalloc; exactly `bytes`,
+ * no rounding).  leyenda_host_free(NULL) is a no-op. */
+int leyenda_host_alloc(uint64_t bytes, void **out);
+int leyenda_host_free(void *p);
 
 /* Run plan of leyenda_sort_runs for n records under a budget: records per run
  * and number of runs (host-only arithmetic, no GPU work).  LEYENDA_EBUDGET if

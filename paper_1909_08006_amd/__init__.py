@@ -94,6 +94,8 @@ def load():
         "leyenda_serve_replay": ([ctypes.POINTER(ServerConfig), u64, ctypes.POINTER(vp), P64,
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)], i32),
+        "leyenda_host_alloc": ([u64, ctypes.POINTER(vp)], i32),
+        "leyenda_host_free": ([vp], i32),
         "leyenda_profile_enable": ([i32], i32),
         "leyenda_profile_read": ([ctypes.POINTER(ctypes.c_double), P64], i32),
     }
@@ -153,6 +155,29 @@ def plan_runs(n: int, budget_bytes: int) -> tuple[int, int]:
     return int(r.value), int(k.value)
 
 
+_PINNED: dict = {}
+
+
+def pinned_empty(nbytes: int):
+    """CPU uint8 tensor of exactly ``nbytes`` in pinned (hipHostMalloc) memory.
+
+    Free it with :func:`pinned_free`; the tensor must not be used afterwards."""
+    import numpy as np
+    import torch
+    ptr = ctypes.c_void_p(0)
+    _check(load().leyenda_host_alloc(nbytes, ctypes.byref(ptr)), "leyenda_host_alloc")
+    arr = np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctypes.c_uint8)), shape=(nbytes,))
+    t = torch.from_numpy(arr)
+    _PINNED[t.data_ptr()] = ptr.value
+    return t
+
+
+def pinned_free(t) -> None:
+    p = _PINNED.pop(t.data_ptr(), None)
+    if p:
+        _check(load().leyenda_host_free(p), "leyenda_host_free")
+
+
 def sort_runs(host_records, budget_bytes: int, host_runs=None, k_max: int = 4096, stream=None):
     """Sorted runs of pinned host records within a device budget.
 
@@ -170,11 +195,12 @@ def sort_runs(host_records, budget_bytes: int, host_runs=None, k_max: int = 4096
 
 
 def merge(host_runs, run_bounds: Sequence[int], budget_bytes: int, host_out=None, stream=None):
-    """K-way merge of sorted runs (pinned host memory) into ``host_out``."""
+    """K-way merge of sorted runs (pinned host memory) into ``host_out``
+    (pinned or pageable; a new pageable tensor by default)."""
     import torch
     n = _nrec(host_runs)
     if host_out is None:
-        host_out = torch.empty_like(host_runs, pin_memory=True)
+        host_out = torch.empty_like(host_runs, pin_memory=False)
     k = len(run_bounds) - 1
     b = (ctypes.c_uint64 * len(run_bounds))(*run_bounds)
     if run_bounds[-1] != n:

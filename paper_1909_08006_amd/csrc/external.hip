@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
+#include <thread>
 #include <vector>
 
 #include "runtime.h"
@@ -307,6 +309,65 @@ struct Pipe {
 
 size_t a256(size_t v) { return (v + 255) / 256 * 256; }
 
+// Host copy split over threads (pageable destination of the merge output).
+void par_copy(uint8_t *dst, const uint8_t *src, size_t bytes) {
+    const unsigned nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+    if (bytes < (8u << 20) || nt == 1) { std::memcpy(dst, src, bytes); return; }
+    std::vector<std::thread> th;
+    const size_t per = (bytes + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; t++) {
+        const size_t a = t * per, b = std::min(bytes, a + per);
+        if (a < b) th.emplace_back([=] { std::memcpy(dst + a, src + a, b - a); });
+    }
+    for (auto &x : th) x.join();
+}
+
+// Device -> pageable host through two pinned bounce buffers: the copy engine
+// fills one while host threads empty the other.
+struct Bounce {
+    static constexpr size_t kPiece = 256u << 20;
+    uint8_t *buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int init() {
+        for (int i = 0; i < 2; i++) {
+            hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&buf[i]), kPiece, hipHostMallocDefault);
+            if (e != hipSuccess) { (void)hipGetLastError(); buf[i] = nullptr; return fail(LEYENDA_ENOMEM, "bounce buffer"); }
+            if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+        }
+        return LEYENDA_OK;
+    }
+    int drain(const uint8_t *src_dev, uint8_t *dst, uint64_t bytes, hipEvent_t ready, hipStream_t s) {
+        hipError_t e = hipStreamWaitEvent(s, ready, 0);
+        if (e != hipSuccess) return hip_fail(e, "bounce wait");
+        uint8_t *pend_dst[2] = {nullptr, nullptr};
+        size_t pend_len[2] = {0, 0};
+        uint64_t off = 0;
+        for (int p = 0; off < bytes || pend_len[0] || pend_len[1]; p ^= 1) {
+            if (pend_len[p]) {
+                if ((e = hipEventSynchronize(ev[p])) != hipSuccess) return hip_fail(e, "bounce copy");
+                par_copy(pend_dst[p], buf[p], pend_len[p]);
+                pend_len[p] = 0;
+            }
+            if (off < bytes) {
+                const size_t len = (size_t)std::min<uint64_t>(kPiece, bytes - off);
+                e = hipMemcpyAsync(buf[p], src_dev + off, len, hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipEventRecord(ev[p], s);
+                if (e != hipSuccess) return hip_fail(e, "bounce copy");
+                pend_dst[p] = dst + off;
+                pend_len[p] = len;
+                off += len;
+            }
+        }
+        return LEYENDA_OK;
+    }
+    ~Bounce() {
+        for (int i = 0; i < 2; i++) {
+            if (ev[i]) { (void)hipEventSynchronize(ev[i]); (void)hipEventDestroy(ev[i]); }
+            if (buf[i]) (void)hipHostFree(buf[i]);
+        }
+    }
+};
+
 // Device bytes one run of r records needs: two input and two output buffers
 // (so upload, sort and download overlap) plus the sort's workspace.
 uint64_t run_bytes(uint64_t r, const Tune &t) { return 4 * a256(r * kRec) + plan_layout(r, 1, t).total + 4096; }
@@ -335,6 +396,25 @@ int plan_runs_t(uint64_t n, uint64_t budget, const Tune &t, uint64_t *R, uint64_
 }  // namespace ley
 
 using namespace ley;
+
+extern "C" int leyenda_host_alloc(uint64_t bytes, void **out) {
+    if (!out) return fail(LEYENDA_EINVAL, "leyenda_host_alloc: NULL");
+    *out = nullptr;
+    if (bytes == 0) return LEYENDA_OK;
+    hipError_t e = hipHostMalloc(out, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *out = nullptr;
+        return fail(LEYENDA_ENOMEM, "hipHostMalloc(%llu): %s", (unsigned long long)bytes, hipGetErrorString(e));
+    }
+    return LEYENDA_OK;
+}
+
+extern "C" int leyenda_host_free(void *p) {
+    if (!p) return LEYENDA_OK;
+    hipError_t e = hipHostFree(p);
+    return e == hipSuccess ? LEYENDA_OK : hip_fail(e, "hipHostFree");
+}
 
 extern "C" int leyenda_plan_runs(uint64_t n, uint64_t device_budget_bytes, uint64_t *run_records, uint64_t *num_runs) {
     if (!run_records || !num_runs) return fail(LEYENDA_EINVAL, "leyenda_plan_runs: NULL");
@@ -413,8 +493,10 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
     if (overlaps(host_runs, n * kRec, host_out, n * kRec))
         return fail(LEYENDA_EINVAL, "leyenda_merge: host_out overlaps host_runs");
     const uint8_t *runs_dev = static_cast<const uint8_t *>(pinned_device_ptr(host_runs));
-    if (!runs_dev || !pinned_device_ptr(host_out))
-        return fail(LEYENDA_EINVAL, "leyenda_merge: host buffers must be pinned (hipHostMalloc / pin_memory)");
+    if (!runs_dev) return fail(LEYENDA_EINVAL, "leyenda_merge: host_runs must be pinned (hipHostMalloc / pin_memory)");
+    // pinned output: chunks go straight device -> host_out; pageable output:
+    // through two pinned bounce buffers drained by host copies
+    const bool direct_out = pinned_device_ptr(host_out) != nullptr;
     for (uint64_t i = 0; i < k; i++)
         if (run_bounds[i + 1] - run_bounds[i] > LEYENDA_MAX_RECORDS)
             return fail(LEYENDA_ETOOBIG, "leyenda_merge: run %llu too long", (unsigned long long)i);
@@ -548,6 +630,9 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
     const uint8_t *runs_h = static_cast<const uint8_t *>(host_runs);
     uint8_t *out_h = static_cast<uint8_t *>(host_out);
     const int cus = device_cus();
+    Bounce bounce;
+    if (!direct_out && (rc = bounce.init())) return rc;
+    uint64_t prev_first = 0, prev_len = 0;
     for (uint64_t c = 0; c < nch; c++) {
         const int b = (int)(c & 1);
         const uint64_t out_first = c * C;
@@ -562,7 +647,7 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
         }
         if (e == hipSuccess) e = hipEventRecord(P.ev[0][b], P.h2d);
         if (e == hipSuccess) e = hipStreamWaitEvent(P.cs, P.ev[0][b], 0);
-        if (e == hipSuccess && c >= 2) e = hipStreamWaitEvent(P.cs, P.ev[2][b], 0);
+        if (e == hipSuccess && c >= 2 && direct_out) e = hipStreamWaitEvent(P.cs, P.ev[2][b], 0);
         if (e != hipSuccess) return hip_fail(e, "leyenda_merge: enqueue");
         k_merge_extract<<<dim3((uint32_t)((clen + kWG - 1) / kWG)), dim3(kWG), 0, P.cs>>>(stage[b], clen, TH[0], TL[0]);
         for (const Round &rd : plan[c]) {
@@ -575,11 +660,24 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
                                                                                    outb[b], clen);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "merge kernels");
         e = hipEventRecord(P.ev[1][b], P.cs);
-        if (e == hipSuccess) e = hipStreamWaitEvent(P.d2h, P.ev[1][b], 0);
-        if (e == hipSuccess) e = hipMemcpyAsync(out_h + out_first * kRec, outb[b], clen * kRec, hipMemcpyDeviceToHost,
-                                                P.d2h);
-        if (e == hipSuccess) e = hipEventRecord(P.ev[2][b], P.d2h);
         if (e != hipSuccess) return hip_fail(e, "leyenda_merge: enqueue");
+        if (direct_out) {
+            e = hipStreamWaitEvent(P.d2h, P.ev[1][b], 0);
+            if (e == hipSuccess) e = hipMemcpyAsync(out_h + out_first * kRec, outb[b], clen * kRec,
+                                                    hipMemcpyDeviceToHost, P.d2h);
+            if (e == hipSuccess) e = hipEventRecord(P.ev[2][b], P.d2h);
+            if (e != hipSuccess) return hip_fail(e, "leyenda_merge: enqueue");
+        } else {
+            // chunk c - 1 drains while chunk c uploads and merges
+            if (c >= 1 && (rc = bounce.drain(outb[b ^ 1], out_h + prev_first * kRec, prev_len * kRec,
+                                             P.ev[1][b ^ 1], P.d2h)))
+                return rc;
+            prev_first = out_first;
+            prev_len = clen;
+        }
     }
+    if (!direct_out && (rc = bounce.drain(outb[(nch - 1) & 1], out_h + prev_first * kRec, prev_len * kRec,
+                                          P.ev[1][(nch - 1) & 1], P.d2h)))
+        return rc;
     return P.finish();
 }

@@ -75,6 +75,17 @@ def test_merge_of_given_runs(gpu, k):
     np.testing.assert_array_equal(merged.numpy().reshape(n, 100), oracle.sort(rec))
 
 
+def test_merge_into_pageable_output(gpu):
+    import torch
+    n = 80_000
+    rec = datagen.uniform(n, 71)
+    budget = budget_for_runs(gpu, n, 4)
+    runs, bounds = gpu.sort_runs(pinned(rec), budget)
+    out = np.empty((n, 100), dtype=np.uint8)
+    gpu.merge(runs, bounds, budget_bytes=2_000_000, host_out=torch.from_numpy(out).view(-1))
+    np.testing.assert_array_equal(out, oracle.sort(rec))
+
+
 def test_tiny_and_single(gpu):
     for n in (1, 2, 37):
         rec = datagen.uniform(n, 3)
