@@ -25,25 +25,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GB/s of 100-byte records sorted (10 GB, in-HBM); p50/p99 latency batched"
 HBM_PEAK_GBS = 8000.0
-PMC_FILE = os.path.join(ROOT, "profiles", "gather_internal_1e8_pmc.txt")
+PMC_FILE = os.path.join(ROOT, "profiles", "sort_internal_1e8_pmc.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1909_08006_amd", "csrc", "sort_kernels.hip")
 
 # Algorithmic bytes per record of each phase (element granularity, no line overfetch):
 #   extract   reads the 10 key bytes, writes a 16-byte (key, index) tuple
 #   partition per level: reads + writes 16-byte tuples (32 B) for every moved key,
 #             and levels >= 1 first read 8 key bytes per key for their histograms
-#   local     reads 16-byte tuples, writes a 4-byte index
-#   gather    reads the 4-byte index and the 100-byte record, writes 100 bytes
-ALG_BYTES = {"extract": 26, "local": 20, "gather": 204}
+#   local     (local sort fused with the record gather) reads the 16-byte tuple
+#             and the 100-byte record, writes the 100-byte record
+ALG_BYTES = {"extract": 26, "local": 216}
+KERNEL_OF = {"extract": "k_extract", "partition": "k_hist+k_plan+k_scatter", "local": "k_local"}
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def pmc_traffic(n: int):
-    """HBM bytes per gather launch from the committed rocprofv3 counter summary,
-    or None if absent or taken on a different kernel source."""
+def pmc_traffic(n: int, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None if absent, for another kernel, or taken on a different
+    kernel source."""
     if not os.path.exists(PMC_FILE):
         return None
     fields = {}
@@ -52,7 +54,8 @@ def pmc_traffic(n: int):
             k, _, v = line.strip().partition("=")
             fields[k.strip()] = v.strip()
     src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
-    if fields.get("kernel_source_sha256_16") != src_hash or int(fields.get("n_records", -1)) != n:
+    if (fields.get("kernel_source_sha256_16") != src_hash or int(fields.get("n_records", -1)) != n
+            or fields.get("kernel") != kernel):
         return None
     return int(float(fields["hbm_bytes_per_launch"]))
 
@@ -179,7 +182,7 @@ def main() -> int:
     ley.profile_enable(False)
     ms = (t1 - t0) * 1e3 / args.steps
     gbs = n * 100 / (ms / 1e3) / 1e9
-    avg = {k: v / max(calls, 1) for k, v in phases.items()}
+    avg = {k: v / max(calls, 1) for k, v in phases.items() if k != "gather"}  # gather is fused into local
 
     # output sanity: keys non-decreasing (device-side check of big-endian key words)
     keys = out.view(n, 100)[:, :10].to(torch.int64)
@@ -194,11 +197,10 @@ def main() -> int:
     passes = moved / n
     b_alg = 250 + 32 * passes
     part_bytes = 32 * moved + 8 * sum(st["moved"][1:])
-    alg = {"extract": ALG_BYTES["extract"] * n, "partition": part_bytes, "local": ALG_BYTES["local"] * n,
-           "gather": ALG_BYTES["gather"] * n}
+    alg = {"extract": ALG_BYTES["extract"] * n, "partition": part_bytes, "local": ALG_BYTES["local"] * n}
     dom = max(avg, key=lambda k: avg[k])
     achieved = alg[dom] / (avg[dom] / 1e3) / 1e9
-    traffic = pmc_traffic(n) if dom == "gather" else None
+    traffic = pmc_traffic(n, KERNEL_OF[dom])
 
     res = {
         "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -207,8 +209,7 @@ def main() -> int:
         "config": {"workload": "internal sort, 100,000,000 x 100-byte records (10 GB) in HBM, uniform 10-byte keys",
                    "n_records": n, "record_bytes": 100, "key_bytes": 10, "seed": datagen.SEED_INTERNAL,
                    "params": ley.get_params()},
-        "roofline": {"bound": "hbm", "kernel": {"gather": "k_gather_plain", "extract": "k_extract",
-                                                "partition": "k_hist+k_scatter", "local": "k_local"}[dom],
+        "roofline": {"bound": "hbm", "kernel": KERNEL_OF[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "phases_ms": {k: round(v, 4) for k, v in avg.items()},

@@ -15,8 +15,9 @@
 //   k_local     per small bucket, in one workgroup's LDS: radix partition on
 //               the first varying digit (SingleThreadRadixSort), recursion on
 //               sub-buckets above the tiny threshold, and a comparison sort of
-//               tiny sub-buckets (ComparisonSort)
-//   k_gather    record scatter by the sorted tuples: out[j] = in[idx[j]]
+//               tiny sub-buckets (ComparisonSort); then the same workgroup
+//               scatters the bucket's records by the sorted tuples into the
+//               output (record scatter of Section 3.2): out[j] = in[idx[j]]
 //
 // Tuples are kept as two arrays (struct of arrays): H = key bytes 0..7 as a
 // big-endian u64, L = key bytes 8..9 (big-endian) << 32 | record index.
@@ -108,17 +109,17 @@ __device__ __forceinline__ bool seg_ok(const Work &w, const Seg &sg, uint32_t ti
 // inside the local sort).  Called by all threads of a workgroup.
 
 __device__ void emit_task(const Work &w, uint64_t start, uint32_t count, uint8_t buf, uint8_t flags,
-                          uint16_t pos) {
+                          uint16_t req) {
     const uint32_t j = atomicAdd(&w.ctl->ntask, 1u);
     if (j >= w.max_tasks) { atomicOr(&w.ctl->guard, 1u); return; }
     Task t;
-    t.start = start; t.count = count; t.buf = buf; t.flags = flags; t.pos = pos;
+    t.start = start; t.count = count; t.buf = buf; t.flags = flags; t.req = req;
     w.tasks[j] = t;
 }
 
 // A range whose keys are all equal is already in final (index) order; it is
 // cut into local-capacity chunks so each task stays bounded.
-__device__ void emit_sorted(const Work &w, uint64_t start, uint64_t count, uint8_t buf) {
+__device__ void emit_sorted(const Work &w, uint64_t start, uint64_t count, uint8_t buf, uint16_t req) {
     const uint64_t nch = (count + kLocalCap - 1) / kLocalCap;
     const uint32_t j0 = atomicAdd(&w.ctl->ntask, (uint32_t)nch);
     if ((uint64_t)j0 + nch > w.max_tasks) { atomicOr(&w.ctl->guard, 2u); return; }
@@ -126,7 +127,7 @@ __device__ void emit_sorted(const Work &w, uint64_t start, uint64_t count, uint8
         Task t;
         t.start = start + k * kLocalCap;
         t.count = (uint32_t)min<uint64_t>(kLocalCap, count - k * kLocalCap);
-        t.buf = buf; t.flags = kTaskSorted; t.pos = 0;
+        t.buf = buf; t.flags = kTaskSorted; t.req = req;
         w.tasks[j0 + k] = t;
     }
 }
@@ -183,7 +184,7 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
     if (sg.count <= tu.big) {  // small bucket: one local-sort task as it is
         if (d == 0) {
             sp->spos = kNoScatter;
-            emit_task(w, sg.start, sg.count, sg.buf, 0, sg.pos);
+            emit_task(w, sg.start, sg.count, sg.buf, 0, sg.req);
         }
         return;
     }
@@ -201,7 +202,7 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
         if (d == 0) {
             sp->spos = kNoScatter;
             const uint32_t f = first_varying(p_mask[0], p_mask[1], p_mask[2], p_mask[3]);
-            if (f >= kKeyBits) emit_sorted(w, sg.start, sg.count, sg.buf);
+            if (f >= kKeyBits) emit_sorted(w, sg.start, sg.count, sg.buf, sg.req);
             else new_segment(w, tu, lev + 1, sg.start, sg.count, max(f, (uint32_t)sg.pos + kRB), sg.buf, sg.req);
         }
         return;
@@ -219,7 +220,7 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
     const uint32_t cpos = p + kRB;
     if (cnt > tu.big) {
         if (cpos < kKeyBits) new_segment(w, tu, lev + 1, sg.start + base, cnt, cpos, cbuf, sg.req);
-        else emit_sorted(w, sg.start + base, cnt, cbuf);  // all 80 key bits fixed: equal keys
+        else emit_sorted(w, sg.start + base, cnt, cbuf, sg.req);  // all 80 key bits fixed: equal keys
     }
     __syncthreads();
     if (d == 0) {  // pack consecutive small buckets into tasks of at most kLocalCap keys
@@ -244,7 +245,7 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
     __syncthreads();
     for (uint32_t t = d; t < p_ntask; t += kWG) {
         Task tk;
-        tk.start = sg.start + p_tstart[t]; tk.count = p_tcnt[t]; tk.buf = cbuf; tk.flags = 0; tk.pos = (uint16_t)p;
+        tk.start = sg.start + p_tstart[t]; tk.count = p_tcnt[t]; tk.buf = cbuf; tk.flags = 0; tk.req = sg.req;
         w.tasks[p_slot + t] = tk;
     }
     __syncthreads();
@@ -388,22 +389,32 @@ __global__ __launch_bounds__(kWG) void k_hist(Work w, Tune tu, int lev) {
         const uint32_t nvalid = (uint32_t)min<uint64_t>(tu.tile, sg.count - local0);
         const uint64_t *H = w.H[sg.buf] + sg.start + local0;
         const uint64_t *L = w.L[sg.buf] + sg.start + local0;
+        // key bytes 8..9 are read only when the digit reaches them; otherwise
+        // their mask reads "varying", so a bucket constant through byte 7
+        // moves on to bit 64 and the next level reads them
+        const bool needL = sg.pos + kRB > 64;
         __syncthreads();
         uint64_t h[ITEMS], l[ITEMS];
 #pragma unroll
         for (int u = 0; u < ITEMS; u++) {
             const uint32_t q = u * kWG + threadIdx.x;
             h[u] = 0; l[u] = 0;
-            if (q < nvalid) { h[u] = H[q]; l[u] = L[q]; }
+            if (q < nvalid) {
+                h[u] = H[q];
+                if (needL) l[u] = L[q];
+            }
         }
-        uint64_t oh = 0, onh = 0, ol = 0, onl = 0;
+        uint64_t oh = 0, onh = 0, ol = needL ? 0 : 0xFFFFu, onl = needL ? 0 : 0xFFFFu;
 #pragma unroll
         for (int u = 0; u < ITEMS; u++) {
             const uint32_t q = u * kWG + threadIdx.x;
             if (q < nvalid) {
-                const uint64_t k16 = (l[u] >> 32) & 0xFFFFu;
                 atomicAdd(&sh[digit_at(h[u], l[u], sg.pos)], 1u);
-                oh |= h[u]; onh |= ~h[u]; ol |= k16; onl |= (~k16) & 0xFFFFu;
+                oh |= h[u]; onh |= ~h[u];
+                if (needL) {
+                    const uint64_t k16 = (l[u] >> 32) & 0xFFFFu;
+                    ol |= k16; onl |= (~k16) & 0xFFFFu;
+                }
             }
         }
         block_masks(oh, onh, ol, onl, smask);
@@ -567,6 +578,32 @@ __device__ __forceinline__ uint64_t wave_and64(uint64_t v) {
 
 constexpr int kStack = kLocalCap / 2;
 
+// Records of one sorted task into its request's output: out[j] = in[sidx[j]].
+// One dword per lane per step over the task's contiguous output range, so
+// stores are contiguous and each source record is read as whole 100-byte spans.
+__device__ __forceinline__ void gather_task(const Req &rq, uint64_t task_start, uint32_t m, const uint32_t *sidx) {
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(rq.in);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(rq.out + (task_start - rq.start) * kRec);
+    for (uint32_t j0 = 0; j0 < m; j0 += kWG) {
+        const uint32_t nr = min((uint32_t)kWG, m - j0);
+        uint32_t v[25];
+#pragma unroll
+        for (int u = 0; u < 25; u++) {
+            const uint32_t q = threadIdx.x + kWG * u, r = q / 25u, kk = q - 25u * r;
+            v[u] = 0;
+            if (r < nr) {
+                const uint32_t ix = sidx[j0 + r];
+                if (ix < rq.n) v[u] = src[(uint64_t)ix * 25 + kk];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 25; u++) {
+            const uint32_t q = threadIdx.x + kWG * u, r = q / 25u;
+            if (r < nr) dst[(uint64_t)j0 * 25 + q] = v[u];
+        }
+    }
+}
+
 __global__ __launch_bounds__(kWG) void k_local(Work w, Tune tu) {
     __shared__ uint64_t sH[kLocalCap];
     __shared__ uint64_t sL[kLocalCap];
@@ -581,6 +618,7 @@ __global__ __launch_bounds__(kWG) void k_local(Work w, Tune tu) {
     __shared__ uint32_t s_task;
 
     const uint32_t ntask = min(w.ctl->ntask, w.max_tasks);
+    const uint32_t nreq = w.hdr->nreq;
     const uint32_t tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     for (;;) {
         __syncthreads();
@@ -589,16 +627,22 @@ __global__ __launch_bounds__(kWG) void k_local(Work w, Tune tu) {
         const uint32_t j = s_task;
         if (j >= ntask) break;
         const Task tk = w.tasks[j];
-        if (tk.start + tk.count > w.n || tk.buf > 1 || tk.count > kLocalCap) {
+        if (tk.start + tk.count > w.n || tk.buf > 1 || tk.count > kLocalCap || tk.req >= nreq) {
+            if (tid == 0) atomicOr(&w.ctl->guard, 64u);
+            continue;
+        }
+        const Req rq = w.reqs[tk.req];
+        if (tk.start < rq.start || tk.start + tk.count > rq.start + rq.n) {
             if (tid == 0) atomicOr(&w.ctl->guard, 64u);
             continue;
         }
         const uint64_t *Hs = w.H[tk.buf] + tk.start;
         const uint64_t *Ls = w.L[tk.buf] + tk.start;
-        uint32_t *out = w.idx + tk.start;
         const uint32_t m = tk.count;
-        if ((tk.flags & kTaskSorted) || m <= 1) {
-            for (uint32_t q = tid; q < m; q += kWG) out[q] = (uint32_t)Ls[q];
+        if ((tk.flags & kTaskSorted) || m <= 1) {  // already in order
+            for (uint32_t q = tid; q < m; q += kWG) segb[q] = (uint32_t)Ls[q];
+            __syncthreads();
+            gather_task(rq, tk.start, m, segb);
             continue;
         }
         for (uint32_t q = tid; q < m; q += kWG) {
@@ -704,58 +748,11 @@ __global__ __launch_bounds__(kWG) void k_local(Work w, Tune tu) {
             if (q < m) segb[fv[u]] = iv[u];
         }
         __syncthreads();
-        for (uint32_t q = tid; q < m; q += kWG) out[q] = segb[q];
+        gather_task(rq, tk.start, m, segb);
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_gather: records in sorted order, out[j] = in[idx[j]] per request.  A
-// block copies 256 records with one dword per lane per step, so stores are
-// contiguous and each source record is read as whole 100-byte spans.
-
-__device__ __forceinline__ uint32_t find_req(const Req *reqs, uint32_t nreq, uint64_t g) {
-    uint32_t lo = 0, hi = nreq - 1;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (reqs[mid].start <= g) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-__global__ __launch_bounds__(kWG) void k_gather(const Req *reqs, const Hdr *hdr, const uint32_t *idx) {
-    __shared__ const uint32_t *ssrc[kWG];
-    __shared__ uint32_t *sdst[kWG];
-    const uint64_t n = hdr->n_total;
-    const uint32_t nreq = hdr->nreq;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * kWG; g0 < n; g0 += (uint64_t)gridDim.x * kWG) {
-        const uint32_t nr = (uint32_t)min<uint64_t>(kWG, n - g0);
-        __syncthreads();
-        if (threadIdx.x < nr) {
-            const uint64_t g = g0 + threadIdx.x;
-            const uint32_t r = find_req(reqs, nreq, g);
-            const Req rq = reqs[r];
-            const uint32_t ix = idx[g];
-            // a sorted index is always inside its request; fall back to the
-            // record itself if a guard fired upstream
-            const uint64_t si = ix < rq.n ? ix : (g - rq.start);
-            ssrc[threadIdx.x] = reinterpret_cast<const uint32_t *>(rq.in + si * kRec);
-            sdst[threadIdx.x] = reinterpret_cast<uint32_t *>(rq.out + (g - rq.start) * kRec);
-        }
-        __syncthreads();
-        uint32_t v[25];
-#pragma unroll
-        for (int u = 0; u < 25; u++) {
-            const uint32_t q = threadIdx.x + kWG * u, r = q / 25u, kk = q - 25u * r;
-            if (r < nr) v[u] = ssrc[r][kk];
-        }
-#pragma unroll
-        for (int u = 0; u < 25; u++) {
-            const uint32_t q = threadIdx.x + kWG * u, r = q / 25u, kk = q - 25u * r;
-            if (r < nr) sdst[r][kk] = v[u];
-        }
-    }
-}
-
 // Plain gather for the step-level test entry point.
 __global__ __launch_bounds__(kWG) void k_gather_plain(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx,
                                                       uint8_t *out, uint64_t n) {
@@ -838,15 +835,6 @@ hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_
                             int cus, hipEvent_t *ev) {
     if (t.tile_items == 8) return launch_levels<8>(w, t, nreq, tiles0, s, cus, ev);
     return launch_levels<16>(w, t, nreq, tiles0, s, cus, ev);
-}
-
-hipError_t launch_gather_batch(const Work &w, uint32_t nreq, hipStream_t s, int cus) {
-    (void)nreq;
-    const uint64_t blocks = (w.n + kWG - 1) / kWG;
-    const uint64_t cap = (uint64_t)cus * 64;
-    const uint32_t g = (uint32_t)(blocks < 1 ? 1 : (blocks < cap ? blocks : cap));
-    k_gather<<<dim3(g), dim3(kWG), 0, s>>>(w.reqs, w.hdr, w.idx);
-    return hipGetLastError();
 }
 
 hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,
