@@ -338,7 +338,7 @@ def stats(stream=None) -> dict:
             "tasks": int(s.tasks), "guard": int(s.guard)}
 
 
-PHASES = ("extract", "partition", "local", "gather")  # "local" includes the fused record gather
+PHASES = ("extract", "partition", "local", "gather")
 
 
 def profile_enable(on: bool = True) -> None:

@@ -79,6 +79,7 @@ int engine_build(BatchEngine &E, hipStream_t user, uint64_t n, uint32_t r, const
     if ((e = hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return hip_fail(e, "hipStreamBeginCapture");
     hipError_t le = launch_sort_core(w, t, 0, 0, E.cap, device_cus());
+    if (le == hipSuccess) le = launch_gather_batch(w, E.cap, device_cus());
     e = hipStreamEndCapture(E.cap, &E.graph);
     if (le != hipSuccess) return hip_fail(le, "batch capture launches");
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");

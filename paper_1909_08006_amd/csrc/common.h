@@ -95,6 +95,7 @@ struct Tune {
 struct Work {
     uint64_t *H[2];      // big-endian key bytes 0..7
     uint64_t *L[2];      // (key bytes 8..9) << 32 | record index
+    uint32_t *idx;       // sorted record index per output position
     Ctl *ctl;
     Seg *segs[2];        // by level parity
     uint32_t *rep[2];    // histogram replicas [rep][kRepWords], by level parity
@@ -111,7 +112,7 @@ struct Work {
 struct Layout {
     uint64_t n;
     uint32_t max_seg, max_tiles, max_tasks, max_reqs, max_reps;
-    size_t off_H0, off_H1, off_L0, off_L1, off_ctl, off_seg0, off_seg1, off_rep0,
+    size_t off_H0, off_H1, off_L0, off_L1, off_idx, off_ctl, off_seg0, off_seg1, off_rep0,
         off_rep1, off_ts0, off_ts1, off_status, off_tasks, off_reqs, off_hdr, total;
 };
 Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t);
@@ -119,12 +120,13 @@ Work bind_layout(const Layout &L, void *base);
 
 // Launch wrappers (sort_kernels.hip).  All return hipError_t of the launches.
 // ev (optional): three events recorded after extraction, after the
-// partition levels and after the local sorts with their record gathers.  nreq = tiles0 = 0 launches
+// partition levels and after the local sorts.  nreq = tiles0 = 0 launches
 // fixed grids that read every size from the device (for graph capture).
 hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
                             hipStream_t s, int cus, hipEvent_t *ev = nullptr);
 hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,
                                 uint64_t n, hipStream_t s);
+hipError_t launch_gather_batch(const Work &w, hipStream_t s, int cus, hipEvent_t done = nullptr);  // grid-stride, sizes from the device header
 hipError_t launch_debug_extract(const uint8_t *rec, uint64_t n, uint64_t *hi, uint64_t *lo,
                                 uint32_t *hist, hipStream_t s);
 

@@ -100,6 +100,7 @@ Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t) {
     L.off_H1 = take(nn * 8);
     L.off_L0 = take(nn * 8);
     L.off_L1 = take(nn * 8);
+    L.off_idx = take(nn * 4);
     L.off_ctl = take(sizeof(Ctl));
     L.off_seg0 = take((size_t)L.max_seg * sizeof(Seg));
     L.off_seg1 = take((size_t)L.max_seg * sizeof(Seg));
@@ -122,6 +123,7 @@ Work bind_layout(const Layout &L, void *base) {
     w.H[1] = reinterpret_cast<uint64_t *>(b + L.off_H1);
     w.L[0] = reinterpret_cast<uint64_t *>(b + L.off_L0);
     w.L[1] = reinterpret_cast<uint64_t *>(b + L.off_L1);
+    w.idx = reinterpret_cast<uint32_t *>(b + L.off_idx);
     w.ctl = reinterpret_cast<Ctl *>(b + L.off_ctl);
     w.segs[0] = reinterpret_cast<Seg *>(b + L.off_seg0);
     w.segs[1] = reinterpret_cast<Seg *>(b + L.off_seg1);
@@ -321,8 +323,11 @@ int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream
     k_setup_single<<<1, 1, 0, stream>>>(w.reqs, w.hdr, static_cast<const uint8_t *>(records_dev),
                                         static_cast<uint8_t *>(out_dev), n, tiles0);
     hipError_t e = launch_sort_core(w, t, 1, tiles0, stream, device_cus(), prof ? pc.e + 1 : nullptr);
-    if (prof) prof_finish(pc, stream);
     if (e != hipSuccess) return hip_fail(e, "sort kernels");
+    e = launch_gather_single(static_cast<const uint8_t *>(records_dev), n, w.idx, static_cast<uint8_t *>(out_dev),
+                             n, stream);
+    if (prof) prof_finish(pc, stream);
+    if (e != hipSuccess) return hip_fail(e, "gather kernel");
     return LEYENDA_OK;
 }
 

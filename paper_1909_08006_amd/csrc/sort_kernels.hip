@@ -15,9 +15,9 @@
 //   k_local     per small bucket, in one workgroup's LDS: radix partition on
 //               the first varying digit (SingleThreadRadixSort), recursion on
 //               sub-buckets above the tiny threshold, and a comparison sort of
-//               tiny sub-buckets (ComparisonSort); then the same workgroup
-//               scatters the bucket's records by the sorted tuples into the
-//               output (record scatter of Section 3.2): out[j] = in[idx[j]]
+//               tiny sub-buckets (ComparisonSort)
+//   k_gather    record scatter by the sorted tuples (Section 3.2):
+//               out[j] = in[idx[j]]
 //
 // Tuples are kept as two arrays (struct of arrays): H = key bytes 0..7 as a
 // big-endian u64, L = key bytes 8..9 (big-endian) << 32 | record index.
@@ -578,36 +578,22 @@ __device__ __forceinline__ uint64_t wave_and64(uint64_t v) {
 
 constexpr int kStack = kLocalCap / 2;
 
-// Records of one sorted task into its request's output: out[j] = in[sidx[j]].
-// One dword per lane per step over the task's contiguous output range, so
-// stores are contiguous and each source record is read as whole 100-byte spans.
-__device__ __forceinline__ void gather_task(const Req &rq, uint64_t task_start, uint32_t m, const uint32_t *sidx) {
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(rq.in);
-    uint32_t *dst = reinterpret_cast<uint32_t *>(rq.out + (task_start - rq.start) * kRec);
-    for (uint32_t j0 = 0; j0 < m; j0 += kWG) {
-        const uint32_t nr = min((uint32_t)kWG, m - j0);
-        uint32_t v[25];
-#pragma unroll
-        for (int u = 0; u < 25; u++) {
-            const uint32_t q = threadIdx.x + kWG * u, r = q / 25u, kk = q - 25u * r;
-            v[u] = 0;
-            if (r < nr) {
-                const uint32_t ix = sidx[j0 + r];
-                if (ix < rq.n) v[u] = src[(uint64_t)ix * 25 + kk];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 25; u++) {
-            const uint32_t q = threadIdx.x + kWG * u, r = q / 25u;
-            if (r < nr) dst[(uint64_t)j0 * 25 + q] = v[u];
-        }
-    }
+// A task read back from the device list is inside the tuple space and inside
+// its request (defence against a fired capacity guard).
+__device__ __forceinline__ bool task_ok(const Work &w, const Task &tk, uint32_t nreq) {
+    if (tk.start + tk.count > w.n || tk.buf > 1 || tk.count > kLocalCap || tk.req >= nreq) return false;
+    const Req &rq = w.reqs[tk.req];
+    return tk.start >= rq.start && tk.start + tk.count <= rq.start + rq.n;
 }
 
+// Small buckets, each sorted in one workgroup's LDS; the sorted order (record
+// index per output position) goes to idx for the gather.  The next task id is
+// taken before the sort and its descriptor read before the write-out, so
+// neither waits on the critical path.
 __global__ __launch_bounds__(kWG) void k_local(Work w, Tune tu) {
     __shared__ uint64_t sH[kLocalCap];
     __shared__ uint64_t sL[kLocalCap];
-    __shared__ uint32_t segb[kLocalCap];   // per position: sub-bucket [lo, hi) packed lo | hi << 16
+    __shared__ uint32_t segb[kLocalCap];   // sub-bucket [lo, hi) per position (lo | hi << 16); then the order
     __shared__ uint32_t cnt[kWaves][kRadix];
     __shared__ uint32_t lbase[kRadix];
     __shared__ uint32_t ltot[kRadix];
@@ -615,42 +601,53 @@ __global__ __launch_bounds__(kWG) void k_local(Work w, Tune tu) {
     __shared__ uint32_t tmp[kWaves];
     __shared__ uint64_t orh[kWaves], andh[kWaves], orl[kWaves], andl[kWaves];
     __shared__ int stk_n;
-    __shared__ uint32_t s_task;
+    __shared__ uint32_t s_next;
 
     const uint32_t ntask = min(w.ctl->ntask, w.max_tasks);
     const uint32_t nreq = w.hdr->nreq;
     const uint32_t tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-    for (;;) {
-        __syncthreads();
-        if (tid == 0) s_task = atomicAdd(&w.ctl->task_ctr, 1u);
-        __syncthreads();
-        const uint32_t j = s_task;
-        if (j >= ntask) break;
-        const Task tk = w.tasks[j];
-        if (tk.start + tk.count > w.n || tk.buf > 1 || tk.count > kLocalCap || tk.req >= nreq) {
-            if (tid == 0) atomicOr(&w.ctl->guard, 64u);
-            continue;
+
+    // current task descriptor; its keys are read straight into LDS
+    Task tk{};
+    bool ok = false;
+    auto fetch = [&](uint32_t jn) {
+        ok = false;
+        if (jn < ntask) {
+            tk = w.tasks[jn];
+            ok = task_ok(w, tk, nreq);
+            if (!ok && tid == 0) atomicOr(&w.ctl->guard, 64u);
         }
-        const Req rq = w.reqs[tk.req];
-        if (tk.start < rq.start || tk.start + tk.count > rq.start + rq.n) {
-            if (tid == 0) atomicOr(&w.ctl->guard, 64u);
-            continue;
+    };
+
+    if (tid == 0) s_next = atomicAdd(&w.ctl->task_ctr, 1u);
+    __syncthreads();
+    uint32_t j = s_next;
+    fetch(j);
+    while (j < ntask) {
+        const bool cur_ok = ok;
+        const Task cur = tk;
+        const uint32_t m = cur_ok ? cur.count : 0u;
+        const bool sorted = (cur.flags & kTaskSorted) || m <= 1;
+        __syncthreads();  // the previous task's gather is done with segb
+        // the task's keys into LDS
+        {
+            const uint64_t *Hs = w.H[cur.buf] + cur.start;
+            const uint64_t *Ls = w.L[cur.buf] + cur.start;
+            for (uint32_t q = tid; q < m; q += kWG) {
+                if (sorted) {
+                    segb[q] = (uint32_t)Ls[q];
+                } else {
+                    sH[q] = Hs[q];
+                    sL[q] = Ls[q];
+                    segb[q] = q | ((q + 1) << 16);
+                }
+            }
         }
-        const uint64_t *Hs = w.H[tk.buf] + tk.start;
-        const uint64_t *Ls = w.L[tk.buf] + tk.start;
-        const uint32_t m = tk.count;
-        if ((tk.flags & kTaskSorted) || m <= 1) {  // already in order
-            for (uint32_t q = tid; q < m; q += kWG) segb[q] = (uint32_t)Ls[q];
-            __syncthreads();
-            gather_task(rq, tk.start, m, segb);
-            continue;
+        if (tid == 0) {
+            stk[0] = 0u | (m << 16);
+            stk_n = sorted ? 0 : 1;
+            s_next = atomicAdd(&w.ctl->task_ctr, 1u);  // next task id, used after the sort
         }
-        for (uint32_t q = tid; q < m; q += kWG) {
-            sH[q] = Hs[q];
-            sL[q] = Ls[q];
-            segb[q] = q | ((q + 1) << 16);
-        }
-        if (tid == 0) { stk[0] = 0u | (m << 16); stk_n = 1; }
         __syncthreads();
         for (;;) {
             const int nst = min(stk_n, kStack);
@@ -721,38 +718,110 @@ __global__ __launch_bounds__(kWG) void k_local(Work w, Tune tu) {
             }
             __syncthreads();
         }
-        // tiny sub-buckets: position = sub-bucket start + number of smaller tuples
-        uint32_t fv[kLocalItems], iv[kLocalItems];
+        if (!sorted) {
+            // tiny sub-buckets: position = sub-bucket start + number of smaller tuples
+            uint32_t fv[kLocalItems], iv[kLocalItems];
 #pragma unroll
-        for (int u = 0; u < kLocalItems; u++) {
-            const uint32_t q = u * kWG + tid;
-            fv[u] = q; iv[u] = 0;
-            if (q < m) {
-                const uint32_t sb = segb[q], lo = sb & 0xFFFFu, hi = min(sb >> 16, m);
-                const uint64_t kh = sH[q], kl = sL[q];
-                iv[u] = (uint32_t)kl;
-                if (hi > lo + 1) {
-                    uint32_t r = 0;
-                    for (uint32_t jj = lo; jj < hi; jj++) {
-                        const uint64_t oh2 = sH[jj], ol2 = sL[jj];
-                        r += (oh2 < kh) || (oh2 == kh && ol2 < kl);
+            for (int u = 0; u < kLocalItems; u++) {
+                const uint32_t q = u * kWG + tid;
+                fv[u] = q; iv[u] = 0;
+                if (q < m) {
+                    const uint32_t sb = segb[q], lo = sb & 0xFFFFu, hi = min(sb >> 16, m);
+                    const uint64_t kh = sH[q], kl = sL[q];
+                    iv[u] = (uint32_t)kl;
+                    if (hi > lo + 1) {
+                        uint32_t r = 0;
+                        for (uint32_t jj = lo; jj < hi; jj++) {
+                            const uint64_t oh2 = sH[jj], ol2 = sL[jj];
+                            r += (oh2 < kh) || (oh2 == kh && ol2 < kl);
+                        }
+                        fv[u] = lo + r;
                     }
-                    fv[u] = lo + r;
                 }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kLocalItems; u++) {
+                const uint32_t q = u * kWG + tid;
+                if (q < m) segb[fv[u]] = iv[u];
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kLocalItems; u++) {
-            const uint32_t q = u * kWG + tid;
-            if (q < m) segb[fv[u]] = iv[u];
+        const uint32_t jn = s_next;
+        fetch(jn);
+        if (cur_ok) {
+            uint32_t *out = w.idx + cur.start;
+            for (uint32_t q = tid; q < m; q += kWG) out[q] = segb[q];
         }
-        __syncthreads();
-        gather_task(rq, tk.start, m, segb);
+        j = jn;
     }
 }
 
 // ---------------------------------------------------------------------------
+// k_gather: records in sorted order, out[j] = in[idx[j]] per request.  A
+// block copies 256 records with one dword per lane per step, so stores are
+// contiguous and each source record is read as whole 100-byte spans.
+
+__device__ __forceinline__ uint32_t find_req(const Req *reqs, uint32_t nreq, uint64_t g) {
+    uint32_t lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (reqs[mid].start <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kWG) void k_gather(const Req *reqs, const Hdr *hdr, const uint32_t *idx) {
+    __shared__ uint32_t sidx[kWG];
+    __shared__ uint32_t s_r0, s_r1;
+    const uint64_t n = hdr->n_total;
+    const uint32_t nreq = hdr->nreq;
+    const uint64_t g0 = (uint64_t)blockIdx.x * kWG;
+    if (g0 >= n) return;
+    const uint32_t nr = (uint32_t)min<uint64_t>(kWG, n - g0);
+    if (threadIdx.x == 0) s_r0 = find_req(reqs, nreq, g0);
+    if (threadIdx.x == 64) s_r1 = find_req(reqs, nreq, g0 + nr - 1);
+    __syncthreads();
+    const uint32_t r0 = __builtin_amdgcn_readfirstlane(s_r0), r1 = __builtin_amdgcn_readfirstlane(s_r1);
+    if (r0 == r1) {  // the whole block belongs to one request (the common case)
+        const uint8_t *in = reqs[r0].in;
+        uint8_t *out = reqs[r0].out;
+        const uint64_t rn = reqs[r0].n, rs = reqs[r0].start;
+        if (threadIdx.x < nr) {
+            const uint32_t ix = idx[g0 + threadIdx.x];
+            sidx[threadIdx.x] = ix < rn ? ix : (uint32_t)(g0 + threadIdx.x - rs);
+        }
+        __syncthreads();
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(in);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(out) + (g0 - rs) * 25;
+        uint32_t v[25];
+#pragma unroll
+        for (int u = 0; u < 25; u++) {
+            const uint32_t q = threadIdx.x + kWG * u, r = q / 25u, kk = q - 25u * r;
+            if (r < nr) v[u] = src[(uint64_t)sidx[r] * 25 + kk];
+        }
+#pragma unroll
+        for (int u = 0; u < 25; u++) {
+            const uint32_t q = threadIdx.x + kWG * u, r = q / 25u;
+            if (r < nr) dst[q] = v[u];
+        }
+        return;
+    }
+    // a block across a request boundary: one record per thread
+    if (threadIdx.x < nr) {
+        const uint64_t g = g0 + threadIdx.x;
+        const uint32_t r = find_req(reqs, nreq, g);
+        const Req rq = reqs[r];
+        const uint32_t ix = idx[g];
+        // a sorted index is always inside its request; fall back to the
+        // record itself if a guard fired upstream
+        const uint64_t si = ix < rq.n ? ix : (g - rq.start);
+        const uint32_t *s1 = reinterpret_cast<const uint32_t *>(rq.in + si * kRec);
+        uint32_t *d1 = reinterpret_cast<uint32_t *>(rq.out + (g - rq.start) * kRec);
+        for (int kk = 0; kk < 25; kk++) d1[kk] = s1[kk];
+    }
+}
+
 // Plain gather for the step-level test entry point.
 __global__ __launch_bounds__(kWG) void k_gather_plain(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx,
                                                       uint8_t *out, uint64_t n) {
@@ -835,6 +904,16 @@ hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_
                             int cus, hipEvent_t *ev) {
     if (t.tile_items == 8) return launch_levels<8>(w, t, nreq, tiles0, s, cus, ev);
     return launch_levels<16>(w, t, nreq, tiles0, s, cus, ev);
+}
+
+hipError_t launch_gather_batch(const Work &w, hipStream_t s, int cus, hipEvent_t done) {
+    (void)done;
+    (void)cus;
+    // one block per 256 records of the workspace capacity; blocks past the
+    // batch's record count exit at once
+    const uint64_t blocks = (w.n + kWG - 1) / kWG;
+    k_gather<<<dim3((uint32_t)(blocks < 1 ? 1 : blocks)), dim3(kWG), 0, s>>>(w.reqs, w.hdr, w.idx);
+    return hipGetLastError();
 }
 
 hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,
