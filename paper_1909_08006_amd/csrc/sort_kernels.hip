@@ -587,10 +587,10 @@ __device__ __forceinline__ bool task_ok(const Work &w, const Task &tk, uint32_t 
 }
 
 // Small buckets, each sorted in one workgroup's LDS; the sorted order (record
-// index per output position) goes to idx for the gather.  The next task id is
-// taken before the sort and its descriptor read before the write-out, so
-// neither waits on the critical path.
-__global__ __launch_bounds__(kWG) void k_local(Work w, Tune tu) {
+// index per output position) goes to idx for the gather.  Task ids are taken
+// one task ahead and the next task's keys are loaded into registers while the
+// current task sorts, so global latency stays off the critical path.
+__global__ __launch_bounds__(kWG, 3) void k_local(Work w, Tune tu) {
     __shared__ uint64_t sH[kLocalCap];
     __shared__ uint64_t sL[kLocalCap];
     __shared__ uint32_t segb[kLocalCap];   // sub-bucket [lo, hi) per position (lo | hi << 16); then the order
@@ -607,7 +607,9 @@ __global__ __launch_bounds__(kWG) void k_local(Work w, Tune tu) {
     const uint32_t nreq = w.hdr->nreq;
     const uint32_t tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
 
-    // current task descriptor; its keys are read straight into LDS
+    // the next task: descriptor and keys in registers (striped, q = u * kWG + tid),
+    // loaded while the current task sorts
+    uint64_t ph[kLocalItems], pl[kLocalItems];
     Task tk{};
     bool ok = false;
     auto fetch = [&](uint32_t jn) {
@@ -617,38 +619,58 @@ __global__ __launch_bounds__(kWG) void k_local(Work w, Tune tu) {
             ok = task_ok(w, tk, nreq);
             if (!ok && tid == 0) atomicOr(&w.ctl->guard, 64u);
         }
+        const uint32_t c = ok ? tk.count : 0u;
+        const uint64_t *Hs = w.H[tk.buf & 1] + tk.start;
+        const uint64_t *Ls = w.L[tk.buf & 1] + tk.start;
+#pragma unroll
+        for (int u = 0; u < kLocalItems; u++) {
+            const uint32_t q = u * kWG + tid;
+            ph[u] = 0; pl[u] = 0;
+            if (q < c) { ph[u] = Hs[q]; pl[u] = Ls[q]; }
+        }
     };
 
     if (tid == 0) s_next = atomicAdd(&w.ctl->task_ctr, 1u);
     __syncthreads();
     uint32_t j = s_next;
     fetch(j);
+    __syncthreads();
+    if (tid == 0) s_next = atomicAdd(&w.ctl->task_ctr, 1u);  // one task ahead
     while (j < ntask) {
         const bool cur_ok = ok;
         const Task cur = tk;
         const uint32_t m = cur_ok ? cur.count : 0u;
         const bool sorted = (cur.flags & kTaskSorted) || m <= 1;
-        __syncthreads();  // the previous task's gather is done with segb
-        // the task's keys into LDS
-        {
-            const uint64_t *Hs = w.H[cur.buf] + cur.start;
-            const uint64_t *Ls = w.L[cur.buf] + cur.start;
-            for (uint32_t q = tid; q < m; q += kWG) {
+        // the task's keys into LDS, with the key masks of the whole task
+        uint64_t th = 0, tah = ~0ull, tl = 0, tal = ~0ull;
+#pragma unroll
+        for (int u = 0; u < kLocalItems; u++) {
+            const uint32_t q = u * kWG + tid;
+            if (q < m) {
                 if (sorted) {
-                    segb[q] = (uint32_t)Ls[q];
+                    segb[q] = (uint32_t)pl[u];
                 } else {
-                    sH[q] = Hs[q];
-                    sL[q] = Ls[q];
+                    sH[q] = ph[u];
+                    sL[q] = pl[u];
                     segb[q] = q | ((q + 1) << 16);
+                    const uint64_t kk = (pl[u] >> 32) & 0xFFFFu;
+                    th |= ph[u]; tah &= ph[u]; tl |= kk; tal &= kk;
                 }
             }
         }
+        th = wave_or64(th); tah = wave_and64(tah);
+        tl = wave_or64(tl); tal = wave_and64(tal);
+        if (lane == 0) { orh[wv] = th; andh[wv] = tah; orl[wv] = tl; andl[wv] = tal; }
         if (tid == 0) {
             stk[0] = 0u | (m << 16);
             stk_n = sorted ? 0 : 1;
-            s_next = atomicAdd(&w.ctl->task_ctr, 1u);  // next task id, used after the sort
         }
         __syncthreads();
+        const uint32_t jn = s_next;
+        fetch(jn);  // the next task's keys load while this one sorts
+        __syncthreads();
+        if (tid == 0) s_next = atomicAdd(&w.ctl->task_ctr, 1u);
+        bool top = true;
         for (;;) {
             const int nst = min(stk_n, kStack);
             if (nst <= 0) break;
@@ -656,16 +678,19 @@ __global__ __launch_bounds__(kWG) void k_local(Work w, Tune tu) {
             __syncthreads();
             if (tid == 0) stk_n = nst - 1;
             const uint32_t a = e & 0xFFFFu, len = e >> 16;
-            // which key bits vary over [a, a + len)
-            uint64_t oh = 0, ah = ~0ull, ol = 0, al = ~0ull;
-            for (uint32_t q = a + tid; q < a + len; q += kWG) {
-                const uint64_t hh = sH[q], kk = (sL[q] >> 32) & 0xFFFFu;
-                oh |= hh; ah &= hh; ol |= kk; al &= kk;
+            // which key bits vary over [a, a + len) (for the whole task: from the load)
+            if (!top) {
+                uint64_t oh = 0, ah = ~0ull, ol = 0, al = ~0ull;
+                for (uint32_t q = a + tid; q < a + len; q += kWG) {
+                    const uint64_t hh = sH[q], kk = (sL[q] >> 32) & 0xFFFFu;
+                    oh |= hh; ah &= hh; ol |= kk; al &= kk;
+                }
+                oh = wave_or64(oh); ah = wave_and64(ah);
+                ol = wave_or64(ol); al = wave_and64(al);
+                if (lane == 0) { orh[wv] = oh; andh[wv] = ah; orl[wv] = ol; andl[wv] = al; }
+                __syncthreads();
             }
-            oh = wave_or64(oh); ah = wave_and64(ah);
-            ol = wave_or64(ol); al = wave_and64(al);
-            if (lane == 0) { orh[wv] = oh; andh[wv] = ah; orl[wv] = ol; andl[wv] = al; }
-            __syncthreads();
+            top = false;
             uint64_t OH = 0, AH = ~0ull, OL = 0, AL = ~0ull;
 #pragma unroll
             for (int k2 = 0; k2 < kWaves; k2++) { OH |= orh[k2]; AH &= andh[k2]; OL |= orl[k2]; AL &= andl[k2]; }
@@ -747,12 +772,11 @@ __global__ __launch_bounds__(kWG) void k_local(Work w, Tune tu) {
             }
         }
         __syncthreads();
-        const uint32_t jn = s_next;
-        fetch(jn);
         if (cur_ok) {
             uint32_t *out = w.idx + cur.start;
             for (uint32_t q = tid; q < m; q += kWG) out[q] = segb[q];
         }
+        __syncthreads();  // segb and the mask slots are reused by the next task
         j = jn;
     }
 }
