@@ -201,6 +201,8 @@ int leyenda_serve_replay(const leyenda_server_config *cfg, uint64_t count, const
  *                ordered by comparisons instead of another radix partition
  *                (Algorithm 1's tinyBucketThreshold); 1..64.
  * local_capacity keys one workgroup sorts in LDS (2048).
+ * scatter_threads threads per device-wide partition workgroup (256 or 512;
+ *                the tile stays 256 * tile_items keys).
  * ------------------------------------------------------------------------- */
 typedef struct {
     uint32_t digit_bits;
@@ -208,6 +210,7 @@ typedef struct {
     uint32_t big_threshold;
     uint32_t tiny_threshold;
     uint32_t local_capacity;
+    uint32_t scatter_threads;
 } leyenda_params;
 
 int leyenda_get_params(leyenda_params *out);

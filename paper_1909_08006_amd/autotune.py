@@ -27,7 +27,8 @@ DEFAULT_SPACE = {
     "digit_bits": [8],
     "tile_items": [8, 16],
     "big_threshold": [512, 1024, 2048],
-    "tiny_threshold": [8, 16, 32, 64],
+    "tiny_threshold": [16, 32, 64],
+    "scatter_threads": [256, 512],
 }
 
 

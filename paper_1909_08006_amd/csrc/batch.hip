@@ -52,7 +52,8 @@ std::mutex g_batch_mu;
 std::map<std::pair<int, hipStream_t>, BatchEngine> g_batch;
 
 bool same_tune(const Tune &a, const Tune &b) {
-    return a.tile_items == b.tile_items && a.tile == b.tile && a.big == b.big && a.tiny == b.tiny;
+    return a.tile_items == b.tile_items && a.tile == b.tile && a.big == b.big && a.tiny == b.tiny &&
+           a.scatter_wg == b.scatter_wg;
 }
 
 // (Re)builds the engine for at least n records and r requests: workspace,

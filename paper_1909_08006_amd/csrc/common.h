@@ -89,6 +89,7 @@ struct Tune {
     uint32_t tile;         // kWG * tile_items
     uint32_t big;          // big-bucket threshold
     uint32_t tiny;         // comparison-sort threshold inside the local sort
+    uint32_t scatter_wg;   // threads per partition workgroup (256 or 512; same tile)
 };
 
 // Device workspace views for one sort.

@@ -75,8 +75,9 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint32_t *
     return base + below;
 }
 
-// Exclusive prefix sum over the workgroup's 256 threads (one value each).
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp /*[kWaves]*/) {
+// Exclusive prefix sum over the workgroup's threads (one value each; NW waves).
+template <int NW = kWaves>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp /*[NW]*/) {
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t x = v;
 #pragma unroll
@@ -88,7 +89,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp /*
     __syncthreads();
     uint32_t pre = 0;
 #pragma unroll
-    for (int k = 0; k < kWaves; k++) pre += (k < (int)w) ? tmp[k] : 0u;
+    for (int k = 0; k < NW; k++) pre += (k < (int)w) ? tmp[k] : 0u;
     __syncthreads();
     return pre + x - v;
 }
@@ -439,15 +440,18 @@ __global__ __launch_bounds__(kWG) void k_plan(Work w, Tune tu, int lev) {
 // ---------------------------------------------------------------------------
 // k_scatter: one device-wide stable partition pass of the big buckets of level lev
 
-template <int ITEMS>
-__global__ __launch_bounds__(kWG) void k_scatter(Work w, Tune tu, int lev) {
-    constexpr int TILE = kWG * ITEMS;
+// WG threads, ITEMS keys each (a tile is WG * ITEMS keys); the 256 digit
+// lanes of the histogram, look-back and offsets are threads 0..255.
+template <int ITEMS, int WG>
+__global__ __launch_bounds__(WG) void k_scatter(Work w, Tune tu, int lev) {
+    constexpr int TILE = WG * ITEMS;
+    constexpr int NW = WG / 64;
     __shared__ uint64_t sH[TILE];
     __shared__ uint64_t sL[TILE];
-    __shared__ uint32_t cnt[kWaves][kRadix];
+    __shared__ uint32_t cnt[NW][kRadix];
     __shared__ uint32_t lbase[kRadix];
     __shared__ unsigned long long gbase[kRadix];
-    __shared__ uint32_t tmp[kWaves];
+    __shared__ uint32_t tmp[NW];
     __shared__ uint32_t s_tile;
 
     const uint32_t ntiles = min(w.ctl->ntiles[lev], w.max_tiles);
@@ -469,8 +473,7 @@ __global__ __launch_bounds__(kWG) void k_scatter(Work w, Tune tu, int lev) {
         const uint32_t nvalid = (uint32_t)min<uint64_t>(TILE, sg.count - local0);
         const uint64_t *Hs = w.H[sg.buf] + sg.start + local0;
         const uint64_t *Ls = w.L[sg.buf] + sg.start + local0;
-#pragma unroll
-        for (int j = 0; j < kWaves; j++) cnt[j][tid] = 0;
+        for (uint32_t i = tid; i < NW * kRadix; i += WG) (&cnt[0][0])[i] = 0;
         uint64_t h[ITEMS], l[ITEMS];
         uint32_t dg[ITEMS], rk[ITEMS];
 #pragma unroll
@@ -488,18 +491,22 @@ __global__ __launch_bounds__(kWG) void k_scatter(Work w, Tune tu, int lev) {
             rk[u] = wave_rank(dg[u], valid, cnt[wv]);
         }
         __syncthreads();
-        // per-digit wave prefixes and the tile total
+        // per-digit wave prefixes and the tile total (digit lanes: tid < 256)
+        const bool dl = tid < (uint32_t)kRadix;
         uint32_t tot = 0;
+        if (dl) {
 #pragma unroll
-        for (int j = 0; j < kWaves; j++) {
-            const uint32_t cj = cnt[j][tid];
-            cnt[j][tid] = tot;
-            tot += cj;
+            for (int j = 0; j < NW; j++) {
+                const uint32_t cj = cnt[j][tid];
+                cnt[j][tid] = tot;
+                tot += cj;
+            }
         }
         // decoupled look-back over earlier tiles of the same bucket
-        unsigned long long *st = w.status + (size_t)tile * kRadix + tid;
+        unsigned long long *st = w.status + (size_t)tile * kRadix + (dl ? tid : 0u);
         unsigned long long excl = 0;
-        if (k == 0) {
+        if (!dl) {
+        } else if (k == 0) {
             st_agent(st, kFlagInc | tot);
         } else {
             st_agent(st, kFlagAgg | tot);
@@ -517,10 +524,12 @@ __global__ __launch_bounds__(kWG) void k_scatter(Work w, Tune tu, int lev) {
             }
             st_agent(st, kFlagInc | (excl + tot));
         }
-        const uint32_t lb = block_excl_scan(tot, tmp);
-        const uint32_t bb = w.rep[lev & 1][(size_t)sg.rep_first * kRepWords + tid];
-        lbase[tid] = lb;
-        gbase[tid] = sg.start + bb + excl - lb;
+        const uint32_t lb = block_excl_scan<NW>(tot, tmp);
+        if (dl) {
+            const uint32_t bb = w.rep[lev & 1][(size_t)sg.rep_first * kRepWords + tid];
+            lbase[tid] = lb;
+            gbase[tid] = sg.start + bb + excl - lb;
+        }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < ITEMS; u++) {
@@ -536,7 +545,7 @@ __global__ __launch_bounds__(kWG) void k_scatter(Work w, Tune tu, int lev) {
         uint64_t *Ld = w.L[sg.buf ^ 1];
 #pragma unroll
         for (int u = 0; u < ITEMS; u++) {
-            const uint32_t q = u * kWG + tid;
+            const uint32_t q = u * WG + tid;
             if (q < nvalid) {
                 const uint64_t hh = sH[q], ll = sL[q];
                 const uint64_t dst = gbase[digit_at(hh, ll, sg.spos)] + q;
@@ -556,9 +565,9 @@ __global__ __launch_bounds__(kWG) void k_scatter(Work w, Tune tu, int lev) {
         if (g.count == 0 || (uint64_t)g.first_tile + g.ntiles > w.max_tiles ||
             (uint64_t)g.rep_first + g.nrep > w.max_reps)
             continue;
-        for (uint32_t t = tid; t < g.ntiles; t += kWG) w.tile_seg[(lev + 1) & 1][g.first_tile + t] = s2;
+        for (uint32_t t = tid; t < g.ntiles; t += WG) w.tile_seg[(lev + 1) & 1][g.first_tile + t] = s2;
         uint32_t *rp = w.rep[(lev + 1) & 1] + (size_t)g.rep_first * kRepWords;
-        for (uint32_t i = tid; i < g.nrep * kRepWords; i += kWG) rp[i] = 0;
+        for (uint32_t i = tid; i < g.nrep * kRepWords; i += WG) rp[i] = 0;
     }
 }
 
@@ -892,13 +901,13 @@ __global__ __launch_bounds__(kWG) void k_extract_plain(const uint8_t *rec, uint6
 // ---------------------------------------------------------------------------
 // launch wrappers
 
-static int occupancy(const void *fn, int cus) {
+static int occupancy(const void *fn, int cus, int wg = kWG) {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kWG, 0) != hipSuccess || per < 1) per = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, wg, 0) != hipSuccess || per < 1) per = 1;
     return per * cus;
 }
 
-template <int ITEMS>
+template <int ITEMS, int SWG>
 static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
                                 hipStream_t s, int cus, hipEvent_t *ev) {
     // nreq / tiles0 == 0: sizes known only on the device (captured sequences)
@@ -906,9 +915,10 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
     const int g_ext = tiles0 ? (int)max(1u, min(tiles0, (uint32_t)(cus * 16))) : cus * 16;
     k_extract<ITEMS><<<dim3(g_ext), dim3(kWG), 0, s>>>(w, t);
     if (ev) (void)hipEventRecord(ev[0], s);
+    constexpr int SITEMS = ITEMS * kWG / SWG;  // same tile, SWG threads
     static int g_sc = 0, g_hist = 0, g_loc = 0;
     if (!g_sc) {
-        g_sc = occupancy(reinterpret_cast<const void *>(&k_scatter<ITEMS>), cus);
+        g_sc = occupancy(reinterpret_cast<const void *>(&k_scatter<SITEMS, SWG>), cus, SWG);
         g_hist = occupancy(reinterpret_cast<const void *>(&k_hist<ITEMS>), cus);
         g_loc = occupancy(reinterpret_cast<const void *>(&k_local), cus);
     }
@@ -916,7 +926,7 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
     for (int lev = 0; lev < kMaxLev; lev++) {
         if (lev > 0) k_hist<ITEMS><<<dim3(g_hist), dim3(kWG), 0, s>>>(w, t, lev);
         k_plan<<<dim3(g_plan), dim3(kWG), 0, s>>>(w, t, lev);
-        k_scatter<ITEMS><<<dim3(g_sc), dim3(kWG), 0, s>>>(w, t, lev);
+        k_scatter<SITEMS, SWG><<<dim3(g_sc), dim3(SWG), 0, s>>>(w, t, lev);
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     k_local<<<dim3(g_loc), dim3(kWG), 0, s>>>(w, t);
@@ -926,8 +936,11 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
 
 hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0, hipStream_t s,
                             int cus, hipEvent_t *ev) {
-    if (t.tile_items == 8) return launch_levels<8>(w, t, nreq, tiles0, s, cus, ev);
-    return launch_levels<16>(w, t, nreq, tiles0, s, cus, ev);
+    if (t.tile_items == 8)
+        return t.scatter_wg == 512 ? launch_levels<8, 512>(w, t, nreq, tiles0, s, cus, ev)
+                                   : launch_levels<8, 256>(w, t, nreq, tiles0, s, cus, ev);
+    return t.scatter_wg == 512 ? launch_levels<16, 512>(w, t, nreq, tiles0, s, cus, ev)
+                               : launch_levels<16, 256>(w, t, nreq, tiles0, s, cus, ev);
 }
 
 hipError_t launch_gather_batch(const Work &w, hipStream_t s, int cus, hipEvent_t done) {

@@ -38,9 +38,9 @@ def test_status_strings_and_param_checks():
     assert lib.leyenda_status_string(-3) == b"does not fit the device budget"
     assert lib.leyenda_status_string(0) == b"ok"
     p = ley.get_params()
-    assert p["digit_bits"] == 8 and p["local_capacity"] == 2048
+    assert p["digit_bits"] == 8 and p["local_capacity"] == 2048 and p["scatter_threads"] == 512
     for bad in [dict(tile_items=3), dict(big_threshold=0), dict(big_threshold=4096), dict(tiny_threshold=0),
-                dict(tiny_threshold=65), dict(digit_bits=4)]:
+                dict(tiny_threshold=65), dict(digit_bits=4), dict(scatter_threads=384)]:
         with pytest.raises(ley.LeyendaError):
             ley.set_params(**bad)
     assert ley.get_params() == p
@@ -51,9 +51,11 @@ def test_load_params_json(tmp_path):
     old = ley.get_params()
     try:
         f = tmp_path / "params.json"
-        f.write_text('{"tile_items": 8, "big_threshold": 1000, "tiny_threshold": 16, "comment": "x"}')
+        f.write_text('{"tile_items": 8, "big_threshold": 1000, "tiny_threshold": 16, "scatter_threads": 256, '
+                     '"comment": "x"}')
         p = ley.load_params(str(f))
         assert p["tile_items"] == 8 and p["big_threshold"] == 1000 and p["tiny_threshold"] == 16
+        assert p["scatter_threads"] == 256
     finally:
         ley.set_params(**old)
 
