@@ -203,6 +203,7 @@ int leyenda_serve_replay(const leyenda_server_config *cfg, uint64_t count, const
  * local_capacity keys one workgroup sorts in LDS (2048).
  * scatter_threads threads per device-wide partition workgroup (256 or 512;
  *                the tile stays 256 * tile_items keys).
+ * local_threads  threads per local-sort workgroup (256 or 512).
  * ------------------------------------------------------------------------- */
 typedef struct {
     uint32_t digit_bits;
@@ -211,6 +212,7 @@ typedef struct {
     uint32_t tiny_threshold;
     uint32_t local_capacity;
     uint32_t scatter_threads;
+    uint32_t local_threads;
 } leyenda_params;
 
 int leyenda_get_params(leyenda_params *out);

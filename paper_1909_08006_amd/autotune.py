@@ -29,6 +29,7 @@ DEFAULT_SPACE = {
     "big_threshold": [512, 1024, 2048],
     "tiny_threshold": [16, 32, 64],
     "scatter_threads": [256, 512],
+    "local_threads": [256, 512],
 }
 
 

@@ -14,6 +14,10 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from forming packed fp32 ops (see the project notes on gfx950)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # every global atomic on a uniform address here is issued by one lane, so
+    # the wave-combining rewrite gains nothing; it also reads the result right
+    # after issue, which would stall the local sort's task-id prefetch
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wno-unused-result", "-Wno-unknown-warning-option",
 ]
 

@@ -53,7 +53,7 @@ std::map<std::pair<int, hipStream_t>, BatchEngine> g_batch;
 
 bool same_tune(const Tune &a, const Tune &b) {
     return a.tile_items == b.tile_items && a.tile == b.tile && a.big == b.big && a.tiny == b.tiny &&
-           a.scatter_wg == b.scatter_wg;
+           a.scatter_wg == b.scatter_wg && a.local_wg == b.local_wg;
 }
 
 // (Re)builds the engine for at least n records and r requests: workspace,

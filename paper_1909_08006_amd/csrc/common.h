@@ -90,6 +90,7 @@ struct Tune {
     uint32_t big;          // big-bucket threshold
     uint32_t tiny;         // comparison-sort threshold inside the local sort
     uint32_t scatter_wg;   // threads per partition workgroup (256 or 512; same tile)
+    uint32_t local_wg;     // threads per local-sort workgroup (256 or 512)
 };
 
 // Device workspace views for one sort.

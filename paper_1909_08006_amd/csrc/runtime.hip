@@ -40,7 +40,7 @@ int hip_fail(hipError_t e, const char *what) {
 // parameters
 
 static std::mutex g_param_mu;
-static leyenda_params g_params = {8, 16, 2048, 32, 2048, 512};
+static leyenda_params g_params = {8, 16, 2048, 32, 2048, 512, 256};
 
 leyenda_params current_params() {
     std::lock_guard<std::mutex> lk(g_param_mu);
@@ -54,13 +54,15 @@ Tune tune_of(const leyenda_params &p) {
     t.big = p.big_threshold;
     t.tiny = p.tiny_threshold;
     t.scatter_wg = p.scatter_threads;
+    t.local_wg = p.local_threads;
     return t;
 }
 
 static bool params_ok(const leyenda_params &p) {
     return p.digit_bits == 8 && (p.tile_items == 8 || p.tile_items == 16) && p.local_capacity == kLocalCap &&
            p.big_threshold >= 1 && p.big_threshold <= p.local_capacity && p.tiny_threshold >= 1 &&
-           p.tiny_threshold <= 64 && (p.scatter_threads == 256 || p.scatter_threads == 512);
+           p.tiny_threshold <= 64 && (p.scatter_threads == 256 || p.scatter_threads == 512) &&
+           (p.local_threads == 256 || p.local_threads == 512);
 }
 
 // ---------------------------------------------------------------------------
@@ -389,6 +391,7 @@ extern "C" int leyenda_load_params(const char *json_path) {
     json_field(s, "tiny_threshold", &p.tiny_threshold);
     json_field(s, "local_capacity", &p.local_capacity);
     json_field(s, "scatter_threads", &p.scatter_threads);
+    json_field(s, "local_threads", &p.local_threads);
     return leyenda_set_params(&p);
 }
 

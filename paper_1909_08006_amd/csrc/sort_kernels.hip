@@ -75,6 +75,31 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint32_t *
     return base + below;
 }
 
+// The same stable rank, split so that the counter updates of all of a
+// thread's items issue back to back instead of one LDS round trip per item:
+// rank_issue leaves in `old` (in one lane per digit) the wave counter's value
+// before this item's keys were added, and packs the digit, the lane holding
+// `old` and the count of lower lanes with the same digit into `pk`;
+// rank_finish turns the pair into the rank.  LDS executes one wave's
+// operations in order, so items issued in key order rank in key order.
+__device__ __forceinline__ void rank_issue(uint32_t d, bool valid, uint32_t *cnt, uint32_t &old, uint32_t &pk) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRB; b++) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    const uint32_t below = __popcll(peers & lanemask_lt());
+    const uint32_t leader = valid ? (uint32_t)__builtin_ctzll(peers) : 0u;
+    old = 0;
+    if (valid && below == 0) old = atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+    pk = d | (leader << 8) | (below << 16);
+}
+__device__ __forceinline__ uint32_t rank_finish(uint32_t old, uint32_t pk) {
+    return (uint32_t)__shfl((int)old, (int)((pk >> 8) & 63u)) + (pk >> 16);
+}
+
 // Exclusive prefix sum over the workgroup's threads (one value each; NW waves).
 template <int NW = kWaves>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp /*[NW]*/) {
@@ -443,7 +468,7 @@ __global__ __launch_bounds__(kWG) void k_plan(Work w, Tune tu, int lev) {
 // WG threads, ITEMS keys each (a tile is WG * ITEMS keys); the 256 digit
 // lanes of the histogram, look-back and offsets are threads 0..255.
 template <int ITEMS, int WG>
-__global__ __launch_bounds__(WG) void k_scatter(Work w, Tune tu, int lev) {
+__global__ __launch_bounds__(WG, WG == 512 ? 2 : 1) void k_scatter(Work w, Tune tu, int lev) {
     constexpr int TILE = WG * ITEMS;
     constexpr int NW = WG / 64;
     __shared__ uint64_t sH[TILE];
@@ -475,7 +500,7 @@ __global__ __launch_bounds__(WG) void k_scatter(Work w, Tune tu, int lev) {
         const uint64_t *Ls = w.L[sg.buf] + sg.start + local0;
         for (uint32_t i = tid; i < NW * kRadix; i += WG) (&cnt[0][0])[i] = 0;
         uint64_t h[ITEMS], l[ITEMS];
-        uint32_t dg[ITEMS], rk[ITEMS];
+        uint32_t pk[ITEMS], rk[ITEMS];
 #pragma unroll
         for (int u = 0; u < ITEMS; u++) {
             const uint32_t q = wv * (ITEMS * 64) + u * 64 + lane;
@@ -487,9 +512,10 @@ __global__ __launch_bounds__(WG) void k_scatter(Work w, Tune tu, int lev) {
         for (int u = 0; u < ITEMS; u++) {
             const uint32_t q = wv * (ITEMS * 64) + u * 64 + lane;
             const bool valid = q < nvalid;
-            dg[u] = valid ? digit_at(h[u], l[u], sg.spos) : 0u;
-            rk[u] = wave_rank(dg[u], valid, cnt[wv]);
+            rank_issue(valid ? digit_at(h[u], l[u], sg.spos) : 0u, valid, cnt[wv], rk[u], pk[u]);
         }
+#pragma unroll
+        for (int u = 0; u < ITEMS; u++) rk[u] = rank_finish(rk[u], pk[u]);
         __syncthreads();
         // per-digit wave prefixes and the tile total (digit lanes: tid < 256)
         const bool dl = tid < (uint32_t)kRadix;
@@ -535,7 +561,8 @@ __global__ __launch_bounds__(WG) void k_scatter(Work w, Tune tu, int lev) {
         for (int u = 0; u < ITEMS; u++) {
             const uint32_t q = wv * (ITEMS * 64) + u * 64 + lane;
             if (q < nvalid) {
-                const uint32_t pos = lbase[dg[u]] + cnt[wv][dg[u]] + rk[u];
+                const uint32_t d = pk[u] & 0xFFu;
+                const uint32_t pos = lbase[d] + cnt[wv][d] + rk[u];
                 sH[pos] = h[u];
                 sL[pos] = l[u];
             }
@@ -587,74 +614,137 @@ __device__ __forceinline__ uint64_t wave_and64(uint64_t v) {
 
 constexpr int kStack = kLocalCap / 2;
 
-// A task read back from the device list is inside the tuple space and inside
-// its request (defence against a fired capacity guard).
-__device__ __forceinline__ bool task_ok(const Work &w, const Task &tk, uint32_t nreq) {
-    if (tk.start + tk.count > w.n || tk.buf > 1 || tk.count > kLocalCap || tk.req >= nreq) return false;
-    const Req &rq = w.reqs[tk.req];
-    return tk.start >= rq.start && tk.start + tk.count <= rq.start + rq.n;
+// Raw buffer loads: lanes whose offset lies past the end of the resource read
+// zero, so loads are issued without branches (the wait counts stay exact and
+// no lane can touch memory outside the range).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ uint32_t ufirst(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// A task descriptor made uniform across the workgroup; ok false (and count 0)
+// when it lies outside the tuple space (defence against a fired capacity guard).
+struct LTask {
+    uint64_t start;
+    uint32_t count;
+    uint32_t buf, flags, req;
+    bool ok;
+};
+
+// dw: lane k of every wave holds dword k (k < 4) of the raw descriptor
+__device__ __forceinline__ LTask task_of(const Work &w, uint32_t dw) {
+    LTask t;
+    t.start = ((uint64_t)__builtin_amdgcn_readlane(dw, 1) << 32) | __builtin_amdgcn_readlane(dw, 0);
+    t.count = __builtin_amdgcn_readlane(dw, 2);
+    const uint32_t x = __builtin_amdgcn_readlane(dw, 3);
+    t.buf = x & 0xFFu;
+    t.flags = (x >> 8) & 0xFFu;
+    t.req = x >> 16;
+    t.ok = t.start + t.count <= w.n && t.buf <= 1 && t.count <= (uint32_t)kLocalCap;
+    if (!t.ok) t.count = 0;
+    return t;
 }
 
 // Small buckets, each sorted in one workgroup's LDS; the sorted order (record
-// index per output position) goes to idx for the gather.  Task ids are taken
-// one task ahead and the next task's keys are loaded into registers while the
-// current task sorts, so global latency stays off the critical path.
-__global__ __launch_bounds__(kWG, 3) void k_local(Work w, Tune tu) {
+// index per output position) goes to idx for the gather.  Three tasks are in
+// flight per workgroup: the current one sorts in LDS while the next one's keys
+// and the one after's descriptor load, and the id after that comes from the
+// task counter.  Every global load is a branch-free buffer load issued after
+// the counter's atomic, so no wait inside the sort stalls on them.
+// Bits [pos, pos + 8) of the 112-bit tuple (the 80 key bits, then the 32-bit
+// record index), most significant bit first; pos < 112.  Tuples are unique, so
+// an order on them needs no stable partition.
+__device__ __forceinline__ uint32_t tuple_digit(uint64_t h, uint64_t l, uint32_t pos) {
+    const uint64_t l2 = l << 16;
+    uint64_t v;
+    if (pos == 0) v = h;
+    else if (pos < 64) v = (h << pos) | (l2 >> (64 - pos));
+    else v = l2 << (pos - 64);
+    return (uint32_t)(v >> 56);
+}
+
+constexpr uint64_t kLowMask48 = 0xFFFFFFFFFFFFull;
+
+// LWG threads, kLocalCap / LWG keys each; the 256 digit lanes of a partition
+// step are threads 0..255.  Keys are ordered as whole (key, index) tuples:
+// radix partitions on the tuple's first varying bit (placement inside a digit
+// is by LDS atomics, not stable) down to tiny sub-buckets, whose members are
+// placed by counting smaller tuples.
+template <int LWG, int MINB>
+__global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
+    constexpr int NW = LWG / 64;
+    constexpr int LI = kLocalCap / LWG;
     __shared__ uint64_t sH[kLocalCap];
     __shared__ uint64_t sL[kLocalCap];
     __shared__ uint32_t segb[kLocalCap];   // sub-bucket [lo, hi) per position (lo | hi << 16); then the order
-    __shared__ uint32_t cnt[kWaves][kRadix];
+    __shared__ uint32_t cnt[kRadix];
     __shared__ uint32_t lbase[kRadix];
     __shared__ uint32_t ltot[kRadix];
     __shared__ uint32_t stk[kStack];
-    __shared__ uint32_t tmp[kWaves];
-    __shared__ uint64_t orh[kWaves], andh[kWaves], orl[kWaves], andl[kWaves];
+    __shared__ uint32_t tmp[NW];
+    __shared__ uint64_t orh[NW], andh[NW], orl[NW], andl[NW];
     __shared__ int stk_n;
     __shared__ uint32_t s_next;
 
     const uint32_t ntask = min(w.ctl->ntask, w.max_tasks);
     const uint32_t nreq = w.hdr->nreq;
     const uint32_t tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const __amdgpu_buffer_rsrc_t r_tasks = rsrc_of(w.tasks, ntask * (uint32_t)sizeof(Task));
+    const __amdgpu_buffer_rsrc_t r_reqs = rsrc_of(w.reqs, nreq * (uint32_t)sizeof(Req));
 
-    // the next task: descriptor and keys in registers (striped, q = u * kWG + tid),
-    // loaded while the current task sorts
-    uint64_t ph[kLocalItems], pl[kLocalItems];
-    Task tk{};
-    bool ok = false;
-    auto fetch = [&](uint32_t jn) {
-        ok = false;
-        if (jn < ntask) {
-            tk = w.tasks[jn];
-            ok = task_ok(w, tk, nreq);
-            if (!ok && tid == 0) atomicOr(&w.ctl->guard, 64u);
-        }
-        const uint32_t c = ok ? tk.count : 0u;
-        const uint64_t *Hs = w.H[tk.buf & 1] + tk.start;
-        const uint64_t *Ls = w.L[tk.buf & 1] + tk.start;
+    uint64_t ph[LI], pl[LI];  // keys of the task after the current one
+    uint32_t nd;              // raw descriptor of the task after that (dword lane & 3)
+    uint32_t rq;              // (start, n) of the request of the keys in flight (dword lane & 3)
+    auto issue_keys = [&](const LTask &t) {
+        const __amdgpu_buffer_rsrc_t rh = rsrc_of(w.H[t.buf & 1] + t.start, t.count * 8u);
+        const __amdgpu_buffer_rsrc_t rl = rsrc_of(w.L[t.buf & 1] + t.start, t.count * 8u);
 #pragma unroll
-        for (int u = 0; u < kLocalItems; u++) {
-            const uint32_t q = u * kWG + tid;
-            ph[u] = 0; pl[u] = 0;
-            if (q < c) { ph[u] = Hs[q]; pl[u] = Ls[q]; }
+        for (int u = 0; u < LI; u++) {
+            const uint32_t q = u * LWG + tid;
+            const auto vh = __builtin_amdgcn_raw_buffer_load_b64(rh, q * 8u, 0, 0);
+            const auto vl = __builtin_amdgcn_raw_buffer_load_b64(rl, q * 8u, 0, 0);
+            ph[u] = ((uint64_t)vh[1] << 32) | vh[0];
+            pl[u] = ((uint64_t)vl[1] << 32) | vl[0];
         }
+        rq = __builtin_amdgcn_raw_buffer_load_b32(r_reqs, t.req * (uint32_t)sizeof(Req) + 16u + (lane & 3u) * 4u, 0, 0);
+    };
+    auto issue_desc = [&](uint32_t id) {
+        nd = __builtin_amdgcn_raw_buffer_load_b32(r_tasks, id * (uint32_t)sizeof(Task) + (lane & 3u) * 4u, 0, 0);
     };
 
+    // prologue: the first task's descriptor and keys, the second's descriptor,
+    // the third's id
     if (tid == 0) s_next = atomicAdd(&w.ctl->task_ctr, 1u);
     __syncthreads();
-    uint32_t j = s_next;
-    fetch(j);
+    uint32_t j = ufirst(s_next);
+    if (j >= ntask) return;
+    issue_desc(j);
+    LTask cur = task_of(w, nd);
+    issue_keys(cur);
     __syncthreads();
-    if (tid == 0) s_next = atomicAdd(&w.ctl->task_ctr, 1u);  // one task ahead
+    if (tid == 0) s_next = atomicAdd(&w.ctl->task_ctr, 1u);
+    __syncthreads();
+    uint32_t jn = ufirst(s_next);
+    issue_desc(jn);
+    __syncthreads();
+    if (tid == 0) s_next = atomicAdd(&w.ctl->task_ctr, 1u);
+    __syncthreads();
+    LTask nxt = task_of(w, nd);
+
     while (j < ntask) {
-        const bool cur_ok = ok;
-        const Task cur = tk;
+        // the current task: inside its request (the request bounds came with its keys)
+        const uint64_t rs = ((uint64_t)__builtin_amdgcn_readlane(rq, 1) << 32) | __builtin_amdgcn_readlane(rq, 0);
+        const uint64_t rn = ((uint64_t)__builtin_amdgcn_readlane(rq, 3) << 32) | __builtin_amdgcn_readlane(rq, 2);
+        const bool cur_ok = cur.ok && cur.req < nreq && cur.start >= rs && cur.start + cur.count <= rs + rn;
+        if (!cur_ok && tid == 0) atomicOr(&w.ctl->guard, 64u);
         const uint32_t m = cur_ok ? cur.count : 0u;
         const bool sorted = (cur.flags & kTaskSorted) || m <= 1;
         // the task's keys into LDS, with the key masks of the whole task
         uint64_t th = 0, tah = ~0ull, tl = 0, tal = ~0ull;
 #pragma unroll
-        for (int u = 0; u < kLocalItems; u++) {
-            const uint32_t q = u * kWG + tid;
+        for (int u = 0; u < LI; u++) {
+            const uint32_t q = u * LWG + tid;
             if (q < m) {
                 if (sorted) {
                     segb[q] = (uint32_t)pl[u];
@@ -662,7 +752,7 @@ __global__ __launch_bounds__(kWG, 3) void k_local(Work w, Tune tu) {
                     sH[q] = ph[u];
                     sL[q] = pl[u];
                     segb[q] = q | ((q + 1) << 16);
-                    const uint64_t kk = (pl[u] >> 32) & 0xFFFFu;
+                    const uint64_t kk = pl[u] & kLowMask48;
                     th |= ph[u]; tah &= ph[u]; tl |= kk; tal &= kk;
                 }
             }
@@ -674,11 +764,14 @@ __global__ __launch_bounds__(kWG, 3) void k_local(Work w, Tune tu) {
             stk[0] = 0u | (m << 16);
             stk_n = sorted ? 0 : 1;
         }
+        // the id three tasks ahead (consumed after the sort), then the next
+        // task's keys, then the descriptor of the one after
+        uint32_t ahead = 0;
+        if (tid == 0) ahead = atomicAdd(&w.ctl->task_ctr, 1u);
+        issue_keys(nxt);
         __syncthreads();
-        const uint32_t jn = s_next;
-        fetch(jn);  // the next task's keys load while this one sorts
-        __syncthreads();
-        if (tid == 0) s_next = atomicAdd(&w.ctl->task_ctr, 1u);
+        const uint32_t jnn = ufirst(s_next);
+        issue_desc(jnn);
         bool top = true;
         for (;;) {
             const int nst = min(stk_n, kStack);
@@ -690,8 +783,8 @@ __global__ __launch_bounds__(kWG, 3) void k_local(Work w, Tune tu) {
             // which key bits vary over [a, a + len) (for the whole task: from the load)
             if (!top) {
                 uint64_t oh = 0, ah = ~0ull, ol = 0, al = ~0ull;
-                for (uint32_t q = a + tid; q < a + len; q += kWG) {
-                    const uint64_t hh = sH[q], kk = (sL[q] >> 32) & 0xFFFFu;
+                for (uint32_t q = a + tid; q < a + len; q += LWG) {
+                    const uint64_t hh = sH[q], kk = sL[q] & kLowMask48;
                     oh |= hh; ah &= hh; ol |= kk; al &= kk;
                 }
                 oh = wave_or64(oh); ah = wave_and64(ah);
@@ -702,35 +795,32 @@ __global__ __launch_bounds__(kWG, 3) void k_local(Work w, Tune tu) {
             top = false;
             uint64_t OH = 0, AH = ~0ull, OL = 0, AL = ~0ull;
 #pragma unroll
-            for (int k2 = 0; k2 < kWaves; k2++) { OH |= orh[k2]; AH &= andh[k2]; OL |= orl[k2]; AL &= andl[k2]; }
-            const uint64_t vh = OH ^ AH, vl = (OL ^ AL) & 0xFFFFu;
-            if (vh == 0 && vl == 0) continue;  // equal keys: already in index order
-            const uint32_t f = vh ? (uint32_t)__clzll(vh) : 64u + ((uint32_t)__clz((uint32_t)vl) - 16u);
-            // stable partition of [a, a + len) by the digit at bit f
-            cnt[0][tid] = 0; cnt[1][tid] = 0; cnt[2][tid] = 0; cnt[3][tid] = 0;
+            for (int k2 = 0; k2 < NW; k2++) { OH |= orh[k2]; AH &= andh[k2]; OL |= orl[k2]; AL &= andl[k2]; }
+            const uint64_t vh = OH ^ AH, vl = (OL ^ AL) & kLowMask48;
+            if (vh == 0 && vl == 0) continue;  // a single tuple
+            const uint32_t f = vh ? (uint32_t)__clzll(vh) : 64u + ((uint32_t)__clzll(vl) - 16u);
+            // partition of [a, a + len) by the tuple digit at bit f
+            const bool dl = tid < (uint32_t)kRadix;
+            if (dl) cnt[tid] = 0;
             __syncthreads();
-            uint64_t h[kLocalItems], l[kLocalItems];
-            uint32_t dg[kLocalItems], rk[kLocalItems];
+            uint64_t h[LI], l[LI];
+            uint32_t dg[LI], rk[LI];
 #pragma unroll
-            for (int u = 0; u < kLocalItems; u++) {
-                const uint32_t i = wv * (kLocalItems * 64) + u * 64 + lane;
+            for (int u = 0; u < LI; u++) {
+                const uint32_t i = u * LWG + tid;
                 const bool valid = i < len;
                 h[u] = valid ? sH[a + i] : 0ull;
                 l[u] = valid ? sL[a + i] : 0ull;
-                dg[u] = valid ? digit_at(h[u], l[u], f) : 0u;
-                rk[u] = wave_rank(dg[u], valid, cnt[wv]);
+                dg[u] = tuple_digit(h[u], l[u], f);
+                rk[u] = valid ? atomicAdd(&cnt[dg[u]], 1u) : 0u;
             }
             __syncthreads();
-            uint32_t tot = 0;
-#pragma unroll
-            for (int k2 = 0; k2 < kWaves; k2++) {
-                const uint32_t cj = cnt[k2][tid];
-                cnt[k2][tid] = tot;
-                tot += cj;
+            const uint32_t tot = dl ? cnt[tid] : 0u;
+            const uint32_t lb = block_excl_scan<NW>(tot, tmp);
+            if (dl) {
+                lbase[tid] = lb;
+                ltot[tid] = tot;
             }
-            const uint32_t lb = block_excl_scan(tot, tmp);
-            lbase[tid] = lb;
-            ltot[tid] = tot;
             if (tot > tu.tiny) {
                 const int slot = atomicAdd(&stk_n, 1);
                 if (slot < kStack) stk[slot] = (a + lb) | (tot << 16);
@@ -738,11 +828,11 @@ __global__ __launch_bounds__(kWG, 3) void k_local(Work w, Tune tu) {
             }
             __syncthreads();
 #pragma unroll
-            for (int u = 0; u < kLocalItems; u++) {
-                const uint32_t i = wv * (kLocalItems * 64) + u * 64 + lane;
+            for (int u = 0; u < LI; u++) {
+                const uint32_t i = u * LWG + tid;
                 if (i < len) {
                     const uint32_t d = dg[u];
-                    const uint32_t np = a + lbase[d] + cnt[wv][d] + rk[u];
+                    const uint32_t np = a + lbase[d] + rk[u];
                     sH[np] = h[u];
                     sL[np] = l[u];
                     const uint32_t c = ltot[d];
@@ -754,10 +844,10 @@ __global__ __launch_bounds__(kWG, 3) void k_local(Work w, Tune tu) {
         }
         if (!sorted) {
             // tiny sub-buckets: position = sub-bucket start + number of smaller tuples
-            uint32_t fv[kLocalItems], iv[kLocalItems];
+            uint32_t fv[LI], iv[LI];
 #pragma unroll
-            for (int u = 0; u < kLocalItems; u++) {
-                const uint32_t q = u * kWG + tid;
+            for (int u = 0; u < LI; u++) {
+                const uint32_t q = u * LWG + tid;
                 fv[u] = q; iv[u] = 0;
                 if (q < m) {
                     const uint32_t sb = segb[q], lo = sb & 0xFFFFu, hi = min(sb >> 16, m);
@@ -775,18 +865,30 @@ __global__ __launch_bounds__(kWG, 3) void k_local(Work w, Tune tu) {
             }
             __syncthreads();
 #pragma unroll
-            for (int u = 0; u < kLocalItems; u++) {
-                const uint32_t q = u * kWG + tid;
+            for (int u = 0; u < LI; u++) {
+                const uint32_t q = u * LWG + tid;
                 if (q < m) segb[fv[u]] = iv[u];
             }
         }
         __syncthreads();
-        if (cur_ok) {
-            uint32_t *out = w.idx + cur.start;
-            for (uint32_t q = tid; q < m; q += kWG) out[q] = segb[q];
+        // the descriptor and id loads of this round have landed (issued before
+        // the sort); take them before the stores so no later wait counts stores
+        const LTask after = task_of(w, nd);
+        if (tid == 0) s_next = ahead;  // every thread read s_next before the sort's first barrier
+        {
+            // a fixed number of stores per thread; lanes past m are dropped
+            const __amdgpu_buffer_rsrc_t ro = rsrc_of(w.idx + cur.start, m * 4u);
+#pragma unroll
+            for (int u = 0; u < LI; u++) {
+                const uint32_t q = u * LWG + tid;
+                __builtin_amdgcn_raw_buffer_store_b32(segb[q], ro, q * 4u, 0, 0);
+            }
         }
-        __syncthreads();  // segb and the mask slots are reused by the next task
+        __syncthreads();  // segb, s_next and the mask slots are reused by the next task
+        cur = nxt;
+        nxt = after;
         j = jn;
+        jn = jnn;
     }
 }
 
@@ -907,7 +1009,7 @@ static int occupancy(const void *fn, int cus, int wg = kWG) {
     return per * cus;
 }
 
-template <int ITEMS, int SWG>
+template <int ITEMS, int SWG, int LWG>
 static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
                                 hipStream_t s, int cus, hipEvent_t *ev) {
     // nreq / tiles0 == 0: sizes known only on the device (captured sequences)
@@ -920,7 +1022,7 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
     if (!g_sc) {
         g_sc = occupancy(reinterpret_cast<const void *>(&k_scatter<SITEMS, SWG>), cus, SWG);
         g_hist = occupancy(reinterpret_cast<const void *>(&k_hist<ITEMS>), cus);
-        g_loc = occupancy(reinterpret_cast<const void *>(&k_local), cus);
+        g_loc = occupancy(reinterpret_cast<const void *>(&k_local<LWG, LWG == 512 ? 2 : 3>), cus, LWG);
     }
     const int g_plan = cus * 4;
     for (int lev = 0; lev < kMaxLev; lev++) {
@@ -929,18 +1031,24 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
         k_scatter<SITEMS, SWG><<<dim3(g_sc), dim3(SWG), 0, s>>>(w, t, lev);
     }
     if (ev) (void)hipEventRecord(ev[1], s);
-    k_local<<<dim3(g_loc), dim3(kWG), 0, s>>>(w, t);
+    k_local<LWG, LWG == 512 ? 2 : 3><<<dim3(g_loc), dim3(LWG), 0, s>>>(w, t);
     if (ev) (void)hipEventRecord(ev[2], s);
     return hipGetLastError();
 }
 
 hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0, hipStream_t s,
                             int cus, hipEvent_t *ev) {
-    if (t.tile_items == 8)
-        return t.scatter_wg == 512 ? launch_levels<8, 512>(w, t, nreq, tiles0, s, cus, ev)
-                                   : launch_levels<8, 256>(w, t, nreq, tiles0, s, cus, ev);
-    return t.scatter_wg == 512 ? launch_levels<16, 512>(w, t, nreq, tiles0, s, cus, ev)
-                               : launch_levels<16, 256>(w, t, nreq, tiles0, s, cus, ev);
+    const int v = (t.tile_items == 8 ? 4 : 0) | (t.scatter_wg == 512 ? 2 : 0) | (t.local_wg == 512 ? 1 : 0);
+    switch (v) {
+    case 0: return launch_levels<16, 256, 256>(w, t, nreq, tiles0, s, cus, ev);
+    case 1: return launch_levels<16, 256, 512>(w, t, nreq, tiles0, s, cus, ev);
+    case 2: return launch_levels<16, 512, 256>(w, t, nreq, tiles0, s, cus, ev);
+    case 3: return launch_levels<16, 512, 512>(w, t, nreq, tiles0, s, cus, ev);
+    case 4: return launch_levels<8, 256, 256>(w, t, nreq, tiles0, s, cus, ev);
+    case 5: return launch_levels<8, 256, 512>(w, t, nreq, tiles0, s, cus, ev);
+    case 6: return launch_levels<8, 512, 256>(w, t, nreq, tiles0, s, cus, ev);
+    default: return launch_levels<8, 512, 512>(w, t, nreq, tiles0, s, cus, ev);
+    }
 }
 
 hipError_t launch_gather_batch(const Work &w, hipStream_t s, int cus, hipEvent_t done) {
