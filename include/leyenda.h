@@ -192,8 +192,8 @@ int leyenda_serve_replay(const leyenda_server_config *cfg, uint64_t count, const
 /* ---------------------------------------------------------------------------
  * Tuning parameters.  They change speed only, never the output bytes.
  * digit_bits     radix digit width in bits (8: 256 buckets per pass, Algorithm 1).
- * tile_items     keys per thread in a device-wide partition tile (8 or 16; a
- *                tile is 256 * tile_items keys).
+ * tile_items     keys per thread in a device-wide partition tile (8, 16 or 32;
+ *                a tile is 256 * tile_items keys).
  * big_threshold  buckets with more keys than this get another device-wide
  *                partition pass (Algorithm 1's bigBucketThreshold);
  *                1 <= big_threshold <= local_capacity.
@@ -201,8 +201,8 @@ int leyenda_serve_replay(const leyenda_server_config *cfg, uint64_t count, const
  *                ordered by comparisons instead of another radix partition
  *                (Algorithm 1's tinyBucketThreshold); 1..64.
  * local_capacity keys one workgroup sorts in LDS (2048).
- * scatter_threads threads per device-wide partition workgroup (256 or 512;
- *                the tile stays 256 * tile_items keys).
+ * scatter_threads threads per device-wide partition workgroup (256, 512 or
+ *                1024; the tile stays 256 * tile_items keys).
  * local_threads  threads per local-sort workgroup (256 or 512).
  * ------------------------------------------------------------------------- */
 typedef struct {

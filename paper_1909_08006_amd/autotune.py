@@ -25,10 +25,10 @@ if ROOT not in sys.path:
 
 DEFAULT_SPACE = {
     "digit_bits": [8],
-    "tile_items": [8, 16],
-    "big_threshold": [512, 1024, 2048],
+    "tile_items": [16, 32],
+    "big_threshold": [1024, 2048],
     "tiny_threshold": [16, 32, 64],
-    "scatter_threads": [256, 512],
+    "scatter_threads": [512, 1024],
     "local_threads": [256, 512],
 }
 

@@ -85,11 +85,11 @@ struct Hdr {
 
 // Runtime tuning values the kernels read.
 struct Tune {
-    uint32_t tile_items;   // 8 or 16
+    uint32_t tile_items;   // 8, 16 or 32
     uint32_t tile;         // kWG * tile_items
     uint32_t big;          // big-bucket threshold
     uint32_t tiny;         // comparison-sort threshold inside the local sort
-    uint32_t scatter_wg;   // threads per partition workgroup (256 or 512; same tile)
+    uint32_t scatter_wg;   // threads per partition workgroup (256, 512 or 1024; same tile)
     uint32_t local_wg;     // threads per local-sort workgroup (256 or 512)
 };
 

@@ -120,6 +120,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp /*
 }
 
 constexpr uint32_t kSpinLimit = 1u << 24;
+constexpr int kLookWin = 8;  // predecessor tiles read per look-back step
 
 // A segment read back from a device table is inside the tuple space and owns
 // the tile that points at it (defence against a fired capacity guard).
@@ -180,6 +181,74 @@ __device__ void new_segment(const Work &w, const Tune &tu, int lev, uint64_t sta
     w.segs[lev & 1][s] = g;
 }
 
+// new_segment for every thread of the workgroup with `need` set, with one
+// atomic per counter for the whole workgroup (the counters of a level are
+// shared by all buckets, so per-child atomics would serialize).  Whole
+// workgroup.
+__device__ void new_segments_block(const Work &w, const Tune &tu, int lev, bool need, uint64_t start,
+                                   uint32_t count, uint32_t pos, uint8_t buf, uint16_t req) {
+    __shared__ uint32_t ns_tmp[kWaves];
+    __shared__ uint32_t ns_tot[3], ns_base[3];
+    const uint32_t nt = need ? (count + tu.tile - 1) / tu.tile : 0u;
+    const uint32_t nr = min(nt, (uint32_t)kMaxRep);
+    const uint32_t es = block_excl_scan(need ? 1u : 0u, ns_tmp);
+    const uint32_t et = block_excl_scan(nt, ns_tmp);
+    const uint32_t er = block_excl_scan(nr, ns_tmp);
+    if (threadIdx.x == kWG - 1) {
+        ns_tot[0] = es + (need ? 1u : 0u);
+        ns_tot[1] = et + nt;
+        ns_tot[2] = er + nr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ns_base[0] = ns_tot[0] ? atomicAdd(&w.ctl->nseg[lev], ns_tot[0]) : 0u;
+        ns_base[1] = ns_tot[1] ? atomicAdd(&w.ctl->ntiles[lev], ns_tot[1]) : 0u;
+        ns_base[2] = ns_tot[2] ? atomicAdd(&w.ctl->rep_ctr[lev], ns_tot[2]) : 0u;
+    }
+    __syncthreads();
+    if (need) {
+        const uint32_t s = ns_base[0] + es, ft = ns_base[1] + et, rf = ns_base[2] + er;
+        if (s >= w.max_seg || (uint64_t)ft + nt > w.max_tiles || (uint64_t)rf + nr > w.max_reps) {
+            atomicOr(&w.ctl->guard, 4u);
+            if (s < w.max_seg) {  // leave a harmless entry: no tiles, nothing to zero
+                Seg g{};
+                g.spos = kNoScatter;
+                w.segs[lev & 1][s] = g;
+            }
+        } else {
+            Seg g;
+            g.start = start; g.count = count; g.first_tile = ft; g.ntiles = nt; g.rep_first = rf;
+            g.nrep = (uint8_t)nr; g.pos = (uint16_t)pos; g.spos = kNoScatter; g.buf = buf; g.req = req;
+            w.segs[lev & 1][s] = g;
+        }
+    }
+}
+
+// Sums the nrep histogram replicas of a bucket for digit lane d (and ORs the
+// key masks for d < 4), eight loads in flight per thread.
+__device__ __forceinline__ uint32_t reduce_replicas(const uint32_t *rp, uint32_t nrep, uint32_t d,
+                                                    unsigned long long *mask_out) {
+    uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const bool dm = d < 4;
+    uint32_t r = 0;
+    for (; r + 8 <= nrep; r += 8) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const uint32_t *q = rp + (size_t)(r + k) * kRepWords;
+            acc[k] += q[d];
+            if (dm) m[k] |= reinterpret_cast<const unsigned long long *>(q + kRadix)[d];
+        }
+    }
+    for (; r < nrep; r++) {
+        const uint32_t *q = rp + (size_t)r * kRepWords;
+        acc[0] += q[d];
+        if (dm) m[0] |= reinterpret_cast<const unsigned long long *>(q + kRadix)[d];
+    }
+    if (dm) *mask_out = m[0] | m[1] | m[2] | m[3] | m[4] | m[5] | m[6] | m[7];
+    return acc[0] + acc[1] + acc[2] + acc[3] + acc[4] + acc[5] + acc[6] + acc[7];
+}
+
 // First key bit that differs between keys of a bucket, from its OR and
 // OR-of-complement masks; kKeyBits if every key is equal.
 __device__ __forceinline__ uint32_t first_varying(uint64_t orh, uint64_t ornh, uint64_t orl, uint64_t ornl) {
@@ -215,14 +284,9 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
         return;
     }
     uint32_t *rp = w.rep[lev & 1] + (size_t)sg.rep_first * kRepWords;
-    uint32_t cnt = 0;
-    for (uint32_t r = 0; r < sg.nrep; r++) cnt += rp[(size_t)r * kRepWords + d];
-    if (d < 4) {
-        unsigned long long m = 0;
-        for (uint32_t r = 0; r < sg.nrep; r++)
-            m |= reinterpret_cast<const unsigned long long *>(rp + (size_t)r * kRepWords + kRadix)[d];
-        p_mask[d] = m;
-    }
+    unsigned long long m = 0;
+    const uint32_t cnt = reduce_replicas(rp, sg.nrep, d, &m);
+    if (d < 4) p_mask[d] = m;
     const int isconst = __syncthreads_or(cnt == sg.count);
     if (isconst) {  // digit at pos is constant over the bucket: skip ahead without moving data
         if (d == 0) {
@@ -244,10 +308,8 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
     }
     const uint8_t cbuf = sg.buf ^ 1;
     const uint32_t cpos = p + kRB;
-    if (cnt > tu.big) {
-        if (cpos < kKeyBits) new_segment(w, tu, lev + 1, sg.start + base, cnt, cpos, cbuf, sg.req);
-        else emit_sorted(w, sg.start + base, cnt, cbuf, sg.req);  // all 80 key bits fixed: equal keys
-    }
+    if (cnt > tu.big && cpos >= kKeyBits) emit_sorted(w, sg.start + base, cnt, cbuf, sg.req);  // equal keys
+    new_segments_block(w, tu, lev + 1, cnt > tu.big && cpos < kKeyBits, sg.start + base, cnt, cpos, cbuf, sg.req);
     __syncthreads();
     if (d == 0) {  // pack consecutive small buckets into tasks of at most kLocalCap keys
         uint32_t nt = 0, cur_start = 0, cur = 0;
@@ -343,6 +405,7 @@ __global__ __launch_bounds__(kWG) void k_init(Work w) {
 
 template <int ITEMS>
 __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
+    constexpr int RI = ITEMS > 16 ? 16 : ITEMS;
     __shared__ uint32_t sh[kRadix];
     __shared__ unsigned long long smask[4];
     const uint32_t ntiles = min(w.ctl->ntiles[0], w.max_tiles);
@@ -359,28 +422,31 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
         const uint64_t local0 = (uint64_t)(tile - sg.first_tile) * tu.tile;
         const uint32_t nvalid = (uint32_t)min<uint64_t>(tu.tile, sg.count - local0);
         __syncthreads();
-        uint32_t a[ITEMS], b[ITEMS], c[ITEMS];
-#pragma unroll
-        for (int u = 0; u < ITEMS; u++) {
-            const uint32_t q = u * kWG + threadIdx.x;
-            if (q < nvalid) {
-                const uint32_t *p = reinterpret_cast<const uint32_t *>(rq.in + (local0 + q) * kRec);
-                a[u] = p[0]; b[u] = p[1]; c[u] = p[2];
-            }
-        }
         uint64_t *H = w.H[0] + sg.start + local0;
         uint64_t *L = w.L[0] + sg.start + local0;
         uint64_t oh = 0, onh = 0, ol = 0, onl = 0;
+#pragma unroll 1
+        for (int r0 = 0; r0 < ITEMS; r0 += RI) {  // RI keys per thread in flight
+            uint32_t a[RI], b[RI], c[RI];
 #pragma unroll
-        for (int u = 0; u < ITEMS; u++) {
-            const uint32_t q = u * kWG + threadIdx.x;
-            if (q < nvalid) {
-                const uint64_t h = __builtin_bswap64(((uint64_t)b[u] << 32) | a[u]);
-                const uint64_t k16 = __builtin_bswap16((uint16_t)(c[u] & 0xFFFFu));
-                H[q] = h;
-                L[q] = (k16 << 32) | (uint32_t)(local0 + q);
-                atomicAdd(&sh[h >> 56], 1u);
-                oh |= h; onh |= ~h; ol |= k16; onl |= (~k16) & 0xFFFFu;
+            for (int u = 0; u < RI; u++) {
+                const uint32_t q = (r0 + u) * kWG + threadIdx.x;
+                if (q < nvalid) {
+                    const uint32_t *p = reinterpret_cast<const uint32_t *>(rq.in + (local0 + q) * kRec);
+                    a[u] = p[0]; b[u] = p[1]; c[u] = p[2];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < RI; u++) {
+                const uint32_t q = (r0 + u) * kWG + threadIdx.x;
+                if (q < nvalid) {
+                    const uint64_t h = __builtin_bswap64(((uint64_t)b[u] << 32) | a[u]);
+                    const uint64_t k16 = __builtin_bswap16((uint16_t)(c[u] & 0xFFFFu));
+                    H[q] = h;
+                    L[q] = (k16 << 32) | (uint32_t)(local0 + q);
+                    atomicAdd(&sh[h >> 56], 1u);
+                    oh |= h; onh |= ~h; ol |= k16; onl |= (~k16) & 0xFFFFu;
+                }
             }
         }
         block_masks(oh, onh, ol, onl, smask);
@@ -395,6 +461,7 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
 
 template <int ITEMS>
 __global__ __launch_bounds__(kWG) void k_hist(Work w, Tune tu, int lev) {
+    constexpr int RI = ITEMS > 16 ? 16 : ITEMS;
     __shared__ uint32_t sh[kRadix];
     __shared__ unsigned long long smask[4];
     const uint32_t ntiles = min(w.ctl->ntiles[lev], w.max_tiles);
@@ -420,26 +487,29 @@ __global__ __launch_bounds__(kWG) void k_hist(Work w, Tune tu, int lev) {
         // moves on to bit 64 and the next level reads them
         const bool needL = sg.pos + kRB > 64;
         __syncthreads();
-        uint64_t h[ITEMS], l[ITEMS];
-#pragma unroll
-        for (int u = 0; u < ITEMS; u++) {
-            const uint32_t q = u * kWG + threadIdx.x;
-            h[u] = 0; l[u] = 0;
-            if (q < nvalid) {
-                h[u] = H[q];
-                if (needL) l[u] = L[q];
-            }
-        }
         uint64_t oh = 0, onh = 0, ol = needL ? 0 : 0xFFFFu, onl = needL ? 0 : 0xFFFFu;
+#pragma unroll 1
+        for (int r0 = 0; r0 < ITEMS; r0 += RI) {  // RI keys per thread in flight
+            uint64_t h[RI], l[RI];
 #pragma unroll
-        for (int u = 0; u < ITEMS; u++) {
-            const uint32_t q = u * kWG + threadIdx.x;
-            if (q < nvalid) {
-                atomicAdd(&sh[digit_at(h[u], l[u], sg.pos)], 1u);
-                oh |= h[u]; onh |= ~h[u];
-                if (needL) {
-                    const uint64_t k16 = (l[u] >> 32) & 0xFFFFu;
-                    ol |= k16; onl |= (~k16) & 0xFFFFu;
+            for (int u = 0; u < RI; u++) {
+                const uint32_t q = (r0 + u) * kWG + threadIdx.x;
+                h[u] = 0; l[u] = 0;
+                if (q < nvalid) {
+                    h[u] = H[q];
+                    if (needL) l[u] = L[q];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < RI; u++) {
+                const uint32_t q = (r0 + u) * kWG + threadIdx.x;
+                if (q < nvalid) {
+                    atomicAdd(&sh[digit_at(h[u], l[u], sg.pos)], 1u);
+                    oh |= h[u]; onh |= ~h[u];
+                    if (needL) {
+                        const uint64_t k16 = (l[u] >> 32) & 0xFFFFu;
+                        ol |= k16; onl |= (~k16) & 0xFFFFu;
+                    }
                 }
             }
         }
@@ -468,7 +538,7 @@ __global__ __launch_bounds__(kWG) void k_plan(Work w, Tune tu, int lev) {
 // WG threads, ITEMS keys each (a tile is WG * ITEMS keys); the 256 digit
 // lanes of the histogram, look-back and offsets are threads 0..255.
 template <int ITEMS, int WG>
-__global__ __launch_bounds__(WG, WG == 512 ? 2 : 1) void k_scatter(Work w, Tune tu, int lev) {
+__global__ __launch_bounds__(WG, WG >= 512 ? 4 : 2) void k_scatter(Work w, Tune tu, int lev) {
     constexpr int TILE = WG * ITEMS;
     constexpr int NW = WG / 64;
     __shared__ uint64_t sH[TILE];
@@ -500,7 +570,7 @@ __global__ __launch_bounds__(WG, WG == 512 ? 2 : 1) void k_scatter(Work w, Tune 
         const uint64_t *Ls = w.L[sg.buf] + sg.start + local0;
         for (uint32_t i = tid; i < NW * kRadix; i += WG) (&cnt[0][0])[i] = 0;
         uint64_t h[ITEMS], l[ITEMS];
-        uint32_t pk[ITEMS], rk[ITEMS];
+        uint32_t pk[ITEMS];  // digit | rank in the wave's digit << 8
 #pragma unroll
         for (int u = 0; u < ITEMS; u++) {
             const uint32_t q = wv * (ITEMS * 64) + u * 64 + lane;
@@ -508,14 +578,17 @@ __global__ __launch_bounds__(WG, WG == 512 ? 2 : 1) void k_scatter(Work w, Tune 
             if (q < nvalid) { h[u] = Hs[q]; l[u] = Ls[q]; }
         }
         __syncthreads();
+        {
+            uint32_t old[ITEMS];
 #pragma unroll
-        for (int u = 0; u < ITEMS; u++) {
-            const uint32_t q = wv * (ITEMS * 64) + u * 64 + lane;
-            const bool valid = q < nvalid;
-            rank_issue(valid ? digit_at(h[u], l[u], sg.spos) : 0u, valid, cnt[wv], rk[u], pk[u]);
+            for (int u = 0; u < ITEMS; u++) {
+                const uint32_t q = wv * (ITEMS * 64) + u * 64 + lane;
+                const bool valid = q < nvalid;
+                rank_issue(valid ? digit_at(h[u], l[u], sg.spos) : 0u, valid, cnt[wv], old[u], pk[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < ITEMS; u++) pk[u] = (pk[u] & 0xFFu) | (rank_finish(old[u], pk[u]) << 8);
         }
-#pragma unroll
-        for (int u = 0; u < ITEMS; u++) rk[u] = rank_finish(rk[u], pk[u]);
         __syncthreads();
         // per-digit wave prefixes and the tile total (digit lanes: tid < 256)
         const bool dl = tid < (uint32_t)kRadix;
@@ -528,44 +601,56 @@ __global__ __launch_bounds__(WG, WG == 512 ? 2 : 1) void k_scatter(Work w, Tune 
                 tot += cj;
             }
         }
-        // decoupled look-back over earlier tiles of the same bucket
+        // this tile's digit counts are known: publish them for later tiles first
         unsigned long long *st = w.status + (size_t)tile * kRadix + (dl ? tid : 0u);
-        unsigned long long excl = 0;
-        if (!dl) {
-        } else if (k == 0) {
-            st_agent(st, kFlagInc | tot);
-        } else {
-            st_agent(st, kFlagAgg | tot);
-            uint32_t spins = 0;
-            for (uint32_t tt = tile - 1; tt >= sg.first_tile; tt--) {
-                const unsigned long long *sp = w.status + (size_t)tt * kRadix + tid;
-                unsigned long long v;
-                while (((v = ld_agent(sp)) >> 62) == 0 && spins < kSpinLimit) {
-                    __builtin_amdgcn_s_sleep(1);
-                    spins++;
-                }
-                if (spins >= kSpinLimit) { atomicOr(&w.ctl->guard, 16u); break; }
-                excl += v & kCountMask;
-                if ((v & kFlagInc) || tt == sg.first_tile) break;
-            }
-            st_agent(st, kFlagInc | (excl + tot));
-        }
+        if (dl) st_agent(st, (k == 0 ? kFlagInc : kFlagAgg) | tot);
         const uint32_t lb = block_excl_scan<NW>(tot, tmp);
-        if (dl) {
-            const uint32_t bb = w.rep[lev & 1][(size_t)sg.rep_first * kRepWords + tid];
-            lbase[tid] = lb;
-            gbase[tid] = sg.start + bb + excl - lb;
-        }
+        if (dl) lbase[tid] = lb;
         __syncthreads();
+        // keys to their place in the tile (digit-major), freeing their registers
 #pragma unroll
         for (int u = 0; u < ITEMS; u++) {
             const uint32_t q = wv * (ITEMS * 64) + u * 64 + lane;
             if (q < nvalid) {
                 const uint32_t d = pk[u] & 0xFFu;
-                const uint32_t pos = lbase[d] + cnt[wv][d] + rk[u];
+                const uint32_t pos = lbase[d] + cnt[wv][d] + (pk[u] >> 8);
                 sH[pos] = h[u];
                 sL[pos] = l[u];
             }
+        }
+        // decoupled look-back over earlier tiles of the same bucket, kLookWin
+        // predecessors at a time: their flags load together, so a walk over
+        // aggregates costs one round trip per window
+        unsigned long long excl = 0;
+        if (dl && k > 0) {
+            uint32_t spins = 0;
+            bool done = false;
+            for (uint32_t t0 = tile - 1; !done;) {
+                unsigned long long v[kLookWin];
+#pragma unroll
+                for (int k2 = 0; k2 < kLookWin; k2++)
+                    v[k2] = (t0 >= sg.first_tile + k2) ? ld_agent(w.status + (size_t)(t0 - k2) * kRadix + tid) : 0ull;
+#pragma unroll
+                for (int k2 = 0; k2 < kLookWin; k2++) {
+                    if (done) break;
+                    const uint32_t tt = t0 - k2;
+                    const unsigned long long *sp = w.status + (size_t)tt * kRadix + tid;
+                    while ((v[k2] >> 62) == 0 && spins < kSpinLimit) {
+                        __builtin_amdgcn_s_sleep(1);
+                        spins++;
+                        v[k2] = ld_agent(sp);
+                    }
+                    if (spins >= kSpinLimit) { atomicOr(&w.ctl->guard, 16u); done = true; break; }
+                    excl += v[k2] & kCountMask;
+                    if ((v[k2] & kFlagInc) || tt == sg.first_tile) done = true;
+                }
+                t0 -= kLookWin;
+            }
+            st_agent(st, kFlagInc | (excl + tot));
+        }
+        if (dl) {
+            const uint32_t bb = w.rep[lev & 1][(size_t)sg.rep_first * kRepWords + tid];
+            gbase[tid] = sg.start + bb + excl - lb;
         }
         __syncthreads();
         uint64_t *Hd = w.H[sg.buf ^ 1];
@@ -1036,18 +1121,29 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
     return hipGetLastError();
 }
 
+template <int ITEMS, int SWG>
+static hipError_t by_local(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0, hipStream_t s, int cus,
+                           hipEvent_t *ev) {
+    return t.local_wg == 512 ? launch_levels<ITEMS, SWG, 512>(w, t, nreq, tiles0, s, cus, ev)
+                             : launch_levels<ITEMS, SWG, 256>(w, t, nreq, tiles0, s, cus, ev);
+}
+
+template <int ITEMS>
+static hipError_t by_scatter(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0, hipStream_t s, int cus,
+                             hipEvent_t *ev) {
+    switch (t.scatter_wg) {
+    case 256: return by_local<ITEMS, 256>(w, t, nreq, tiles0, s, cus, ev);
+    case 512: return by_local<ITEMS, 512>(w, t, nreq, tiles0, s, cus, ev);
+    default: return by_local<ITEMS, 1024>(w, t, nreq, tiles0, s, cus, ev);
+    }
+}
+
 hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0, hipStream_t s,
                             int cus, hipEvent_t *ev) {
-    const int v = (t.tile_items == 8 ? 4 : 0) | (t.scatter_wg == 512 ? 2 : 0) | (t.local_wg == 512 ? 1 : 0);
-    switch (v) {
-    case 0: return launch_levels<16, 256, 256>(w, t, nreq, tiles0, s, cus, ev);
-    case 1: return launch_levels<16, 256, 512>(w, t, nreq, tiles0, s, cus, ev);
-    case 2: return launch_levels<16, 512, 256>(w, t, nreq, tiles0, s, cus, ev);
-    case 3: return launch_levels<16, 512, 512>(w, t, nreq, tiles0, s, cus, ev);
-    case 4: return launch_levels<8, 256, 256>(w, t, nreq, tiles0, s, cus, ev);
-    case 5: return launch_levels<8, 256, 512>(w, t, nreq, tiles0, s, cus, ev);
-    case 6: return launch_levels<8, 512, 256>(w, t, nreq, tiles0, s, cus, ev);
-    default: return launch_levels<8, 512, 512>(w, t, nreq, tiles0, s, cus, ev);
+    switch (t.tile_items) {
+    case 8: return by_scatter<8>(w, t, nreq, tiles0, s, cus, ev);
+    case 16: return by_scatter<16>(w, t, nreq, tiles0, s, cus, ev);
+    default: return by_scatter<32>(w, t, nreq, tiles0, s, cus, ev);
     }
 }
 

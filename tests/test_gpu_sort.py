@@ -139,6 +139,8 @@ def test_sort_worked_example(gpu):
     dict(tile_items=8, big_threshold=300, tiny_threshold=5), dict(scatter_threads=256),
     dict(scatter_threads=256, tile_items=8, big_threshold=1), dict(local_threads=512),
     dict(local_threads=512, tiny_threshold=1), dict(local_threads=512, tiny_threshold=64, big_threshold=2048),
+    dict(tile_items=16, scatter_threads=512), dict(tile_items=32, scatter_threads=512),
+    dict(tile_items=16, scatter_threads=1024, big_threshold=100),
 ])
 def test_params_do_not_change_output(gpu, params):
     rec = pattern("skewed_narrow", 150_000)
