@@ -12,10 +12,11 @@
 //               digit (ParallelRadixSort, "cache aware scattering": tiles are
 //               ranked and staged in LDS, then written as runs), with tile
 //               offsets from a decoupled look-back over per-tile digit counts
-//   k_local     per small bucket, in one workgroup's LDS: radix partition on
-//               the first varying digit (SingleThreadRadixSort), recursion on
-//               sub-buckets above the tiny threshold, and a comparison sort of
-//               tiny sub-buckets (ComparisonSort)
+//   k_local     per small bucket, in one workgroup's LDS: radix partition of
+//               its (key, index) tuples on the first varying tuple digit
+//               (SingleThreadRadixSort), recursion on sub-buckets above the
+//               tiny threshold, and a comparison sort of tiny sub-buckets
+//               (ComparisonSort)
 //   k_gather    record scatter by the sorted tuples (Section 3.2):
 //               out[j] = in[idx[j]]
 //
@@ -57,26 +58,9 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 }
 
 // Stable rank of digit d among the earlier lanes of this wave and the earlier
-// calls of this wave (counted in cnt[]), over lanes with valid == true.
-__device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint32_t *cnt) {
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < kRB; b++) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
-    }
-    const uint32_t below = __popcll(peers & lanemask_lt());
-    uint32_t base = 0;
-    if (valid) base = cnt[d];
-    __builtin_amdgcn_wave_barrier();
-    if (valid && below == 0) cnt[d] = base + (uint32_t)__popcll(peers);
-    __builtin_amdgcn_wave_barrier();
-    return base + below;
-}
-
-// The same stable rank, split so that the counter updates of all of a
-// thread's items issue back to back instead of one LDS round trip per item:
+// items of this wave (counted in cnt[]), over lanes with valid == true.  It is
+// split in two so that the counter updates of all of a thread's items issue
+// back to back instead of one LDS round trip per item:
 // rank_issue leaves in `old` (in one lane per digit) the wave counter's value
 // before this item's keys were added, and packs the digit, the lane holding
 // `old` and the count of lower lanes with the same digit into `pk`;
