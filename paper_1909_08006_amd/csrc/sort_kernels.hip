@@ -84,16 +84,34 @@ __device__ __forceinline__ uint32_t rank_finish(uint32_t old, uint32_t pk) {
     return (uint32_t)__shfl((int)old, (int)((pk >> 8) & 63u)) + (pk >> 16);
 }
 
+// Wave-wide OR / AND (the device library's cross-lane reductions, per half).
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
+    return ((uint64_t)__ockl_wfred_or_u32((uint32_t)(v >> 32)) << 32) | __ockl_wfred_or_u32((uint32_t)v);
+}
+__device__ __forceinline__ uint64_t wave_and64(uint64_t v) {
+    return ((uint64_t)__ockl_wfred_and_u32((uint32_t)(v >> 32)) << 32) | __ockl_wfred_and_u32((uint32_t)v);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave with DPP row shifts: a
+// Hillis-Steele scan inside each row of 16 lanes, then the last lane of row 0
+// is added to row 1 (and of row 2 to row 3), then lane 31 to rows 2 and 3.
+// Lanes a shift would read from outside the row add zero.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kRowShr + 1, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kRowShr + 2, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kRowShr + 4, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kRowShr + 8, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kRowBcast15, 0xa, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kRowBcast31, 0xc, 0xf, false);
+    return x;
+}
+
 // Exclusive prefix sum over the workgroup's threads (one value each; NW waves).
 template <int NW = kWaves>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp /*[NW]*/) {
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off);
-        if (lane >= (uint32_t)off) x += y;
-    }
+    const uint32_t x = wave_incl_scan(v);
     if (lane == 63) tmp[w] = x;
     __syncthreads();
     uint32_t pre = 0;
@@ -336,13 +354,10 @@ __device__ __forceinline__ void flush_tile_hist(uint32_t *rep, const uint32_t *s
 // Reduces per-thread key masks (OR of h, OR of ~h, OR of k16, OR of ~k16) over the workgroup.
 __device__ __forceinline__ void block_masks(uint64_t oh, uint64_t onh, uint64_t ol, uint64_t onl,
                                             unsigned long long *smask) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        oh |= __shfl_xor(oh, off);
-        onh |= __shfl_xor(onh, off);
-        ol |= __shfl_xor(ol, off);
-        onl |= __shfl_xor(onl, off);
-    }
+    oh = wave_or64(oh);
+    onh = wave_or64(onh);
+    ol = wave_or64(ol);
+    onl = wave_or64(onl);
     if ((threadIdx.x & 63) == 0) {
         atomicOr(&smask[0], (unsigned long long)oh);
         atomicOr(&smask[1], (unsigned long long)onh);
@@ -670,16 +685,7 @@ __global__ __launch_bounds__(WG, WG >= 512 ? 4 : 2) void k_scatter(Work w, Tune 
 // ---------------------------------------------------------------------------
 // k_local: small buckets sorted inside one workgroup's LDS
 
-__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) v |= __shfl_xor(v, off);
-    return v;
-}
-__device__ __forceinline__ uint64_t wave_and64(uint64_t v) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) v &= __shfl_xor(v, off);
-    return v;
-}
+
 
 constexpr int kStack = kLocalCap / 2;
 
