@@ -107,6 +107,17 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     return x;
 }
 
+// Raw buffer loads: lanes whose offset lies past the end of the resource read
+// zero, so loads are issued without branches (the wait counts stay exact and
+// no lane can touch memory outside the range).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+// A value every lane holds alike, moved to scalar registers (buffer resources
+// must be uniform; the compiler cannot always prove it).
+__device__ __forceinline__ uint32_t ufirst(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Exclusive prefix sum over the workgroup's threads (one value each; NW waves).
 template <int NW = kWaves>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp /*[NW]*/) {
@@ -550,8 +561,12 @@ __global__ __launch_bounds__(WG, WG >= 512 ? 4 : 2) void k_scatter(Work w, Tune 
 
     const uint32_t ntiles = min(w.ctl->ntiles[lev], w.max_tiles);
     const uint32_t nseg = min(w.ctl->nseg[lev], w.max_seg);
-    const uint32_t tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     for (;;) {
+        // thread coordinates re-derived per tile: keeps the compiler from
+        // hoisting every per-item index out of the loop (and spilling them)
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const uint32_t wv = tid >> 6, lane = tid & 63;
         __syncthreads();
         if (tid == 0) s_tile = atomicAdd(&w.ctl->tile_ctr[lev], 1u);
         __syncthreads();
@@ -577,16 +592,19 @@ __global__ __launch_bounds__(WG, WG >= 512 ? 4 : 2) void k_scatter(Work w, Tune 
             if (q < nvalid) { h[u] = Hs[q]; l[u] = Ls[q]; }
         }
         __syncthreads();
-        {
-            uint32_t old[ITEMS];
+        // ranks, eight items at a time (bounds the registers of the old values)
+        constexpr int RCH = ITEMS < 8 ? ITEMS : 8;
 #pragma unroll
-            for (int u = 0; u < ITEMS; u++) {
+        for (int c0 = 0; c0 < ITEMS; c0 += RCH) {
+            uint32_t old[RCH];
+#pragma unroll
+            for (int u = c0; u < c0 + RCH; u++) {
                 const uint32_t q = wv * (ITEMS * 64) + u * 64 + lane;
                 const bool valid = q < nvalid;
-                rank_issue(valid ? digit_at(h[u], l[u], sg.spos) : 0u, valid, cnt[wv], old[u], pk[u]);
+                rank_issue(valid ? digit_at(h[u], l[u], sg.spos) : 0u, valid, cnt[wv], old[u - c0], pk[u]);
             }
 #pragma unroll
-            for (int u = 0; u < ITEMS; u++) pk[u] = (pk[u] & 0xFFu) | (rank_finish(old[u], pk[u]) << 8);
+            for (int u = c0; u < c0 + RCH; u++) pk[u] = (pk[u] & 0xFFu) | (rank_finish(old[u - c0], pk[u]) << 8);
         }
         __syncthreads();
         // per-digit wave prefixes and the tile total (digit lanes: tid < 256)
@@ -606,7 +624,7 @@ __global__ __launch_bounds__(WG, WG >= 512 ? 4 : 2) void k_scatter(Work w, Tune 
         const uint32_t lb = block_excl_scan<NW>(tot, tmp);
         if (dl) lbase[tid] = lb;
         __syncthreads();
-        // keys to their place in the tile (digit-major), freeing their registers
+        // keys to their slots in the tile (digit-major), freeing their registers
 #pragma unroll
         for (int u = 0; u < ITEMS; u++) {
             const uint32_t q = wv * (ITEMS * 64) + u * 64 + lane;
@@ -670,6 +688,7 @@ __global__ __launch_bounds__(WG, WG >= 512 ? 4 : 2) void k_scatter(Work w, Tune 
         }
     }
     // set up level lev + 1: tile map and zeroed histogram replicas of its buckets
+    const uint32_t tid = threadIdx.x;
     const uint32_t nn = min(w.ctl->nseg[lev + 1], w.max_seg);
     for (uint32_t s2 = blockIdx.x; s2 < nn; s2 += gridDim.x) {
         const Seg g = w.segs[(lev + 1) & 1][s2];
@@ -689,14 +708,7 @@ __global__ __launch_bounds__(WG, WG >= 512 ? 4 : 2) void k_scatter(Work w, Tune 
 
 constexpr int kStack = kLocalCap / 2;
 
-// Raw buffer loads: lanes whose offset lies past the end of the resource read
-// zero, so loads are issued without branches (the wait counts stay exact and
-// no lane can touch memory outside the range).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void *p, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
-}
 
-__device__ __forceinline__ uint32_t ufirst(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // A task descriptor made uniform across the workgroup; ok false (and count 0)
 // when it lies outside the tuple space (defence against a fired capacity guard).
@@ -750,8 +762,7 @@ template <int LWG, int MINB>
 __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
     constexpr int NW = LWG / 64;
     constexpr int LI = kLocalCap / LWG;
-    __shared__ uint64_t sH[kLocalCap];
-    __shared__ uint64_t sL[kLocalCap];
+    __shared__ ulonglong2 sK[kLocalCap];  // (H, L) of each tuple, one 16-byte LDS access
     __shared__ uint32_t segb[kLocalCap];   // sub-bucket [lo, hi) per position (lo | hi << 16); then the order
     __shared__ uint32_t cnt[kRadix];
     __shared__ uint32_t lbase[kRadix];
@@ -824,8 +835,7 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
                 if (sorted) {
                     segb[q] = (uint32_t)pl[u];
                 } else {
-                    sH[q] = ph[u];
-                    sL[q] = pl[u];
+                    sK[q] = make_ulonglong2(ph[u], pl[u]);
                     segb[q] = q | ((q + 1) << 16);
                     const uint64_t kk = pl[u] & kLowMask48;
                     th |= ph[u]; tah &= ph[u]; tl |= kk; tal &= kk;
@@ -859,7 +869,8 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
             if (!top) {
                 uint64_t oh = 0, ah = ~0ull, ol = 0, al = ~0ull;
                 for (uint32_t q = a + tid; q < a + len; q += LWG) {
-                    const uint64_t hh = sH[q], kk = sL[q] & kLowMask48;
+                    const ulonglong2 t = sK[q];
+                    const uint64_t hh = t.x, kk = t.y & kLowMask48;
                     oh |= hh; ah &= hh; ol |= kk; al &= kk;
                 }
                 oh = wave_or64(oh); ah = wave_and64(ah);
@@ -884,8 +895,9 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
             for (int u = 0; u < LI; u++) {
                 const uint32_t i = u * LWG + tid;
                 const bool valid = i < len;
-                h[u] = valid ? sH[a + i] : 0ull;
-                l[u] = valid ? sL[a + i] : 0ull;
+                const ulonglong2 t = valid ? sK[a + i] : make_ulonglong2(0ull, 0ull);
+                h[u] = t.x;
+                l[u] = t.y;
                 dg[u] = tuple_digit(h[u], l[u], f);
                 rk[u] = valid ? atomicAdd(&cnt[dg[u]], 1u) : 0u;
             }
@@ -908,8 +920,7 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
                 if (i < len) {
                     const uint32_t d = dg[u];
                     const uint32_t np = a + lbase[d] + rk[u];
-                    sH[np] = h[u];
-                    sL[np] = l[u];
+                    sK[np] = make_ulonglong2(h[u], l[u]);
                     const uint32_t c = ltot[d];
                     const uint32_t lo = a + lbase[d];
                     segb[np] = (c > tu.tiny) ? (np | ((np + 1) << 16)) : (lo | ((lo + c) << 16));
@@ -926,13 +937,22 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
                 fv[u] = q; iv[u] = 0;
                 if (q < m) {
                     const uint32_t sb = segb[q], lo = sb & 0xFFFFu, hi = min(sb >> 16, m);
-                    const uint64_t kh = sH[q], kl = sL[q];
+                    const ulonglong2 me = sK[q];
+                    const uint64_t kh = me.x, kl = me.y;
                     iv[u] = (uint32_t)kl;
                     if (hi > lo + 1) {
-                        uint32_t r = 0;
-                        for (uint32_t jj = lo; jj < hi; jj++) {
-                            const uint64_t oh2 = sH[jj], ol2 = sL[jj];
-                            r += (oh2 < kh) || (oh2 == kh && ol2 < kl);
+                        // four members per step: their LDS reads overlap
+                        uint32_t r = 0, jj = lo;
+                        for (; jj + 4 <= hi; jj += 4) {
+                            const ulonglong2 o0 = sK[jj], o1 = sK[jj + 1], o2 = sK[jj + 2], o3 = sK[jj + 3];
+                            r += (o0.x < kh) || (o0.x == kh && o0.y < kl);
+                            r += (o1.x < kh) || (o1.x == kh && o1.y < kl);
+                            r += (o2.x < kh) || (o2.x == kh && o2.y < kl);
+                            r += (o3.x < kh) || (o3.x == kh && o3.y < kl);
+                        }
+                        for (; jj < hi; jj++) {
+                            const ulonglong2 o = sK[jj];
+                            r += (o.x < kh) || (o.x == kh && o.y < kl);
                         }
                         fv[u] = lo + r;
                     }
