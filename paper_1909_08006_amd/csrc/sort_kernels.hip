@@ -118,6 +118,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void *p, uint32_
 // must be uniform; the compiler cannot always prove it).
 __device__ __forceinline__ uint32_t ufirst(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Dwords in device (global) memory, for pointers read from device tables,
+// whose address space the compiler cannot infer (it would emit flat accesses).
+typedef const __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) uint32_t gu32w;
+
 // Exclusive prefix sum over the workgroup's threads (one value each; NW waves).
 template <int NW = kWaves>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp /*[NW]*/) {
@@ -442,7 +447,8 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
             for (int u = 0; u < RI; u++) {
                 const uint32_t q = (r0 + u) * kWG + threadIdx.x;
                 if (q < nvalid) {
-                    const uint32_t *p = reinterpret_cast<const uint32_t *>(rq.in + (local0 + q) * kRec);
+                    // the caller's records are device memory: global (not flat) loads
+                    const gu32 *p = (const gu32 *)(rq.in + (local0 + q) * kRec);
                     a[u] = p[0]; b[u] = p[1]; c[u] = p[2];
                 }
             }
@@ -1022,8 +1028,10 @@ __global__ __launch_bounds__(kWG) void k_gather(const Req *reqs, const Hdr *hdr,
             sidx[threadIdx.x] = ix < rn ? ix : (uint32_t)(g0 + threadIdx.x - rs);
         }
         __syncthreads();
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(in);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(out) + (g0 - rs) * 25;
+        // request buffers are device memory: global (not flat) accesses, so
+        // the waits on the LDS index reads do not also wait on record loads
+        const gu32 *src = (const gu32 *)in;
+        gu32w *dst = (gu32w *)out + (g0 - rs) * 25;
         uint32_t v[25];
 #pragma unroll
         for (int u = 0; u < 25; u++) {
@@ -1046,8 +1054,8 @@ __global__ __launch_bounds__(kWG) void k_gather(const Req *reqs, const Hdr *hdr,
         // a sorted index is always inside its request; fall back to the
         // record itself if a guard fired upstream
         const uint64_t si = ix < rq.n ? ix : (g - rq.start);
-        const uint32_t *s1 = reinterpret_cast<const uint32_t *>(rq.in + si * kRec);
-        uint32_t *d1 = reinterpret_cast<uint32_t *>(rq.out + (g - rq.start) * kRec);
+        const gu32 *s1 = (const gu32 *)(rq.in + si * kRec);
+        gu32w *d1 = (gu32w *)(rq.out + (g - rq.start) * kRec);
         for (int kk = 0; kk < 25; kk++) d1[kk] = s1[kk];
     }
 }
