@@ -329,24 +329,47 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
     if (cnt > tu.big && cpos >= kKeyBits) emit_sorted(w, sg.start + base, cnt, cbuf, sg.req);  // equal keys
     new_segments_block(w, tu, lev + 1, cnt > tu.big && cpos < kKeyBits, sg.start + base, cnt, cpos, cbuf, sg.req);
     __syncthreads();
-    if (d == 0) {  // pack consecutive small buckets into tasks of at most kLocalCap keys
+    if (d < 64) {
+        // pack consecutive small buckets into tasks of at most kLocalCap keys
+        // (greedy, in digit order): wave 0 holds the counts and offsets in
+        // registers (lane l: digits 4l..4l+3) and walks them with lane reads,
+        // so the sequential walk costs no memory round trips
+        uint32_t c4[4], b4[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) { c4[k] = p_cnt[4 * d + k]; b4[k] = p_base[4 * d + k]; }
         uint32_t nt = 0, cur_start = 0, cur = 0;
-        for (int e = 0; e < kRadix; e++) {
-            const uint32_t ce = p_cnt[e];
-            if (ce == 0) continue;
-            if (ce > tu.big) {
-                if (cur) { p_tstart[nt] = cur_start; p_tcnt[nt++] = cur; cur = 0; }
-                continue;
+        for (int e4 = 0; e4 < kRadix / 4; e4++) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const uint32_t ce = __builtin_amdgcn_readlane(c4[k], e4);
+                if (ce == 0) continue;
+                if (ce > tu.big) {
+                    if (cur) {
+                        if (d == 0) { p_tstart[nt] = cur_start; p_tcnt[nt] = cur; }
+                        nt++;
+                        cur = 0;
+                    }
+                    continue;
+                }
+                if (cur && cur + ce > (uint32_t)kLocalCap) {
+                    if (d == 0) { p_tstart[nt] = cur_start; p_tcnt[nt] = cur; }
+                    nt++;
+                    cur = 0;
+                }
+                if (cur == 0) cur_start = __builtin_amdgcn_readlane(b4[k], e4);
+                cur += ce;
             }
-            if (cur && cur + ce > (uint32_t)kLocalCap) { p_tstart[nt] = cur_start; p_tcnt[nt++] = cur; cur = 0; }
-            if (cur == 0) cur_start = p_base[e];
-            cur += ce;
         }
-        if (cur) { p_tstart[nt] = cur_start; p_tcnt[nt++] = cur; }
-        uint32_t slot = atomicAdd(&w.ctl->ntask, nt);
-        if ((uint64_t)slot + nt > w.max_tasks) { atomicOr(&w.ctl->guard, 1u); nt = 0; }
-        p_ntask = nt;
-        p_slot = slot;
+        if (cur) {
+            if (d == 0) { p_tstart[nt] = cur_start; p_tcnt[nt] = cur; }
+            nt++;
+        }
+        if (d == 0) {
+            uint32_t slot = atomicAdd(&w.ctl->ntask, nt);
+            if ((uint64_t)slot + nt > w.max_tasks) { atomicOr(&w.ctl->guard, 1u); nt = 0; }
+            p_ntask = nt;
+            p_slot = slot;
+        }
     }
     __syncthreads();
     for (uint32_t t = d; t < p_ntask; t += kWG) {
