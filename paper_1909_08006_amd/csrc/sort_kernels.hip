@@ -443,7 +443,7 @@ __global__ __launch_bounds__(kWG) void k_init(Work w) {
 
 template <int ITEMS>
 __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
-    constexpr int RI = ITEMS > 16 ? 16 : ITEMS;
+    constexpr int RI = ITEMS > 8 ? 8 : ITEMS;
     __shared__ uint32_t sh[kRadix];
     __shared__ unsigned long long smask[4];
     const uint32_t ntiles = min(w.ctl->ntiles[0], w.max_tiles);
@@ -470,9 +470,12 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
             for (int u = 0; u < RI; u++) {
                 const uint32_t q = (r0 + u) * kWG + threadIdx.x;
                 if (q < nvalid) {
-                    // the caller's records are device memory: global (not flat) loads
+                    // the caller's records are device memory: global (not flat)
+                    // loads, marked non-temporal (each line is read once here)
                     const gu32 *p = (const gu32 *)(rq.in + (local0 + q) * kRec);
-                    a[u] = p[0]; b[u] = p[1]; c[u] = p[2];
+                    a[u] = __builtin_nontemporal_load(p);
+                    b[u] = __builtin_nontemporal_load(p + 1);
+                    c[u] = __builtin_nontemporal_load(p + 2);
                 }
             }
 #pragma unroll
@@ -481,8 +484,9 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
                 if (q < nvalid) {
                     const uint64_t h = __builtin_bswap64(((uint64_t)b[u] << 32) | a[u]);
                     const uint64_t k16 = __builtin_bswap16((uint16_t)(c[u] & 0xFFFFu));
-                    H[q] = h;
-                    L[q] = (k16 << 32) | (uint32_t)(local0 + q);
+                    // tuples: written once, read by the next pass (far beyond the caches)
+                    __builtin_nontemporal_store(h, H + q);
+                    __builtin_nontemporal_store((k16 << 32) | (uint32_t)(local0 + q), L + q);
                     atomicAdd(&sh[h >> 56], 1u);
                     oh |= h; onh |= ~h; ol |= k16; onl |= (~k16) & 0xFFFFu;
                 }
@@ -535,8 +539,9 @@ __global__ __launch_bounds__(kWG) void k_hist(Work w, Tune tu, int lev) {
                 const uint32_t q = (r0 + u) * kWG + threadIdx.x;
                 h[u] = 0; l[u] = 0;
                 if (q < nvalid) {
-                    h[u] = H[q];
-                    if (needL) l[u] = L[q];
+                    // non-temporal: the bucket is far larger than the caches
+                    h[u] = __builtin_nontemporal_load(H + q);
+                    if (needL) l[u] = __builtin_nontemporal_load(L + q);
                 }
             }
 #pragma unroll
@@ -1061,10 +1066,11 @@ __global__ __launch_bounds__(kWG) void k_gather(const Req *reqs, const Hdr *hdr,
             const uint32_t q = threadIdx.x + kWG * u, r = q / 25u, kk = q - 25u * r;
             if (r < nr) v[u] = src[(uint64_t)sidx[r] * 25 + kk];
         }
+        // output lines are written once and not read back here: non-temporal
 #pragma unroll
         for (int u = 0; u < 25; u++) {
             const uint32_t q = threadIdx.x + kWG * u, r = q / 25u;
-            if (r < nr) dst[q] = v[u];
+            if (r < nr) __builtin_nontemporal_store(v[u], dst + q);
         }
         return;
     }
@@ -1103,7 +1109,7 @@ __global__ __launch_bounds__(kWG) void k_gather_plain(const uint8_t *rec, uint64
 #pragma unroll
     for (int u = 0; u < 25; u++) {
         const uint32_t q = threadIdx.x + kWG * u, r = q / 25u;
-        if (r < nr) dst[q] = v[u];
+        if (r < nr) __builtin_nontemporal_store(v[u], dst + q);
     }
 }
 
