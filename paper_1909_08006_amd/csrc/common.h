@@ -18,8 +18,9 @@ constexpr int kLocalCap = 2048;    // keys per local (LDS) sort task
 constexpr int kLocalItems = kLocalCap / kWG;
 constexpr uint16_t kNoScatter = 0xFFFF;
 
-constexpr uint64_t kFlagAgg = 1ull << 62;  // look-back status: tile aggregate published
+constexpr uint64_t kFlagAgg = 1ull << 62;  // look-back status: chunk aggregate published
 constexpr uint64_t kFlagInc = 2ull << 62;  // look-back status: inclusive prefix published
+constexpr int kChunkTiles = 128;           // tiles per chunk of the tile-offset scan
 constexpr uint64_t kCountMask = (1ull << 62) - 1;
 
 constexpr uint8_t kTaskSorted = 1;  // task range is already in final order
@@ -56,6 +57,7 @@ struct Ctl {
     uint32_t ntiles[kMaxLev + 2];
     uint32_t tile_ctr[kMaxLev + 2];
     uint32_t rep_ctr[kMaxLev + 2];
+    uint32_t chunk_ctr[kMaxLev + 2];
     uint32_t ntask;
     uint32_t task_ctr;
     uint32_t guard;
@@ -102,7 +104,8 @@ struct Work {
     Seg *segs[2];        // by level parity
     uint32_t *rep[2];    // histogram replicas [rep][kRepWords], by level parity
     uint32_t *tile_seg[2];
-    unsigned long long *status;  // [tile][kRadix]
+    unsigned long long *status;  // [tile][kRadix]: digit count, then offset among the bucket's tiles
+    unsigned long long *cstat;   // [chunk][kRadix]: look-back words of the tile-offset scan
     Task *tasks;
     Req *reqs;
     Hdr *hdr;
@@ -115,7 +118,7 @@ struct Layout {
     uint64_t n;
     uint32_t max_seg, max_tiles, max_tasks, max_reqs, max_reps;
     size_t off_H0, off_H1, off_L0, off_L1, off_idx, off_ctl, off_seg0, off_seg1, off_rep0,
-        off_rep1, off_ts0, off_ts1, off_status, off_tasks, off_reqs, off_hdr, total;
+        off_rep1, off_ts0, off_ts1, off_status, off_cstat, off_tasks, off_reqs, off_hdr, total;
 };
 Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t);
 Work bind_layout(const Layout &L, void *base);

@@ -113,6 +113,7 @@ Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t) {
     L.off_ts0 = take((size_t)L.max_tiles * 4);
     L.off_ts1 = take((size_t)L.max_tiles * 4);
     L.off_status = take((size_t)L.max_tiles * kRadix * 8);
+    L.off_cstat = take(((size_t)L.max_tiles / kChunkTiles + 1) * kRadix * 8);
     L.off_tasks = take((size_t)L.max_tasks * sizeof(Task));
     L.off_reqs = take((size_t)L.max_reqs * sizeof(Req));
     L.off_hdr = take(sizeof(Hdr));
@@ -136,6 +137,7 @@ Work bind_layout(const Layout &L, void *base) {
     w.tile_seg[0] = reinterpret_cast<uint32_t *>(b + L.off_ts0);
     w.tile_seg[1] = reinterpret_cast<uint32_t *>(b + L.off_ts1);
     w.status = reinterpret_cast<unsigned long long *>(b + L.off_status);
+    w.cstat = reinterpret_cast<unsigned long long *>(b + L.off_cstat);
     w.tasks = reinterpret_cast<Task *>(b + L.off_tasks);
     w.reqs = reinterpret_cast<Req *>(b + L.off_reqs);
     w.hdr = reinterpret_cast<Hdr *>(b + L.off_hdr);

@@ -8,10 +8,11 @@
 //               masks (AlphaSort-style key-pointer extraction, Section 3.2)
 //   k_hist      per level >= 1: digit histograms and key masks of big buckets
 //   k_plan      per level: bucket policy of Algorithm 1 for every big bucket
+//   k_tscan     per level: each tile's per-digit offset among its bucket's
+//               tiles, from the tile counts of the histogram pass
 //   k_scatter   per level: stable device-wide partition of big buckets by one
 //               digit (ParallelRadixSort, "cache aware scattering": tiles are
-//               ranked and staged in LDS, then written as runs), with tile
-//               offsets from a decoupled look-back over per-tile digit counts
+//               ranked and staged in LDS, then written as runs)
 //   k_local     per small bucket, in one workgroup's LDS: radix partition of
 //               its (key, index) tuples on the first varying tuple digit
 //               (SingleThreadRadixSort), recursion on sub-buckets above the
@@ -138,7 +139,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp /*
 }
 
 constexpr uint32_t kSpinLimit = 1u << 24;
-constexpr int kLookWin = 8;  // predecessor tiles read per look-back step
 
 // A segment read back from a device table is inside the tuple space and owns
 // the tile that points at it (defence against a fired capacity guard).
@@ -380,9 +380,12 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
     __syncthreads();
 }
 
-// Adds a tile's LDS histogram and key masks into one replica of its bucket.
-__device__ __forceinline__ void flush_tile_hist(uint32_t *rep, const uint32_t *sh, const unsigned long long *smask) {
+// Adds a tile's LDS histogram and key masks into one replica of its bucket,
+// and stores the tile's digit counts.
+__device__ __forceinline__ void flush_tile_hist(uint32_t *rep, const uint32_t *sh, const unsigned long long *smask,
+                                                unsigned long long *tile_count) {
     const uint32_t v = sh[threadIdx.x];
+    tile_count[threadIdx.x] = v;  // this tile's digit counts, for the tile-offset scan
     if (v) atomicAdd(&rep[threadIdx.x], v);
     if (threadIdx.x < 4) {
         const unsigned long long m = smask[threadIdx.x];
@@ -452,6 +455,7 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
         sh[threadIdx.x] = 0;
         if (threadIdx.x < 4) smask[threadIdx.x] = 0;
         w.status[(size_t)tile * kRadix + threadIdx.x] = 0;
+        if (tile % kChunkTiles == 0) w.cstat[(size_t)(tile / kChunkTiles) * kRadix + threadIdx.x] = 0;
         const uint32_t s = w.tile_seg[0][tile];
         if (s >= nreq || s >= w.max_seg) { if (threadIdx.x == 0) atomicOr(&w.ctl->guard, 8u); __syncthreads(); continue; }
         const Seg sg = w.segs[0][s];
@@ -494,7 +498,8 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
         }
         block_masks(oh, onh, ol, onl, smask);
         __syncthreads();
-        flush_tile_hist(w.rep[0] + ((size_t)sg.rep_first + (tile - sg.first_tile) % sg.nrep) * kRepWords, sh, smask);
+        flush_tile_hist(w.rep[0] + ((size_t)sg.rep_first + (tile - sg.first_tile) % sg.nrep) * kRepWords, sh, smask,
+                        w.status + (size_t)tile * kRadix);
         __syncthreads();
     }
 }
@@ -513,6 +518,7 @@ __global__ __launch_bounds__(kWG) void k_hist(Work w, Tune tu, int lev) {
         sh[threadIdx.x] = 0;
         if (threadIdx.x < 4) smask[threadIdx.x] = 0;
         w.status[(size_t)tile * kRadix + threadIdx.x] = 0;
+        if (tile % kChunkTiles == 0) w.cstat[(size_t)(tile / kChunkTiles) * kRadix + threadIdx.x] = 0;
         const uint32_t s = w.tile_seg[lev & 1][tile];
         if (s >= nseg) { if (threadIdx.x == 0) atomicOr(&w.ctl->guard, 8u); __syncthreads(); continue; }
         const Seg sg = w.segs[lev & 1][s];
@@ -560,7 +566,7 @@ __global__ __launch_bounds__(kWG) void k_hist(Work w, Tune tu, int lev) {
         block_masks(oh, onh, ol, onl, smask);
         __syncthreads();
         flush_tile_hist(w.rep[lev & 1] + ((size_t)sg.rep_first + (tile - sg.first_tile) % sg.nrep) * kRepWords, sh,
-                        smask);
+                        smask, w.status + (size_t)tile * kRadix);
         __syncthreads();
     }
 }
@@ -577,10 +583,92 @@ __global__ __launch_bounds__(kWG) void k_plan(Work w, Tune tu, int lev) {
 }
 
 // ---------------------------------------------------------------------------
+// k_tscan: every tile's offset, per digit, among the tiles of its bucket
+//
+// status[tile][d] holds the tile's count of digit d (from the histogram pass);
+// this replaces it with the sum over the earlier tiles of the same bucket, so
+// the partition pass needs no cross-tile wait.  Chunks of kChunkTiles tiles
+// are scanned by one workgroup each (digit d by thread d); a bucket that runs
+// over a chunk boundary takes its carry from a decoupled look-back over the
+// earlier chunks, which publish their totals as soon as they have them (a
+// chunk whose last bucket starts inside it publishes an inclusive value at
+// once).
+
+__global__ __launch_bounds__(kWG) void k_tscan(Work w, int lev) {
+    __shared__ uint32_t s_chunk;
+    const uint32_t ntiles = min(w.ctl->ntiles[lev], w.max_tiles);
+    const uint32_t nseg = min(w.ctl->nseg[lev], w.max_seg);
+    const uint32_t nchunks = (ntiles + kChunkTiles - 1) / kChunkTiles;
+    const uint32_t *tmap = w.tile_seg[lev & 1];
+    const Seg *segs = w.segs[lev & 1];
+    const uint32_t d = threadIdx.x;
+    for (;;) {
+        __syncthreads();
+        if (d == 0) s_chunk = atomicAdd(&w.ctl->chunk_ctr[lev], 1u);
+        __syncthreads();
+        const uint32_t c = ufirst(s_chunk);
+        if (c >= nchunks) break;
+        const uint32_t t0 = c * kChunkTiles, t1 = min(t0 + kChunkTiles, ntiles);
+        // the first bucket part continues from earlier chunks unless it starts here
+        const uint32_t s0 = ufirst(tmap[t0]);
+        const bool cont = s0 < nseg && segs[s0].first_tile < t0;
+        uint32_t cur = s0, first_end = t1;
+        unsigned long long run = 0;
+        constexpr int B = 16;  // tiles whose loads are in flight together
+        for (uint32_t tb = t0; tb < t1; tb += B) {
+            uint32_t sv[B];
+            unsigned long long cv[B];
+#pragma unroll
+            for (int i = 0; i < B; i++) {
+                const uint32_t t = tb + i;
+                sv[i] = t < t1 ? tmap[t] : cur;
+                cv[i] = t < t1 ? w.status[(size_t)t * kRadix + d] : 0ull;
+            }
+#pragma unroll
+            for (int i = 0; i < B; i++) {
+                const uint32_t t = tb + i;
+                if (t >= t1) break;
+                const uint32_t st = ufirst(sv[i]);
+                if (st != cur) {  // a new bucket starts at t
+                    if (first_end == t1) first_end = t;
+                    cur = st;
+                    run = 0;
+                }
+                w.status[(size_t)t * kRadix + d] = run;
+                run += cv[i];
+            }
+        }
+        unsigned long long *cs = w.cstat + (size_t)c * kRadix + d;
+        if (!cont || first_end < t1) st_agent(cs, kFlagInc | run);  // the last part starts in this chunk
+        else st_agent(cs, kFlagAgg | run);
+        if (!cont) continue;
+        // carry of the first part: look back over earlier chunks
+        unsigned long long carry = 0;
+        uint32_t spins = 0;
+        for (uint32_t cc = c - 1;; cc--) {
+            const unsigned long long *sp = w.cstat + (size_t)cc * kRadix + d;
+            unsigned long long v;
+            while (((v = ld_agent(sp)) >> 62) == 0 && spins < kSpinLimit) {
+                __builtin_amdgcn_s_sleep(1);
+                spins++;
+            }
+            if (spins >= kSpinLimit) { atomicOr(&w.ctl->guard, 16u); break; }
+            carry += v & kCountMask;
+            if ((v & kFlagInc) || cc == 0) break;
+        }
+        if (first_end == t1) st_agent(cs, kFlagInc | (carry + run));
+#pragma unroll 8
+        for (uint32_t t = t0; t < first_end; t++) w.status[(size_t)t * kRadix + d] += carry;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_scatter: one device-wide stable partition pass of the big buckets of level lev
 
 // WG threads, ITEMS keys each (a tile is WG * ITEMS keys); the 256 digit
-// lanes of the histogram, look-back and offsets are threads 0..255.
+// lanes of the histogram and offsets are threads 0..255.  A tile's global
+// offsets are the bucket's digit offsets plus the tile's offsets among the
+// bucket's tiles (k_tscan), so tiles never wait on each other.
 template <int ITEMS, int WG>
 __global__ __launch_bounds__(WG, WG >= 512 ? 4 : 2) void k_scatter(Work w, Tune tu, int lev) {
     constexpr int TILE = WG * ITEMS;
@@ -611,11 +699,16 @@ __global__ __launch_bounds__(WG, WG >= 512 ? 4 : 2) void k_scatter(Work w, Tune 
         const Seg sg = w.segs[lev & 1][s];
         if (sg.spos == kNoScatter || !seg_ok(w, sg, tile) || sg.spos >= kKeyBits) continue;
         const uint64_t seg_end = sg.start + sg.count;
-        const uint32_t k = tile - sg.first_tile;
-        const uint64_t local0 = (uint64_t)k * TILE;
+        const uint64_t local0 = (uint64_t)(tile - sg.first_tile) * TILE;
         const uint32_t nvalid = (uint32_t)min<uint64_t>(TILE, sg.count - local0);
         const uint64_t *Hs = w.H[sg.buf] + sg.start + local0;
         const uint64_t *Ls = w.L[sg.buf] + sg.start + local0;
+        const bool dl = tid < (uint32_t)kRadix;  // digit lanes
+        // digit lane: the digit's bucket offset and this tile's offset among the
+        // bucket's tiles (both known before the pass; used after the ranking)
+        uint64_t toff = 0;
+        if (dl) toff = (uint64_t)w.rep[lev & 1][(size_t)sg.rep_first * kRepWords + tid] +
+                       w.status[(size_t)tile * kRadix + tid];
         for (uint32_t i = tid; i < NW * kRadix; i += WG) (&cnt[0][0])[i] = 0;
         uint64_t h[ITEMS], l[ITEMS];
         uint32_t pk[ITEMS];  // digit | rank in the wave's digit << 8
@@ -641,8 +734,7 @@ __global__ __launch_bounds__(WG, WG >= 512 ? 4 : 2) void k_scatter(Work w, Tune 
             for (int u = c0; u < c0 + RCH; u++) pk[u] = (pk[u] & 0xFFu) | (rank_finish(old[u - c0], pk[u]) << 8);
         }
         __syncthreads();
-        // per-digit wave prefixes and the tile total (digit lanes: tid < 256)
-        const bool dl = tid < (uint32_t)kRadix;
+        // per-digit wave prefixes and the tile total (digit lanes)
         uint32_t tot = 0;
         if (dl) {
 #pragma unroll
@@ -652,9 +744,6 @@ __global__ __launch_bounds__(WG, WG >= 512 ? 4 : 2) void k_scatter(Work w, Tune 
                 tot += cj;
             }
         }
-        // this tile's digit counts are known: publish them for later tiles first
-        unsigned long long *st = w.status + (size_t)tile * kRadix + (dl ? tid : 0u);
-        if (dl) st_agent(st, (k == 0 ? kFlagInc : kFlagAgg) | tot);
         const uint32_t lb = block_excl_scan<NW>(tot, tmp);
         if (dl) lbase[tid] = lb;
         __syncthreads();
@@ -669,40 +758,7 @@ __global__ __launch_bounds__(WG, WG >= 512 ? 4 : 2) void k_scatter(Work w, Tune 
                 sL[pos] = l[u];
             }
         }
-        // decoupled look-back over earlier tiles of the same bucket, kLookWin
-        // predecessors at a time: their flags load together, so a walk over
-        // aggregates costs one round trip per window
-        unsigned long long excl = 0;
-        if (dl && k > 0) {
-            uint32_t spins = 0;
-            bool done = false;
-            for (uint32_t t0 = tile - 1; !done;) {
-                unsigned long long v[kLookWin];
-#pragma unroll
-                for (int k2 = 0; k2 < kLookWin; k2++)
-                    v[k2] = (t0 >= sg.first_tile + k2) ? ld_agent(w.status + (size_t)(t0 - k2) * kRadix + tid) : 0ull;
-#pragma unroll
-                for (int k2 = 0; k2 < kLookWin; k2++) {
-                    if (done) break;
-                    const uint32_t tt = t0 - k2;
-                    const unsigned long long *sp = w.status + (size_t)tt * kRadix + tid;
-                    while ((v[k2] >> 62) == 0 && spins < kSpinLimit) {
-                        __builtin_amdgcn_s_sleep(1);
-                        spins++;
-                        v[k2] = ld_agent(sp);
-                    }
-                    if (spins >= kSpinLimit) { atomicOr(&w.ctl->guard, 16u); done = true; break; }
-                    excl += v[k2] & kCountMask;
-                    if ((v[k2] & kFlagInc) || tt == sg.first_tile) done = true;
-                }
-                t0 -= kLookWin;
-            }
-            st_agent(st, kFlagInc | (excl + tot));
-        }
-        if (dl) {
-            const uint32_t bb = w.rep[lev & 1][(size_t)sg.rep_first * kRepWords + tid];
-            gbase[tid] = sg.start + bb + excl - lb;
-        }
+        if (dl) gbase[tid] = sg.start + toff - lb;
         __syncthreads();
         uint64_t *Hd = w.H[sg.buf ^ 1];
         uint64_t *Ld = w.L[sg.buf ^ 1];
@@ -1160,6 +1216,7 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
     for (int lev = 0; lev < kMaxLev; lev++) {
         if (lev > 0) k_hist<ITEMS><<<dim3(g_hist), dim3(kWG), 0, s>>>(w, t, lev);
         k_plan<<<dim3(g_plan), dim3(kWG), 0, s>>>(w, t, lev);
+        k_tscan<<<dim3(cus), dim3(kWG), 0, s>>>(w, lev);
         k_scatter<SITEMS, SWG><<<dim3(g_sc), dim3(SWG), 0, s>>>(w, t, lev);
     }
     if (ev) (void)hipEventRecord(ev[1], s);
