@@ -624,7 +624,6 @@ __global__ __launch_bounds__(kWG) void k_tscan(Work w, int lev) {
                 sv[i] = t < t1 ? tmap[t] : cur;
                 cv[i] = t < t1 ? w.status[(size_t)t * kRadix + d] : 0ull;
             }
-#pragma unroll
             for (int i = 0; i < B; i++) {
                 const uint32_t t = tb + i;
                 if (t >= t1) break;
@@ -642,22 +641,33 @@ __global__ __launch_bounds__(kWG) void k_tscan(Work w, int lev) {
         if (!cont || first_end < t1) st_agent(cs, kFlagInc | run);  // the last part starts in this chunk
         else st_agent(cs, kFlagAgg | run);
         if (!cont) continue;
-        // carry of the first part: look back over earlier chunks
+        // carry of the first part: look back over earlier chunks, eight at a
+        // time (their words load together; a walk over aggregates costs one
+        // round trip per eight chunks)
+        constexpr int LW = 8;
         unsigned long long carry = 0;
         uint32_t spins = 0;
-        for (uint32_t cc = c - 1;; cc--) {
-            const unsigned long long *sp = w.cstat + (size_t)cc * kRadix + d;
-            unsigned long long v;
-            while (((v = ld_agent(sp)) >> 62) == 0 && spins < kSpinLimit) {
-                __builtin_amdgcn_s_sleep(1);
-                spins++;
+        bool done = false;
+        for (uint32_t c0 = c - 1; !done; c0 -= LW) {
+            unsigned long long v[LW];
+#pragma unroll
+            for (int k = 0; k < LW; k++)
+                v[k] = c0 >= (uint32_t)k ? ld_agent(w.cstat + (size_t)(c0 - k) * kRadix + d) : 0ull;
+#pragma unroll
+            for (int k = 0; k < LW; k++) {
+                if (done) break;
+                const uint32_t cc = c0 - k;
+                while ((v[k] >> 62) == 0 && spins < kSpinLimit) {
+                    __builtin_amdgcn_s_sleep(1);
+                    spins++;
+                    v[k] = ld_agent(w.cstat + (size_t)cc * kRadix + d);
+                }
+                if (spins >= kSpinLimit) { atomicOr(&w.ctl->guard, 16u); done = true; break; }
+                carry += v[k] & kCountMask;
+                if ((v[k] & kFlagInc) || cc == 0) done = true;
             }
-            if (spins >= kSpinLimit) { atomicOr(&w.ctl->guard, 16u); break; }
-            carry += v & kCountMask;
-            if ((v & kFlagInc) || cc == 0) break;
         }
         if (first_end == t1) st_agent(cs, kFlagInc | (carry + run));
-#pragma unroll 8
         for (uint32_t t = t0; t < first_end; t++) w.status[(size_t)t * kRadix + d] += carry;
     }
 }
@@ -669,8 +679,15 @@ __global__ __launch_bounds__(kWG) void k_tscan(Work w, int lev) {
 // lanes of the histogram and offsets are threads 0..255.  A tile's global
 // offsets are the bucket's digit offsets plus the tile's offsets among the
 // bucket's tiles (k_tscan), so tiles never wait on each other.
+// waves per SIMD the scatter's registers are sized for: one workgroup per CU
+// when the tile's LDS staging exceeds half the LDS, else at least two
 template <int ITEMS, int WG>
-__global__ __launch_bounds__(WG, WG >= 512 ? 4 : 2) void k_scatter(Work w, Tune tu, int lev) {
+constexpr int scatter_waves() {
+    return (WG * ITEMS * 16 > 80 * 1024) ? WG / 256 : (WG >= 512 ? 4 : 2);
+}
+
+template <int ITEMS, int WG>
+__global__ __launch_bounds__(WG, (scatter_waves<ITEMS, WG>())) void k_scatter(Work w, Tune tu, int lev) {
     constexpr int TILE = WG * ITEMS;
     constexpr int NW = WG / 64;
     __shared__ uint64_t sH[TILE];
@@ -890,7 +907,8 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
     };
 
     // prologue: the first task's descriptor and keys, the second's descriptor,
-    // the third's id
+    // the third's id; the partition counters start (and stay) at zero
+    for (uint32_t i = tid; i < kRadix; i += LWG) cnt[i] = 0;
     if (tid == 0) s_next = atomicAdd(&w.ctl->task_ctr, 1u);
     __syncthreads();
     uint32_t j = ufirst(s_next);
@@ -935,10 +953,7 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
         th = wave_or64(th); tah = wave_and64(tah);
         tl = wave_or64(tl); tal = wave_and64(tal);
         if (lane == 0) { orh[wv] = th; andh[wv] = tah; orl[wv] = tl; andl[wv] = tal; }
-        if (tid == 0) {
-            stk[0] = 0u | (m << 16);
-            stk_n = sorted ? 0 : 1;
-        }
+        if (tid == 0) stk_n = 0;
         // the id three tasks ahead (consumed after the sort), then the next
         // task's keys, then the descriptor of the one after
         uint32_t ahead = 0;
@@ -947,38 +962,11 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
         __syncthreads();
         const uint32_t jnn = ufirst(s_next);
         issue_desc(jnn);
-        bool top = true;
-        for (;;) {
-            const int nst = min(stk_n, kStack);
-            if (nst <= 0) break;
-            const uint32_t e = stk[nst - 1];
-            __syncthreads();
-            if (tid == 0) stk_n = nst - 1;
-            const uint32_t a = e & 0xFFFFu, len = e >> 16;
-            // which key bits vary over [a, a + len) (for the whole task: from the load)
-            if (!top) {
-                uint64_t oh = 0, ah = ~0ull, ol = 0, al = ~0ull;
-                for (uint32_t q = a + tid; q < a + len; q += LWG) {
-                    const ulonglong2 t = sK[q];
-                    const uint64_t hh = t.x, kk = t.y & kLowMask48;
-                    oh |= hh; ah &= hh; ol |= kk; al &= kk;
-                }
-                oh = wave_or64(oh); ah = wave_and64(ah);
-                ol = wave_or64(ol); al = wave_and64(al);
-                if (lane == 0) { orh[wv] = oh; andh[wv] = ah; orl[wv] = ol; andl[wv] = al; }
-                __syncthreads();
-            }
-            top = false;
-            uint64_t OH = 0, AH = ~0ull, OL = 0, AL = ~0ull;
-#pragma unroll
-            for (int k2 = 0; k2 < NW; k2++) { OH |= orh[k2]; AH &= andh[k2]; OL |= orl[k2]; AL &= andl[k2]; }
-            const uint64_t vh = OH ^ AH, vl = (OL ^ AL) & kLowMask48;
-            if (vh == 0 && vl == 0) continue;  // a single tuple
-            const uint32_t f = vh ? (uint32_t)__clzll(vh) : 64u + ((uint32_t)__clzll(vl) - 16u);
-            // partition of [a, a + len) by the tuple digit at bit f
-            const bool dl = tid < (uint32_t)kRadix;
-            if (dl) cnt[tid] = 0;
-            __syncthreads();
+        // stable-free partition of [a, a + len) by the tuple digit at bit f:
+        // LDS-atomic ranks, one wave scans the 256 counts (and pushes the big
+        // sub-buckets), then every key moves to its sub-bucket.  cnt is zero
+        // on entry; it is zero again on exit.
+        auto partition = [&](uint32_t a, uint32_t len, uint32_t f) {
             uint64_t h[LI], l[LI];
             uint32_t dg[LI], rk[LI];
 #pragma unroll
@@ -992,16 +980,25 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
                 rk[u] = valid ? atomicAdd(&cnt[dg[u]], 1u) : 0u;
             }
             __syncthreads();
-            const uint32_t tot = dl ? cnt[tid] : 0u;
-            const uint32_t lb = block_excl_scan<NW>(tot, tmp);
-            if (dl) {
-                lbase[tid] = lb;
-                ltot[tid] = tot;
-            }
-            if (tot > tu.tiny) {
-                const int slot = atomicAdd(&stk_n, 1);
-                if (slot < kStack) stk[slot] = (a + lb) | (tot << 16);
-                else atomicOr(&w.ctl->guard, 128u);
+            if (wv == 0) {
+                // lane l: digits 4l..4l+3
+                uint32_t c4[4], sum = 0;
+#pragma unroll
+                for (int k2 = 0; k2 < 4; k2++) { c4[k2] = cnt[4 * lane + k2]; sum += c4[k2]; }
+                uint32_t base = wave_incl_scan(sum) - sum;
+#pragma unroll
+                for (int k2 = 0; k2 < 4; k2++) {
+                    const uint32_t dd = 4 * lane + k2, c = c4[k2];
+                    lbase[dd] = base;
+                    ltot[dd] = c;
+                    cnt[dd] = 0;
+                    if (c > tu.tiny) {
+                        const int slot = atomicAdd(&stk_n, 1);
+                        if (slot < kStack) stk[slot] = (a + base) | (c << 16);
+                        else atomicOr(&w.ctl->guard, 128u);
+                    }
+                    base += c;
+                }
             }
             __syncthreads();
 #pragma unroll
@@ -1017,6 +1014,42 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
                 }
             }
             __syncthreads();
+        };
+        // first varying tuple bit from the masks in LDS; kKeyBits + 32 if none
+        auto varying_bit = [&]() -> uint32_t {
+            uint64_t OH = 0, AH = ~0ull, OL = 0, AL = ~0ull;
+#pragma unroll
+            for (int k2 = 0; k2 < NW; k2++) { OH |= orh[k2]; AH &= andh[k2]; OL |= orl[k2]; AL &= andl[k2]; }
+            const uint64_t vh = OH ^ AH, vl = (OL ^ AL) & kLowMask48;
+            if (vh) return (uint32_t)__clzll(vh);
+            if (vl) return 64u + ((uint32_t)__clzll(vl) - 16u);
+            return kKeyBits + 32u;
+        };
+        if (!sorted) {
+            // the whole task, with the masks from the load
+            const uint32_t f = varying_bit();
+            if (f < kKeyBits + 32u) partition(0u, m, f);
+            // sub-buckets above the tiny threshold, depth first
+            for (;;) {
+                const int nst = min(stk_n, kStack);
+                if (nst <= 0) break;
+                const uint32_t e = stk[nst - 1];
+                __syncthreads();
+                if (tid == 0) stk_n = nst - 1;
+                const uint32_t a = e & 0xFFFFu, len = e >> 16;
+                uint64_t oh = 0, ah = ~0ull, ol = 0, al = ~0ull;
+                for (uint32_t q = a + tid; q < a + len; q += LWG) {
+                    const ulonglong2 t = sK[q];
+                    const uint64_t hh = t.x, kk = t.y & kLowMask48;
+                    oh |= hh; ah &= hh; ol |= kk; al &= kk;
+                }
+                oh = wave_or64(oh); ah = wave_and64(ah);
+                ol = wave_or64(ol); al = wave_and64(al);
+                if (lane == 0) { orh[wv] = oh; andh[wv] = ah; orl[wv] = ol; andl[wv] = al; }
+                __syncthreads();
+                const uint32_t f2 = varying_bit();
+                if (f2 < kKeyBits + 32u) partition(a, len, f2);
+            }
         }
         if (!sorted) {
             // tiny sub-buckets: position = sub-bucket start + number of smaller tuples
