@@ -167,6 +167,27 @@ def test_small_config_full_compare(gpu):
     assert_same(got, oracle.sort(rec), "1e6 uniform")
 
 
+@pytest.mark.parametrize("kind", ["uniform", "skewed"])
+def test_tile_offsets_across_scan_chunks(gpu, kind):
+    """3,000,000 records: the level-0 bucket spans three chunks of the tile-offset
+    scan (carries between chunks) and level-1 chunks hold many buckets."""
+    n = 3_000_000
+    rec = datagen.uniform(n, 91) if kind == "uniform" else datagen.skewed(n, 92)
+    assert_same(run_sort(gpu, rec), oracle.sort(rec), f"3e6 {kind}")
+
+
+def test_small_tiles_many_chunks(gpu):
+    """2,048-key tiles: 1,200,000 records make 586 level-0 tiles (five scan chunks)."""
+    rec = datagen.skewed(1_200_000, 93, nvals=256, dup_frac=0.1)
+    want = oracle.sort(rec)
+    old = gpu.get_params()
+    try:
+        gpu.set_params(tile_items=8)
+        assert_same(run_sort(gpu, rec), want, "tile_items=8")
+    finally:
+        gpu.set_params(**old)
+
+
 def test_stats_uniform(gpu):
     import torch
     rec = datagen.uniform(1_000_000, 1)
