@@ -599,6 +599,9 @@ __global__ __launch_bounds__(kWG) void k_tscan(Work w, int lev) {
     const uint32_t ntiles = min(w.ctl->ntiles[lev], w.max_tiles);
     const uint32_t nseg = min(w.ctl->nseg[lev], w.max_seg);
     const uint32_t nchunks = (ntiles + kChunkTiles - 1) / kChunkTiles;
+    // at most one workgroup per chunk takes part (the others would only add
+    // contention on the chunk counter)
+    if (blockIdx.x >= nchunks) return;
     const uint32_t *tmap = w.tile_seg[lev & 1];
     const Seg *segs = w.segs[lev & 1];
     const uint32_t d = threadIdx.x;
@@ -700,7 +703,9 @@ __global__ __launch_bounds__(WG, (scatter_waves<ITEMS, WG>())) void k_scatter(Wo
 
     const uint32_t ntiles = min(w.ctl->ntiles[lev], w.max_tiles);
     const uint32_t nseg = min(w.ctl->nseg[lev], w.max_seg);
-    for (;;) {
+    // at most one workgroup per tile takes tiles (the others go straight to
+    // the set-up of the next level)
+    for (bool more = blockIdx.x < ntiles; more;) {
         // thread coordinates re-derived per tile: keeps the compiler from
         // hoisting every per-item index out of the loop (and spilling them)
         uint32_t tid = threadIdx.x;
@@ -710,7 +715,7 @@ __global__ __launch_bounds__(WG, (scatter_waves<ITEMS, WG>())) void k_scatter(Wo
         if (tid == 0) s_tile = atomicAdd(&w.ctl->tile_ctr[lev], 1u);
         __syncthreads();
         const uint32_t tile = s_tile;
-        if (tile >= ntiles) break;
+        if (tile >= ntiles) { more = false; continue; }
         const uint32_t s = w.tile_seg[lev & 1][tile];
         if (s >= nseg) continue;
         const Seg sg = w.segs[lev & 1][s];
@@ -906,6 +911,9 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
         nd = __builtin_amdgcn_raw_buffer_load_b32(r_tasks, id * (uint32_t)sizeof(Task) + (lane & 3u) * 4u, 0, 0);
     };
 
+    // at most one workgroup per task takes part (the others would only add
+    // contention on the task counter)
+    if (blockIdx.x >= ntask) return;
     // prologue: the first task's descriptor and keys, the second's descriptor,
     // the third's id; the partition counters start (and stay) at zero
     for (uint32_t i = tid; i < kRadix; i += LWG) cnt[i] = 0;
