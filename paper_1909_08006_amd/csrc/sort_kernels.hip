@@ -7,9 +7,9 @@
 //   k_extract   (key, index) tuple per record + first-digit histogram and key
 //               masks (AlphaSort-style key-pointer extraction, Section 3.2)
 //   k_hist      per level >= 1: digit histograms and key masks of big buckets
-//   k_plan      per level: bucket policy of Algorithm 1 for every big bucket
-//   k_tscan     per level: each tile's per-digit offset among its bucket's
-//               tiles, from the tile counts of the histogram pass
+//   k_plan      per level: bucket policy of Algorithm 1 for every big bucket,
+//               then each tile's per-digit offset among its bucket's tiles
+//               (from the tile counts of the histogram pass)
 //   k_scatter   per level: stable device-wide partition of big buckets by one
 //               digit (ParallelRadixSort, "cache aware scattering": tiles are
 //               ranked and staged in LDS, then written as runs)
@@ -574,16 +574,8 @@ __global__ __launch_bounds__(kWG) void k_hist(Work w, Tune tu, int lev) {
 // ---------------------------------------------------------------------------
 // k_plan: plans every big bucket of level lev (after its histogram pass)
 
-__global__ __launch_bounds__(kWG) void k_plan(Work w, Tune tu, int lev) {
-    const uint32_t nseg = min(w.ctl->nseg[lev], w.max_seg);
-    for (uint32_t s = blockIdx.x; s < nseg; s += gridDim.x) {
-        plan_segment(w, tu, lev, s);
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------------------
-// k_tscan: every tile's offset, per digit, among the tiles of its bucket
+// tile-offset scan: every tile's offset, per digit, among the tiles of its bucket
 //
 // status[tile][d] holds the tile's count of digit d (from the histogram pass);
 // this replaces it with the sum over the earlier tiles of the same bucket, so
@@ -594,14 +586,15 @@ __global__ __launch_bounds__(kWG) void k_plan(Work w, Tune tu, int lev) {
 // chunk whose last bucket starts inside it publishes an inclusive value at
 // once).
 
-__global__ __launch_bounds__(kWG) void k_tscan(Work w, int lev) {
+__device__ void tscan_chunks(const Work &w, int lev) {
     __shared__ uint32_t s_chunk;
     const uint32_t ntiles = min(w.ctl->ntiles[lev], w.max_tiles);
     const uint32_t nseg = min(w.ctl->nseg[lev], w.max_seg);
     const uint32_t nchunks = (ntiles + kChunkTiles - 1) / kChunkTiles;
     // at most one workgroup per chunk takes part (the others would only add
-    // contention on the chunk counter)
-    if (blockIdx.x >= nchunks) return;
+    // contention on the chunk counter): the last ones of the grid, which have
+    // the fewest buckets to plan first
+    if (gridDim.x - 1 - blockIdx.x >= nchunks) return;
     const uint32_t *tmap = w.tile_seg[lev & 1];
     const Seg *segs = w.segs[lev & 1];
     const uint32_t d = threadIdx.x;
@@ -675,13 +668,26 @@ __global__ __launch_bounds__(kWG) void k_tscan(Work w, int lev) {
     }
 }
 
+// k_plan: the bucket policy for every big bucket of the level (blocks take
+// buckets in a fixed stride), then the tile-offset scan (blocks take chunks
+// from a counter, so a chunk only waits on chunks already taken).  One launch
+// per level for both keeps the fixed cost of levels without big buckets low.
+__global__ __launch_bounds__(kWG) void k_plan(Work w, Tune tu, int lev) {
+    const uint32_t nseg = min(w.ctl->nseg[lev], w.max_seg);
+    for (uint32_t s = blockIdx.x; s < nseg; s += gridDim.x) {
+        plan_segment(w, tu, lev, s);
+        __syncthreads();
+    }
+    tscan_chunks(w, lev);
+}
+
 // ---------------------------------------------------------------------------
 // k_scatter: one device-wide stable partition pass of the big buckets of level lev
 
 // WG threads, ITEMS keys each (a tile is WG * ITEMS keys); the 256 digit
 // lanes of the histogram and offsets are threads 0..255.  A tile's global
 // offsets are the bucket's digit offsets plus the tile's offsets among the
-// bucket's tiles (k_tscan), so tiles never wait on each other.
+// bucket's tiles (from k_plan), so tiles never wait on each other.
 // waves per SIMD the scatter's registers are sized for: one workgroup per CU
 // when the tile's LDS staging exceeds half the LDS, else at least two
 template <int ITEMS, int WG>
@@ -1257,7 +1263,6 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
     for (int lev = 0; lev < kMaxLev; lev++) {
         if (lev > 0) k_hist<ITEMS><<<dim3(g_hist), dim3(kWG), 0, s>>>(w, t, lev);
         k_plan<<<dim3(g_plan), dim3(kWG), 0, s>>>(w, t, lev);
-        k_tscan<<<dim3(cus), dim3(kWG), 0, s>>>(w, lev);
         k_scatter<SITEMS, SWG><<<dim3(g_sc), dim3(SWG), 0, s>>>(w, t, lev);
     }
     if (ev) (void)hipEventRecord(ev[1], s);
