@@ -9,6 +9,14 @@
 // stream into a HIP graph and replayed for every batch that fits the captured
 // capacity; the per-batch request table travels host -> device before each
 // replay.
+//
+// An engine built for the serving loop ("split") captures two graphs: the
+// first runs the levels [0, kSplitLevels) and then the local sorts and the
+// gather, which stand down if deeper levels still hold big buckets; a word in
+// pinned host memory tells the loop, which then replays the second graph (the
+// remaining levels, local sorts, gather).  Inputs of uniform keys need no
+// second graph up to 2048 * 256^2 records, so a batch pays the launches of
+// kSplitLevels levels instead of all of them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +30,8 @@ namespace ley {
 
 namespace {
 
+constexpr int kSplitLevels = 3;
+
 struct BatchEngine {
     hipStream_t cap = nullptr;
     void *ws = nullptr;
@@ -31,20 +41,31 @@ struct BatchEngine {
     Tune tune{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    char *stage = nullptr;  // pinned: request table + header
+    bool split = false;
+    hipGraph_t graph2 = nullptr;   // split: the remaining levels, local sorts, gather
+    hipGraphExec_t exec2 = nullptr;
+    char *stage = nullptr;  // pinned: request table + header (+ the split flag word)
     hipEvent_t staged = nullptr;
     bool staged_pending = false;
+
+    uint32_t *flag() const {  // split: 1 when the second graph is needed
+        return reinterpret_cast<uint32_t *>(stage + (size_t)r_cap * sizeof(Req) + sizeof(Hdr));
+    }
 
     void release() {
         if (cap) (void)hipStreamSynchronize(cap);
         if (staged) (void)hipEventSynchronize(staged);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (exec2) (void)hipGraphExecDestroy(exec2);
+        if (graph2) (void)hipGraphDestroy(graph2);
         if (ws) (void)hipFree(ws);
         if (stage) (void)hipHostFree(stage);
         if (staged) (void)hipEventDestroy(staged);
         if (cap) (void)hipStreamDestroy(cap);
+        const bool keep_split = split;
         *this = BatchEngine{};
+        split = keep_split;
     }
 };
 
@@ -59,6 +80,7 @@ bool same_tune(const Tune &a, const Tune &b) {
 // (Re)builds the engine for at least n records and r requests: workspace,
 // pinned staging and the captured launch sequence.
 int engine_build(BatchEngine &E, hipStream_t user, uint64_t n, uint32_t r, const Tune &t) {
+    const bool split = E.split;
     hipError_t e;
     if (user) (void)hipStreamSynchronize(user);
     E.release();
@@ -71,20 +93,41 @@ int engine_build(BatchEngine &E, hipStream_t user, uint64_t n, uint32_t r, const
         E.ws = nullptr;
         return fail(LEYENDA_ENOMEM, "batch workspace of %zu bytes", E.L.total);
     }
+    E.split = split;
     if ((e = hipHostMalloc(reinterpret_cast<void **>(&E.stage), (size_t)E.r_cap * sizeof(Req) + sizeof(Hdr) + 256,
                            hipHostMallocDefault)) != hipSuccess)
         return fail(LEYENDA_ENOMEM, "batch staging: %s", hipGetErrorString(e));
+    *E.flag() = 0;
     if ((e = hipEventCreateWithFlags(&E.staged, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
     if ((e = hipStreamCreateWithFlags(&E.cap, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
     const Work w = bind_layout(E.L, E.ws);
     if ((e = hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t le = launch_sort_core(w, t, 0, 0, E.cap, device_cus());
-    if (le == hipSuccess) le = launch_gather_batch(w, E.cap, device_cus());
+    Stage first;
+    if (split) {
+        first.lev_end = kSplitLevels;
+        first.gate = kSplitLevels;
+        first.flag = E.flag();
+    }
+    hipError_t le = launch_sort_core(w, t, 0, 0, E.cap, device_cus(), nullptr, first);
+    if (le == hipSuccess) le = launch_gather_batch(w, E.cap, first.gate);
     e = hipStreamEndCapture(E.cap, &E.graph);
     if (le != hipSuccess) return hip_fail(le, "batch capture launches");
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     if ((e = hipGraphInstantiate(&E.exec, E.graph, nullptr, nullptr, 0)) != hipSuccess)
+        return hip_fail(e, "hipGraphInstantiate");
+    if (!split) return LEYENDA_OK;
+    Stage second;
+    second.lev_begin = kSplitLevels;
+    second.head = false;
+    if ((e = hipStreamBeginCapture(E.cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "hipStreamBeginCapture");
+    le = launch_sort_core(w, t, 0, 0, E.cap, device_cus(), nullptr, second);
+    if (le == hipSuccess) le = launch_gather_batch(w, E.cap);
+    e = hipStreamEndCapture(E.cap, &E.graph2);
+    if (le != hipSuccess) return hip_fail(le, "batch capture launches (second part)");
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    if ((e = hipGraphInstantiate(&E.exec2, E.graph2, nullptr, nullptr, 0)) != hipSuccess)
         return hip_fail(e, "hipGraphInstantiate");
     return LEYENDA_OK;
 }
@@ -159,6 +202,8 @@ int batch_sort(const leyenda_segment *segs, uint64_t count, hipStream_t s) {
     (void)total;
     const Tune t = tune_of(current_params());
     // groups of at most 65535 requests (request ids are 16-bit on the device)
+    if (count > 65535 && batch_is_split(s))
+        return fail(LEYENDA_EINVAL, "leyenda_sort_batch: a two-part engine takes at most 65535 requests");
     for (uint64_t i = 0; i < count; i += 65535) {
         int rc = batch_group(segs + i, std::min<uint64_t>(65535, count - i), s, t);
         if (rc) return rc;
@@ -168,17 +213,43 @@ int batch_sort(const leyenda_segment *segs, uint64_t count, hipStream_t s) {
 
 // Pre-sizes the batch engine of stream s (used by the serving engine so that
 // its device memory is fixed when it is created).
-int batch_reserve(hipStream_t s, uint64_t n, uint32_t r, size_t *bytes) {
+int batch_reserve(hipStream_t s, uint64_t n, uint32_t r, size_t *bytes, bool split) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     const Tune t = tune_of(current_params());
     std::lock_guard<std::mutex> lk(g_batch_mu);
     BatchEngine &E = g_batch[{dev, s}];
+    E.split = split;
     int rc = engine_build(E, s, n, std::min<uint32_t>(r, 65535u), t);
     if (rc) { E.release(); return rc; }
     if (bytes) *bytes = E.L.total;
     return LEYENDA_OK;
+}
+
+bool batch_is_split(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    auto it = g_batch.find({dev, s});
+    return it != g_batch.end() && it->second.split;
+}
+
+// After the first part of a batch on stream s has completed: replays the
+// second part if the first reported deeper levels (returns 1), else 0.
+int batch_continue_if_needed(hipStream_t s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    auto it = g_batch.find({dev, s});
+    if (it == g_batch.end() || !it->second.split || !it->second.exec2) return 0;
+    BatchEngine &E = it->second;
+    const uint32_t deep = __atomic_load_n(E.flag(), __ATOMIC_ACQUIRE);
+    if (!deep) return 0;
+    *E.flag() = 0;
+    if ((e = hipGraphLaunch(E.exec2, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch (second part)");
+    return 1;
 }
 
 uint64_t batch_bytes(uint64_t n, uint32_t r) {

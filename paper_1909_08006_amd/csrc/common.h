@@ -127,11 +127,24 @@ Work bind_layout(const Layout &L, void *base);
 // ev (optional): three events recorded after extraction, after the
 // partition levels and after the local sorts.  nreq = tiles0 = 0 launches
 // fixed grids that read every size from the device (for graph capture).
+// Part of the launch sequence.  A sort may run in two parts: the first with
+// the levels [0, gate) and a tail that stands down when level `gate` still has
+// big buckets (reported through `flag`), the second with the remaining levels
+// and the tail.
+struct Stage {
+    int lev_begin = 0, lev_end = kMaxLev;  // partition levels launched
+    bool head = true;                      // k_init + k_extract first
+    bool tail = true;                      // the local sorts after
+    int gate = kMaxLev;                    // the tail exits if level `gate` has big buckets
+    uint32_t *flag = nullptr;              // host-visible word: 1 if level `gate` has big buckets
+};
 hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
-                            hipStream_t s, int cus, hipEvent_t *ev = nullptr);
+                            hipStream_t s, int cus, hipEvent_t *ev = nullptr, const Stage &st = Stage{});
 hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,
                                 uint64_t n, hipStream_t s);
-hipError_t launch_gather_batch(const Work &w, hipStream_t s, int cus, hipEvent_t done = nullptr);  // grid-stride, sizes from the device header
+// The batch gather (sizes from the device header); exits like the tail of a
+// Stage when level `gate` has big buckets.
+hipError_t launch_gather_batch(const Work &w, hipStream_t s, int gate = kMaxLev);
 hipError_t launch_debug_extract(const uint8_t *rec, uint64_t n, uint64_t *hi, uint64_t *lo,
                                 uint32_t *hist, hipStream_t s);
 

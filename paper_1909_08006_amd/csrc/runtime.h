@@ -24,7 +24,12 @@ int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream
 
 // batch.hip
 int batch_sort(const leyenda_segment *segs, uint64_t count, hipStream_t s);
-int batch_reserve(hipStream_t s, uint64_t n, uint32_t r, size_t *bytes);
+// split: two-part launch sequence for the serving loop (see batch.hip); after
+// a batch's first part completes, batch_continue_if_needed replays the second
+// part when it is needed (returns 1), else returns 0 (negative: error).
+int batch_reserve(hipStream_t s, uint64_t n, uint32_t r, size_t *bytes, bool split = false);
+bool batch_is_split(hipStream_t s);
+int batch_continue_if_needed(hipStream_t s);
 uint64_t batch_bytes(uint64_t n, uint32_t r);
 void batch_forget(hipStream_t s);
 void batch_release_all();

@@ -117,8 +117,17 @@ static void dispatch_once(leyenda_server &S, bool *did) {
     bool retired = false;
     for (Slot &sl : S.slots) {
         if (!sl.busy) continue;
-        const hipError_t q = hipEventQuery(sl.done);
+        hipError_t q = hipEventQuery(sl.done);
         if (q == hipErrorNotReady) continue;
+        if (q == hipSuccess && S.cfg.batched) {
+            // the first part of a two-part batch: the second part if needed
+            const int c = batch_continue_if_needed(sl.s);
+            if (c == 1 && hipEventRecord(sl.done, sl.s) == hipSuccess) {
+                *did = true;
+                continue;
+            }
+            if (c != 0) q = hipErrorUnknown;
+        }
         const double t = now_s();
         for (uint64_t tag : sl.tags) {
             SReq &r = S.reqs[tag];
@@ -218,7 +227,7 @@ extern "C" int leyenda_server_create(const leyenda_server_config *cfg, leyenda_s
     for (Slot &sl : S->slots) {
         int rc;
         if (S->cfg.batched) {
-            rc = batch_reserve(sl.s, S->cfg.max_batch_records, S->cfg.max_batch, nullptr);
+            rc = batch_reserve(sl.s, S->cfg.max_batch_records, S->cfg.max_batch, nullptr, true);
         } else {
             void *ws = nullptr;
             rc = get_workspace(sl.s, plan_layout(S->cfg.max_batch_records, 1, S->tune).total, &ws);

@@ -877,7 +877,7 @@ constexpr uint64_t kLowMask48 = 0xFFFFFFFFFFFFull;
 // is by LDS atomics, not stable) down to tiny sub-buckets, whose members are
 // placed by counting smaller tuples.
 template <int LWG, int MINB>
-__global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
+__global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu, int gate) {
     constexpr int NW = LWG / 64;
     constexpr int LI = kLocalCap / LWG;
     __shared__ ulonglong2 sK[kLocalCap];  // (H, L) of each tuple, one 16-byte LDS access
@@ -891,6 +891,8 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu) {
     __shared__ int stk_n;
     __shared__ uint32_t s_next;
 
+    // a first part of a two-part sort stands down when deeper levels remain
+    if (gate < kMaxLev && w.ctl->nseg[gate] > 0) return;
     const uint32_t ntask = min(w.ctl->ntask, w.max_tasks);
     const uint32_t nreq = w.hdr->nreq;
     const uint32_t tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
@@ -1138,9 +1140,11 @@ __device__ __forceinline__ uint32_t find_req(const Req *reqs, uint32_t nreq, uin
     return lo;
 }
 
-__global__ __launch_bounds__(kWG) void k_gather(const Req *reqs, const Hdr *hdr, const uint32_t *idx) {
+__global__ __launch_bounds__(kWG) void k_gather(const Req *reqs, const Hdr *hdr, const uint32_t *idx,
+                                                const Ctl *ctl, int gate) {
     __shared__ uint32_t sidx[kWG];
     __shared__ uint32_t s_r0, s_r1;
+    if (gate < kMaxLev && ctl->nseg[gate] > 0) return;  // the second part gathers
     const uint64_t n = hdr->n_total;
     const uint32_t nreq = hdr->nreq;
     const uint64_t g0 = (uint64_t)blockIdx.x * kWG;
@@ -1244,13 +1248,22 @@ static int occupancy(const void *fn, int cus, int wg = kWG) {
     return per * cus;
 }
 
+// Reports to the host whether level `gate` has big buckets (a second part of
+// the sort is needed).  System-scope store: the host reads it after an event.
+__global__ void k_flag(Work w, int gate, uint32_t *flag) {
+    const uint32_t deep = (gate < kMaxLev && w.ctl->nseg[gate] > 0) ? 1u : 0u;
+    __hip_atomic_store(flag, deep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 template <int ITEMS, int SWG, int LWG>
 static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
-                                hipStream_t s, int cus, hipEvent_t *ev) {
-    // nreq / tiles0 == 0: sizes known only on the device (captured sequences)
-    k_init<<<dim3(nreq ? max(1u, min(nreq, 1024u)) : 1024u), dim3(kWG), 0, s>>>(w);
-    const int g_ext = tiles0 ? (int)max(1u, min(tiles0, (uint32_t)(cus * 16))) : cus * 16;
-    k_extract<ITEMS><<<dim3(g_ext), dim3(kWG), 0, s>>>(w, t);
+                                hipStream_t s, int cus, hipEvent_t *ev, const Stage &st) {
+    if (st.head) {
+        // nreq / tiles0 == 0: sizes known only on the device (captured sequences)
+        k_init<<<dim3(nreq ? max(1u, min(nreq, 1024u)) : 1024u), dim3(kWG), 0, s>>>(w);
+        const int g_ext = tiles0 ? (int)max(1u, min(tiles0, (uint32_t)(cus * 16))) : cus * 16;
+        k_extract<ITEMS><<<dim3(g_ext), dim3(kWG), 0, s>>>(w, t);
+    }
     if (ev) (void)hipEventRecord(ev[0], s);
     constexpr int SITEMS = ITEMS * kWG / SWG;  // same tile, SWG threads
     static int g_sc = 0, g_hist = 0, g_loc = 0;
@@ -1260,50 +1273,49 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
         g_loc = occupancy(reinterpret_cast<const void *>(&k_local<LWG, LWG == 512 ? 2 : 3>), cus, LWG);
     }
     const int g_plan = cus * 4;
-    for (int lev = 0; lev < kMaxLev; lev++) {
+    for (int lev = st.lev_begin; lev < st.lev_end; lev++) {
         if (lev > 0) k_hist<ITEMS><<<dim3(g_hist), dim3(kWG), 0, s>>>(w, t, lev);
         k_plan<<<dim3(g_plan), dim3(kWG), 0, s>>>(w, t, lev);
         k_scatter<SITEMS, SWG><<<dim3(g_sc), dim3(SWG), 0, s>>>(w, t, lev);
     }
+    if (st.flag) k_flag<<<dim3(1), dim3(1), 0, s>>>(w, st.gate, st.flag);
     if (ev) (void)hipEventRecord(ev[1], s);
-    k_local<LWG, LWG == 512 ? 2 : 3><<<dim3(g_loc), dim3(LWG), 0, s>>>(w, t);
+    if (st.tail) k_local<LWG, LWG == 512 ? 2 : 3><<<dim3(g_loc), dim3(LWG), 0, s>>>(w, t, st.gate);
     if (ev) (void)hipEventRecord(ev[2], s);
     return hipGetLastError();
 }
 
 template <int ITEMS, int SWG>
 static hipError_t by_local(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0, hipStream_t s, int cus,
-                           hipEvent_t *ev) {
-    return t.local_wg == 512 ? launch_levels<ITEMS, SWG, 512>(w, t, nreq, tiles0, s, cus, ev)
-                             : launch_levels<ITEMS, SWG, 256>(w, t, nreq, tiles0, s, cus, ev);
+                           hipEvent_t *ev, const Stage &st) {
+    return t.local_wg == 512 ? launch_levels<ITEMS, SWG, 512>(w, t, nreq, tiles0, s, cus, ev, st)
+                             : launch_levels<ITEMS, SWG, 256>(w, t, nreq, tiles0, s, cus, ev, st);
 }
 
 template <int ITEMS>
 static hipError_t by_scatter(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0, hipStream_t s, int cus,
-                             hipEvent_t *ev) {
+                             hipEvent_t *ev, const Stage &st) {
     switch (t.scatter_wg) {
-    case 256: return by_local<ITEMS, 256>(w, t, nreq, tiles0, s, cus, ev);
-    case 512: return by_local<ITEMS, 512>(w, t, nreq, tiles0, s, cus, ev);
-    default: return by_local<ITEMS, 1024>(w, t, nreq, tiles0, s, cus, ev);
+    case 256: return by_local<ITEMS, 256>(w, t, nreq, tiles0, s, cus, ev, st);
+    case 512: return by_local<ITEMS, 512>(w, t, nreq, tiles0, s, cus, ev, st);
+    default: return by_local<ITEMS, 1024>(w, t, nreq, tiles0, s, cus, ev, st);
     }
 }
 
 hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0, hipStream_t s,
-                            int cus, hipEvent_t *ev) {
+                            int cus, hipEvent_t *ev, const Stage &st) {
     switch (t.tile_items) {
-    case 8: return by_scatter<8>(w, t, nreq, tiles0, s, cus, ev);
-    case 16: return by_scatter<16>(w, t, nreq, tiles0, s, cus, ev);
-    default: return by_scatter<32>(w, t, nreq, tiles0, s, cus, ev);
+    case 8: return by_scatter<8>(w, t, nreq, tiles0, s, cus, ev, st);
+    case 16: return by_scatter<16>(w, t, nreq, tiles0, s, cus, ev, st);
+    default: return by_scatter<32>(w, t, nreq, tiles0, s, cus, ev, st);
     }
 }
 
-hipError_t launch_gather_batch(const Work &w, hipStream_t s, int cus, hipEvent_t done) {
-    (void)done;
-    (void)cus;
+hipError_t launch_gather_batch(const Work &w, hipStream_t s, int gate) {
     // one block per 256 records of the workspace capacity; blocks past the
     // batch's record count exit at once
     const uint64_t blocks = (w.n + kWG - 1) / kWG;
-    k_gather<<<dim3((uint32_t)(blocks < 1 ? 1 : blocks)), dim3(kWG), 0, s>>>(w.reqs, w.hdr, w.idx);
+    k_gather<<<dim3((uint32_t)(blocks < 1 ? 1 : blocks)), dim3(kWG), 0, s>>>(w.reqs, w.hdr, w.idx, w.ctl, gate);
     return hipGetLastError();
 }
 

@@ -88,3 +88,40 @@ def test_server_errors(gpu, pool):
             srv.release(5)
     finally:
         srv.close()
+
+
+def _deep_records(n, seed):
+    """Keys that keep big buckets past the third partition level: 90% share key
+    bytes 0..7 (they differ in bytes 8..9 only), the rest uniform."""
+    rec = datagen.uniform(n, seed)
+    m = int(n * 0.9)
+    rec[:m, :8] = 0x3C
+    return rec
+
+
+def test_server_second_part_for_deep_buckets(gpu):
+    """The batched server's launch sequence runs the first partition levels, then its local
+    sorts stand down and a second part runs the deeper levels when big buckets remain;
+    outputs of such requests, mixed with ordinary ones in one batch, equal the oracle's."""
+    import torch
+    deep = _deep_records(1_000_000, 301)
+    flat = datagen.uniform(200_000, 302)
+    d_deep = torch.from_numpy(deep).cuda().view(-1)
+    d_flat = torch.from_numpy(flat).cuda().view(-1)
+    srv = gpu.Server(budget_bytes=4 << 30, slots=2, max_batch=8, max_batch_records=1_500_000)
+    try:
+        srv.submit(d_flat[: 150_000 * 100], 0)
+        srv.submit(d_deep, 1)
+        srv.submit(d_flat[150_000 * 100:], 2)
+        got = {}
+        while len(got) < 3:
+            for dn in srv.poll(timeout_s=2.0):
+                assert dn["status"] == 0
+                got[dn["tag"]] = srv.output(dn).cpu().numpy()
+                srv.release(dn["tag"])
+        torch.cuda.synchronize()
+    finally:
+        srv.close()
+    np.testing.assert_array_equal(got[1], oracle.sort(deep))
+    np.testing.assert_array_equal(got[0], oracle.sort(flat[:150_000]))
+    np.testing.assert_array_equal(got[2], oracle.sort(flat[150_000:]))
