@@ -15,7 +15,6 @@ constexpr int kMaxRep = 64;        // histogram replicas per bucket (spreads the
 constexpr int kRepWords = kRadix + 8;  // replica: 256 counts + OR / OR-of-complement masks (4 x u64)
 constexpr int kMaxLev = (kKeyBits + kRB - 1) / kRB;  // device-wide partition levels at most
 constexpr int kLocalCap = 2048;    // keys per local (LDS) sort task
-constexpr int kLocalItems = kLocalCap / kWG;
 constexpr uint16_t kNoScatter = 0xFFFF;
 
 constexpr uint64_t kFlagAgg = 1ull << 62;  // look-back status: chunk aggregate published
