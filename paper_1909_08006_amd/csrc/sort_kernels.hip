@@ -53,11 +53,6 @@ __device__ __forceinline__ uint32_t ld_agent32(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint64_t lanemask_lt() {
-    const uint32_t lane = __lane_id();
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
 // Stable rank of digit d among the earlier lanes of this wave and the earlier
 // items of this wave (counted in cnt[]), over lanes with valid == true.  It is
 // split in two so that the counter updates of all of a thread's items issue
@@ -67,18 +62,25 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // `old` and the count of lower lanes with the same digit into `pk`;
 // rank_finish turns the pair into the rank.  LDS executes one wave's
 // operations in order, so items issued in key order rank in key order.
+// The lanes that share the digit come from one ballot per digit bit: a lane
+// accumulates, per 32-lane half, the lanes whose bit differs from its own
+// (n |= ballot ^ own-bit-mask, one three-input bit operation per half).
 __device__ __forceinline__ void rank_issue(uint32_t d, bool valid, uint32_t *cnt, uint32_t &old, uint32_t &pk) {
-    uint64_t peers = __ballot(valid);
+    const uint64_t vb = __ballot(valid);
+    uint32_t nlo = ~(uint32_t)vb, nhi = ~(uint32_t)(vb >> 32);  // lanes that differ (or are idle)
 #pragma unroll
     for (int b = 0; b < kRB; b++) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
+        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);  // 0 or all ones
+        const uint64_t bal = __ballot(m != 0u);
+        nlo = __builtin_amdgcn_bitop3_b32(nlo, (uint32_t)bal, m, 0xF6);  // nlo | (bal ^ m)
+        nhi = __builtin_amdgcn_bitop3_b32(nhi, (uint32_t)(bal >> 32), m, 0xF6);
     }
-    const uint32_t below = __popcll(peers & lanemask_lt());
-    const uint32_t leader = valid ? (uint32_t)__builtin_ctzll(peers) : 0u;
+    const uint32_t plo = ~nlo, phi = ~nhi;  // peers: valid lanes with the same digit
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
+    // an idle lane has no peers; it reads lane 0
+    const uint32_t leader = (uint32_t)__builtin_ctzll(((uint64_t)phi << 32) | plo | (uint64_t)!valid);
     old = 0;
-    if (valid && below == 0) old = atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+    if (valid && below == 0) old = atomicAdd(&cnt[d], (uint32_t)(__popc(plo) + __popc(phi)));
     pk = d | (leader << 8) | (below << 16);
 }
 __device__ __forceinline__ uint32_t rank_finish(uint32_t old, uint32_t pk) {
