@@ -242,8 +242,11 @@ int leyenda_sort_stats(void *stream, leyenda_stats *out);
  *   [1] device-wide partition levels (histograms, planning, scatter passes),
  *   [2] local sorts in LDS,
  *   [3] record gather,
- * and calls the number of sorts timed.  leyenda_profile_read synchronizes
- * the events it reads. */
+ * and calls the number of sorts timed.  A sort of 8 Mi records or more runs
+ * its local sorts and gathers per output part, the gather of a part on a side
+ * stream while later parts are sorted; there [2] ends with the last part's
+ * local sorts and [3] is the sum of the gather kernels' own durations, so the
+ * phases overlap.  leyenda_profile_read synchronizes the events it reads. */
 int leyenda_profile_enable(int on);
 int leyenda_profile_read(double *phase_ms, uint64_t *calls);
 

@@ -23,6 +23,9 @@ constexpr int kChunkTiles = 128;           // tiles per chunk of the tile-offset
 constexpr uint64_t kCountMask = (1ull << 62) - 1;
 
 constexpr uint8_t kTaskSorted = 1;  // task range is already in final order
+// Output parts of a large single sort: the local sorts of part k run as one
+// launch, and the gather of part k overlaps the local sorts of later parts.
+constexpr int kParts = 4;
 
 // A bucket that gets a device-wide partition pass at some level.
 struct Seg {
@@ -57,8 +60,8 @@ struct Ctl {
     uint32_t tile_ctr[kMaxLev + 2];
     uint32_t rep_ctr[kMaxLev + 2];
     uint32_t chunk_ctr[kMaxLev + 2];
-    uint32_t ntask;
-    uint32_t task_ctr;
+    uint32_t ntask[kParts];     // local-sort tasks per output part
+    uint32_t task_ctr[kParts];  // next task of each part
     uint32_t guard;
     uint32_t pad;
     unsigned long long moved[kMaxLev + 2];
@@ -105,10 +108,12 @@ struct Work {
     uint32_t *tile_seg[2];
     unsigned long long *status;  // [tile][kRadix]: digit count, then offset among the bucket's tiles
     unsigned long long *cstat;   // [chunk][kRadix]: look-back words of the tile-offset scan
-    Task *tasks;
+    Task *tasks;         // [kParts][max_tasks]
     Req *reqs;
     Hdr *hdr;
     uint64_t n;          // keys in the tuple space
+    uint64_t part_len;   // tuple positions per output part (a task joins the part of its start)
+    uint32_t nparts;     // output parts in use (1..kParts)
     uint32_t max_seg, max_tiles, max_tasks, max_reqs, max_reps;
 };
 
@@ -139,6 +144,9 @@ struct Stage {
 };
 hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
                             hipStream_t s, int cus, hipEvent_t *ev = nullptr, const Stage &st = Stage{});
+// The local sorts of the tasks of output part `part` alone (for a sort run
+// with Stage::tail false and w.nparts > 1, one launch per part in order).
+hipError_t launch_local_part(const Work &w, const Tune &t, hipStream_t s, int cus, int part);
 hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,
                                 uint64_t n, hipStream_t s);
 // The batch gather (sizes from the device header); exits like the tail of a

@@ -114,7 +114,7 @@ Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t) {
     L.off_ts1 = take((size_t)L.max_tiles * 4);
     L.off_status = take((size_t)L.max_tiles * kRadix * 8);
     L.off_cstat = take(((size_t)L.max_tiles / kChunkTiles + 1) * kRadix * 8);
-    L.off_tasks = take((size_t)L.max_tasks * sizeof(Task));
+    L.off_tasks = take((size_t)kParts * L.max_tasks * sizeof(Task));
     L.off_reqs = take((size_t)L.max_reqs * sizeof(Req));
     L.off_hdr = take(sizeof(Hdr));
     L.total = o;
@@ -142,6 +142,8 @@ Work bind_layout(const Layout &L, void *base) {
     w.reqs = reinterpret_cast<Req *>(b + L.off_reqs);
     w.hdr = reinterpret_cast<Hdr *>(b + L.off_hdr);
     w.n = L.n;
+    w.part_len = ~0ull;  // one output part unless the caller splits the sort
+    w.nparts = 1;
     w.max_seg = L.max_seg;
     w.max_tiles = L.max_tiles;
     w.max_tasks = L.max_tasks;
@@ -150,11 +152,28 @@ Work bind_layout(const Layout &L, void *base) {
     return w;
 }
 
+// Side stream of a workspace: the gathers of the output parts run there,
+// each after the local sorts of its part (events), so they overlap the local
+// sorts of the later parts.
+struct Side {
+    hipStream_t s = nullptr;
+    hipEvent_t ready[kParts] = {};
+    hipEvent_t done = nullptr;
+};
+
 struct PoolEntry {
     void *ptr = nullptr;
     size_t bytes = 0;
     Layout layout{};
+    Side side;
 };
+
+static void side_destroy(Side &sd) {
+    for (hipEvent_t &e : sd.ready)
+        if (e) (void)hipEventDestroy(e), e = nullptr;
+    if (sd.done) (void)hipEventDestroy(sd.done), sd.done = nullptr;
+    if (sd.s) (void)hipStreamDestroy(sd.s), sd.s = nullptr;
+}
 
 static std::mutex g_pool_mu;
 static std::map<std::pair<int, hipStream_t>, PoolEntry> g_pool;
@@ -196,6 +215,27 @@ int remember_layout(hipStream_t stream, const Layout &L) {
     return LEYENDA_OK;
 }
 
+// The side stream and events of the workspace of `stream` (created on first use).
+static int get_side(hipStream_t stream, Side **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    Side &sd = g_pool[{dev, stream}].side;
+    if (!sd.s) {
+        e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking);
+        for (int k = 0; k < kParts && e == hipSuccess; k++)
+            e = hipEventCreateWithFlags(&sd.ready[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            side_destroy(sd);
+            return hip_fail(e, "side stream");
+        }
+    }
+    *out = &sd;
+    return LEYENDA_OK;
+}
+
 static int find_workspace(hipStream_t stream, void **ptr, Layout *L) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return LEYENDA_EHIP;
@@ -214,7 +254,9 @@ void pool_forget(hipStream_t stream) {
     auto it = g_pool.find({dev, stream});
     if (it == g_pool.end()) return;
     (void)hipStreamSynchronize(stream);
+    if (it->second.side.s) (void)hipStreamSynchronize(it->second.side.s);
     if (it->second.ptr) (void)hipFree(it->second.ptr);
+    side_destroy(it->second.side);
     g_pool.erase(it);
 }
 
@@ -225,6 +267,7 @@ int release_all() {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     for (auto &kv : g_pool) {
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+        side_destroy(kv.second.side);
     }
     g_pool.clear();
     return LEYENDA_OK;
@@ -265,8 +308,13 @@ __global__ void k_setup_single(Req *reqs, Hdr *hdr, const uint8_t *in, uint8_t *
 // ---------------------------------------------------------------------------
 // phase timing with HIP events on the sort's own stream
 
+// e: sort start, after extraction, after the levels, after the local sorts,
+// end.  When the gather runs per output part on the side stream, g holds an
+// event pair around each part's gather and the gather phase is their sum.
 struct ProfCall {
     hipEvent_t e[5];
+    hipEvent_t g[2 * kParts];
+    int ng = 0;
 };
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
@@ -300,16 +348,27 @@ static int prof_drain() {
     for (auto &pc : g_prof_pending) {
         hipError_t e = hipEventSynchronize(pc.e[4]);
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-        for (int i = 0; i < 4; i++) {
+        for (int i = 0; i < (pc.ng ? 3 : 4); i++) {
             float ms = 0;
             if (hipEventElapsedTime(&ms, pc.e[i], pc.e[i + 1]) == hipSuccess) g_prof_ms[i] += ms;
         }
+        for (int k = 0; k < pc.ng; k++) {
+            float ms = 0;
+            if (hipEventSynchronize(pc.g[2 * k + 1]) == hipSuccess &&
+                hipEventElapsedTime(&ms, pc.g[2 * k], pc.g[2 * k + 1]) == hipSuccess)
+                g_prof_ms[3] += ms;
+        }
         g_prof_calls++;
         for (int i = 0; i < 5; i++) (void)hipEventDestroy(pc.e[i]);
+        for (int i = 0; i < 2 * pc.ng; i++) (void)hipEventDestroy(pc.g[i]);
     }
     g_prof_pending.clear();
     return LEYENDA_OK;
 }
+
+// Output parts of a single sort of n records: one below 8 Mi records (the
+// overlap would not pay for the extra launches), else kParts.
+static uint32_t parts_for(uint64_t n) { return n < (8ull << 20) ? 1u : (uint32_t)kParts; }
 
 int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t) {
     const Layout L = plan_layout(n, 1, t);
@@ -328,12 +387,53 @@ int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream
     const bool prof = prof_start(&pc, stream);
     k_setup_single<<<1, 1, 0, stream>>>(w.reqs, w.hdr, static_cast<const uint8_t *>(records_dev),
                                         static_cast<uint8_t *>(out_dev), n, tiles0);
-    hipError_t e = launch_sort_core(w, t, 1, tiles0, stream, device_cus(), prof ? pc.e + 1 : nullptr);
-    if (e != hipSuccess) return hip_fail(e, "sort kernels");
-    e = launch_gather_single(static_cast<const uint8_t *>(records_dev), n, w.idx, static_cast<uint8_t *>(out_dev),
-                             n, stream);
+    const uint32_t K = parts_for(n);
+    if (K == 1) {
+        hipError_t e = launch_sort_core(w, t, 1, tiles0, stream, device_cus(), prof ? pc.e + 1 : nullptr);
+        if (e != hipSuccess) return hip_fail(e, "sort kernels");
+        e = launch_gather_single(static_cast<const uint8_t *>(records_dev), n, w.idx,
+                                 static_cast<uint8_t *>(out_dev), n, stream);
+        if (prof) prof_finish(pc, stream);
+        if (e != hipSuccess) return hip_fail(e, "gather kernel");
+        return LEYENDA_OK;
+    }
+    // K output parts: the local sorts of part k, then (side stream) its gather
+    Side *sd = nullptr;
+    int rc = get_side(stream, &sd);
+    if (rc) return rc;
+    Work wp = w;
+    wp.nparts = K;
+    wp.part_len = (n + K - 1) / K;
+    bool pg = false;  // per-part gather events (else the gather phase is what follows the local sorts)
+    if (prof) {
+        int made = 0;
+        while (made < (int)(2 * K) && hipEventCreate(&pc.g[made]) == hipSuccess) made++;
+        if (made == (int)(2 * K)) {
+            pc.ng = (int)K;
+            pg = true;
+        } else {
+            for (int i = 0; i < made; i++) (void)hipEventDestroy(pc.g[i]);
+        }
+    }
+    Stage st;
+    st.tail = false;
+    hipError_t e = launch_sort_core(wp, t, 1, tiles0, stream, device_cus(), prof ? pc.e + 1 : nullptr, st);
+    const uint8_t *rec = static_cast<const uint8_t *>(records_dev);
+    uint8_t *out = static_cast<uint8_t *>(out_dev);
+    for (uint32_t k = 0; k < K && e == hipSuccess; k++) {
+        const uint64_t c0 = k * wp.part_len, c1 = std::min<uint64_t>(n, c0 + wp.part_len);
+        e = launch_local_part(wp, t, stream, device_cus(), (int)k);
+        if (e == hipSuccess) e = hipEventRecord(sd->ready[k], stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sd->s, sd->ready[k], 0);
+        if (e == hipSuccess && pg) e = hipEventRecord(pc.g[2 * k], sd->s);
+        if (e == hipSuccess && c1 > c0) e = launch_gather_single(rec, n, w.idx + c0, out + c0 * kRec, c1 - c0, sd->s);
+        if (e == hipSuccess && pg) e = hipEventRecord(pc.g[2 * k + 1], sd->s);
+    }
+    if (e == hipSuccess && prof) e = hipEventRecord(pc.e[3], stream);
+    if (e == hipSuccess) e = hipEventRecord(sd->done, sd->s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(stream, sd->done, 0);
     if (prof) prof_finish(pc, stream);
-    if (e != hipSuccess) return hip_fail(e, "gather kernel");
+    if (e != hipSuccess) return hip_fail(e, "sort kernels");
     return LEYENDA_OK;
 }
 
@@ -416,7 +516,8 @@ extern "C" int leyenda_sort_stats(void *stream, leyenda_stats *out) {
         out->moved[l] = c.moved[l];
         if (c.moved[l]) out->levels = l + 1;
     }
-    out->tasks = c.ntask;
+    out->tasks = 0;
+    for (int p = 0; p < kParts; p++) out->tasks += c.ntask[p];
     out->guard = c.guard;
     return LEYENDA_OK;
 }

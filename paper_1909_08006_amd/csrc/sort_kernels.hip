@@ -155,27 +155,42 @@ __device__ __forceinline__ bool seg_ok(const Work &w, const Seg &sg, uint32_t ti
 // digit, small ones go to the task queue, tiny ones are sorted by comparison
 // inside the local sort).  Called by all threads of a workgroup.
 
+// Output part of a task starting at tuple position `start`.
+__device__ __forceinline__ uint32_t part_of(const Work &w, uint64_t start) {
+    return (uint32_t)min<uint64_t>(w.nparts - 1, start / w.part_len);
+}
+
 __device__ void emit_task(const Work &w, uint64_t start, uint32_t count, uint8_t buf, uint8_t flags,
                           uint16_t req) {
-    const uint32_t j = atomicAdd(&w.ctl->ntask, 1u);
+    const uint32_t p = part_of(w, start);
+    const uint32_t j = atomicAdd(&w.ctl->ntask[p], 1u);
     if (j >= w.max_tasks) { atomicOr(&w.ctl->guard, 1u); return; }
     Task t;
     t.start = start; t.count = count; t.buf = buf; t.flags = flags; t.req = req;
-    w.tasks[j] = t;
+    w.tasks[(size_t)p * w.max_tasks + j] = t;
 }
 
 // A range whose keys are all equal is already in final (index) order; it is
-// cut into local-capacity chunks so each task stays bounded.
+// cut into local-capacity chunks so each task stays bounded.  Consecutive
+// chunks of one output part take their slots with one atomic.
 __device__ void emit_sorted(const Work &w, uint64_t start, uint64_t count, uint8_t buf, uint16_t req) {
     const uint64_t nch = (count + kLocalCap - 1) / kLocalCap;
-    const uint32_t j0 = atomicAdd(&w.ctl->ntask, (uint32_t)nch);
-    if ((uint64_t)j0 + nch > w.max_tasks) { atomicOr(&w.ctl->guard, 2u); return; }
-    for (uint64_t k = 0; k < nch; k++) {
-        Task t;
-        t.start = start + k * kLocalCap;
-        t.count = (uint32_t)min<uint64_t>(kLocalCap, count - k * kLocalCap);
-        t.buf = buf; t.flags = kTaskSorted; t.req = req;
-        w.tasks[j0 + k] = t;
+    for (uint64_t k0 = 0; k0 < nch;) {
+        const uint32_t p = part_of(w, start + k0 * kLocalCap);
+        // first chunk that starts in a later part
+        const uint64_t k1 = p + 1 >= w.nparts
+                                ? nch
+                                : min(nch, ((p + 1) * w.part_len - start + kLocalCap - 1) / kLocalCap);
+        const uint32_t j0 = atomicAdd(&w.ctl->ntask[p], (uint32_t)(k1 - k0));
+        if ((uint64_t)j0 + (k1 - k0) > w.max_tasks) { atomicOr(&w.ctl->guard, 2u); return; }
+        for (uint64_t k = k0; k < k1; k++) {
+            Task t;
+            t.start = start + k * kLocalCap;
+            t.count = (uint32_t)min<uint64_t>(kLocalCap, count - k * kLocalCap);
+            t.buf = buf; t.flags = kTaskSorted; t.req = req;
+            w.tasks[(size_t)p * w.max_tasks + j0 + (k - k0)] = t;
+        }
+        k0 = k1;
     }
 }
 
@@ -291,7 +306,8 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
     __shared__ unsigned long long p_mask[4];
     __shared__ uint32_t p_tstart[kRadix];
     __shared__ uint32_t p_tcnt[kRadix];
-    __shared__ uint32_t p_ntask, p_slot;
+    __shared__ uint32_t p_ntask;
+    __shared__ uint32_t p_pcnt[kParts], p_pfirst[kParts], p_pslot[kParts];
     const uint32_t d = threadIdx.x;
     Seg *sp = &w.segs[lev & 1][s];
     const Seg sg = *sp;
@@ -366,18 +382,35 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
             if (d == 0) { p_tstart[nt] = cur_start; p_tcnt[nt] = cur; }
             nt++;
         }
-        if (d == 0) {
-            uint32_t slot = atomicAdd(&w.ctl->ntask, nt);
-            if ((uint64_t)slot + nt > w.max_tasks) { atomicOr(&w.ctl->guard, 1u); nt = 0; }
-            p_ntask = nt;
-            p_slot = slot;
+        if (d == 0) p_ntask = nt;
+    }
+    if (d < kParts) { p_pcnt[d] = 0; p_pfirst[d] = 0xFFFFFFFFu; }
+    __syncthreads();
+    // the tasks' output parts: their starts increase with t, so each part is a
+    // run of consecutive tasks; one slot allocation per run
+    const uint32_t ntk = p_ntask;
+    for (uint32_t t = d; t < ntk; t += kWG) {
+        const uint32_t pt = part_of(w, sg.start + p_tstart[t]);
+        atomicAdd(&p_pcnt[pt], 1u);
+        atomicMin(&p_pfirst[pt], t);
+    }
+    __syncthreads();
+    if (d < kParts && p_pcnt[d]) {
+        const uint32_t slot = atomicAdd(&w.ctl->ntask[d], p_pcnt[d]);
+        if ((uint64_t)slot + p_pcnt[d] > w.max_tasks) {
+            atomicOr(&w.ctl->guard, 1u);
+            p_pslot[d] = 0xFFFFFFFFu;
+        } else {
+            p_pslot[d] = slot;
         }
     }
     __syncthreads();
-    for (uint32_t t = d; t < p_ntask; t += kWG) {
+    for (uint32_t t = d; t < ntk; t += kWG) {
+        const uint32_t pt = part_of(w, sg.start + p_tstart[t]);
+        if (p_pslot[pt] == 0xFFFFFFFFu) continue;
         Task tk;
         tk.start = sg.start + p_tstart[t]; tk.count = p_tcnt[t]; tk.buf = cbuf; tk.flags = 0; tk.req = sg.req;
-        w.tasks[p_slot + t] = tk;
+        w.tasks[(size_t)pt * w.max_tasks + p_pslot[pt] + (t - p_pfirst[pt])] = tk;
     }
     __syncthreads();
 }
@@ -879,7 +912,7 @@ constexpr uint64_t kLowMask48 = 0xFFFFFFFFFFFFull;
 // is by LDS atomics, not stable) down to tiny sub-buckets, whose members are
 // placed by counting smaller tuples.
 template <int LWG, int MINB>
-__global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu, int gate) {
+__global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu, int gate, int part) {
     constexpr int NW = LWG / 64;
     constexpr int LI = kLocalCap / LWG;
     __shared__ ulonglong2 sK[kLocalCap];  // (H, L) of each tuple, one 16-byte LDS access
@@ -895,10 +928,12 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu, int gate) 
 
     // a first part of a two-part sort stands down when deeper levels remain
     if (gate < kMaxLev && w.ctl->nseg[gate] > 0) return;
-    const uint32_t ntask = min(w.ctl->ntask, w.max_tasks);
+    const uint32_t ntask = min(w.ctl->ntask[part], w.max_tasks);
+    uint32_t *const task_ctr = &w.ctl->task_ctr[part];
     const uint32_t nreq = w.hdr->nreq;
     const uint32_t tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-    const __amdgpu_buffer_rsrc_t r_tasks = rsrc_of(w.tasks, ntask * (uint32_t)sizeof(Task));
+    const __amdgpu_buffer_rsrc_t r_tasks =
+        rsrc_of(w.tasks + (size_t)part * w.max_tasks, ntask * (uint32_t)sizeof(Task));
     const __amdgpu_buffer_rsrc_t r_reqs = rsrc_of(w.reqs, nreq * (uint32_t)sizeof(Req));
 
     uint64_t ph[LI], pl[LI];  // keys of the task after the current one
@@ -927,7 +962,7 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu, int gate) 
     // prologue: the first task's descriptor and keys, the second's descriptor,
     // the third's id; the partition counters start (and stay) at zero
     for (uint32_t i = tid; i < kRadix; i += LWG) cnt[i] = 0;
-    if (tid == 0) s_next = atomicAdd(&w.ctl->task_ctr, 1u);
+    if (tid == 0) s_next = atomicAdd(task_ctr, 1u);
     __syncthreads();
     uint32_t j = ufirst(s_next);
     if (j >= ntask) return;
@@ -935,12 +970,12 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu, int gate) 
     LTask cur = task_of(w, nd);
     issue_keys(cur);
     __syncthreads();
-    if (tid == 0) s_next = atomicAdd(&w.ctl->task_ctr, 1u);
+    if (tid == 0) s_next = atomicAdd(task_ctr, 1u);
     __syncthreads();
     uint32_t jn = ufirst(s_next);
     issue_desc(jn);
     __syncthreads();
-    if (tid == 0) s_next = atomicAdd(&w.ctl->task_ctr, 1u);
+    if (tid == 0) s_next = atomicAdd(task_ctr, 1u);
     __syncthreads();
     LTask nxt = task_of(w, nd);
 
@@ -975,7 +1010,7 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu, int gate) 
         // the id three tasks ahead (consumed after the sort), then the next
         // task's keys, then the descriptor of the one after
         uint32_t ahead = 0;
-        if (tid == 0) ahead = atomicAdd(&w.ctl->task_ctr, 1u);
+        if (tid == 0) ahead = atomicAdd(task_ctr, 1u);
         issue_keys(nxt);
         __syncthreads();
         const uint32_t jnn = ufirst(s_next);
@@ -1282,7 +1317,7 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
     }
     if (st.flag) k_flag<<<dim3(1), dim3(1), 0, s>>>(w, st.gate, st.flag);
     if (ev) (void)hipEventRecord(ev[1], s);
-    if (st.tail) k_local<LWG, LWG == 512 ? 2 : 3><<<dim3(g_loc), dim3(LWG), 0, s>>>(w, t, st.gate);
+    if (st.tail) k_local<LWG, LWG == 512 ? 2 : 3><<<dim3(g_loc), dim3(LWG), 0, s>>>(w, t, st.gate, 0);
     if (ev) (void)hipEventRecord(ev[2], s);
     return hipGetLastError();
 }
@@ -1319,6 +1354,20 @@ hipError_t launch_gather_batch(const Work &w, hipStream_t s, int gate) {
     const uint64_t blocks = (w.n + kWG - 1) / kWG;
     k_gather<<<dim3((uint32_t)(blocks < 1 ? 1 : blocks)), dim3(kWG), 0, s>>>(w.reqs, w.hdr, w.idx, w.ctl, gate);
     return hipGetLastError();
+}
+
+template <int LWG>
+static hipError_t local_part(const Work &w, const Tune &t, hipStream_t s, int cus, int part) {
+    constexpr int MINB = LWG == 512 ? 2 : 3;
+    static int g_loc = 0;
+    if (!g_loc) g_loc = occupancy(reinterpret_cast<const void *>(&k_local<LWG, MINB>), cus, LWG);
+    k_local<LWG, MINB><<<dim3(g_loc), dim3(LWG), 0, s>>>(w, t, kMaxLev, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_local_part(const Work &w, const Tune &t, hipStream_t s, int cus, int part) {
+    if (part < 0 || part >= (int)w.nparts) return hipErrorInvalidValue;
+    return t.local_wg == 512 ? local_part<512>(w, t, s, cus, part) : local_part<256>(w, t, s, cus, part);
 }
 
 hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,
