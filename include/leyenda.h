@@ -73,6 +73,14 @@ int leyenda_sort(const void *records_dev, uint64_t n, void *out_dev, void *strea
  * current parameters (tuple buffers, index array, bucket tables). */
 uint64_t leyenda_workspace_bytes(uint64_t n);
 
+/* Output parts a leyenda_sort of n records runs in: 1 below 8 Mi records,
+ * else 4.  With several parts the local sorts are launched once per part, in
+ * output order, and each part's record gather runs on a side stream of the
+ * sort's stream as soon as that part is sorted, overlapping the local sorts of
+ * the later parts; the sort's stream waits for every gather before it
+ * continues, so callers see one ordered operation.  Pure function. */
+uint32_t leyenda_sort_parts(uint64_t n);
+
 /* ---------------------------------------------------------------------------
  * Limited-memory (external) sort -- Section 3.2, "Overlapping Computation with
  * I/O": a sort stage that sorts chunks into sorted intermediate runs, then a

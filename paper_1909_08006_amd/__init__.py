@@ -74,6 +74,7 @@ def load():
     sig = {
         "leyenda_sort": ([vp, u64, vp, vp], i32),
         "leyenda_workspace_bytes": ([u64], u64),
+        "leyenda_sort_parts": ([u64], ctypes.c_uint32),
         "leyenda_sort_runs": ([vp, u64, u64, vp, P64, u64, P64, vp], i32),
         "leyenda_merge": ([vp, P64, u64, vp, u64, vp], i32),
         "leyenda_plan_runs": ([u64, u64, P64, P64], i32),
@@ -148,6 +149,12 @@ def sort(records, out=None, stream=None):
 
 def workspace_bytes(n: int) -> int:
     return int(load().leyenda_workspace_bytes(n))
+
+
+def sort_parts(n: int) -> int:
+    """Output parts a sort of n records runs in (local sorts and gathers are
+    launched once per part; the gathers overlap later parts' local sorts)."""
+    return int(load().leyenda_sort_parts(n))
 
 
 def plan_runs(n: int, budget_bytes: int) -> tuple[int, int]:

@@ -451,6 +451,8 @@ extern "C" int leyenda_sort(const void *records_dev, uint64_t n, void *out_dev, 
     return sort_device(records_dev, n, out_dev, static_cast<hipStream_t>(stream), tune_of(current_params()));
 }
 
+extern "C" uint32_t leyenda_sort_parts(uint64_t n) { return parts_for(n); }
+
 extern "C" uint64_t leyenda_workspace_bytes(uint64_t n) {
     return plan_layout(n, 1, tune_of(current_params())).total;
 }

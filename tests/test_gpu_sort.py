@@ -188,6 +188,20 @@ def test_small_tiles_many_chunks(gpu):
         gpu.set_params(**old)
 
 
+@pytest.mark.parametrize("name", ["uniform", "few_distinct", "all_equal"])
+def test_output_parts(gpu, name):
+    """8,400,953 records: above the 8 Mi threshold the local sorts run per output
+    part (four) with each part's gather on a side stream.  Equal-key ranges
+    (16 keys; one key) span part boundaries."""
+    import torch
+    n = 8_388_608 + 12_345
+    rec = datagen.uniform(n, 94) if name == "uniform" else pattern(name, n)
+    got = run_sort(gpu, rec)
+    assert_same(got, oracle.sort(rec), f"parts {name}")
+    st = gpu.stats(torch.cuda.current_stream())
+    assert st["guard"] == 0 and st["tasks"] > 0
+
+
 def test_stats_uniform(gpu):
     import torch
     rec = datagen.uniform(1_000_000, 1)

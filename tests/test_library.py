@@ -32,6 +32,12 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_sort_parts_rule():
+    import paper_1909_08006_amd as ley
+    assert [ley.sort_parts(n) for n in (0, 1, 8 * 2**20 - 1)] == [1, 1, 1]
+    assert [ley.sort_parts(n) for n in (8 * 2**20, 10**8, 10**9)] == [4, 4, 4]
+
+
 def test_status_strings_and_param_checks():
     import paper_1909_08006_amd as ley
     lib = ley.load()
