@@ -301,7 +301,10 @@ struct Pipe {
         for (auto &row : ev)
             for (auto &x : row)
                 if (x) (void)hipEventDestroy(x);
-        if (cs) (void)hipStreamDestroy(cs);
+        if (cs) {
+            pool_forget(cs);  // the side stream a large run's sort made for cs
+            (void)hipStreamDestroy(cs);
+        }
         if (h2d) (void)hipStreamDestroy(h2d);
         if (d2h) (void)hipStreamDestroy(d2h);
     }
