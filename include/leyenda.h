@@ -199,6 +199,9 @@ int leyenda_serve_replay(const leyenda_server_config *cfg, uint64_t count, const
 
 /* ---------------------------------------------------------------------------
  * Tuning parameters.  They change speed only, never the output bytes.
+ * Defaults: digit_bits 8, tile_items 32, big_threshold 2048, tiny_threshold 64,
+ * local_capacity 2048, scatter_threads 1024, local_threads 512 (the fastest of
+ * the autotuner's sweep on the 10 GB uniform and 20 GB skewed workloads).
  * digit_bits     radix digit width in bits (8: 256 buckets per pass, Algorithm 1).
  * tile_items     keys per thread in a device-wide partition tile (8, 16 or 32;
  *                a tile is 256 * tile_items keys).

@@ -40,7 +40,7 @@ int hip_fail(hipError_t e, const char *what) {
 // parameters
 
 static std::mutex g_param_mu;
-static leyenda_params g_params = {8, 32, 2048, 32, 2048, 1024, 256};
+static leyenda_params g_params = {8, 32, 2048, 64, 2048, 1024, 512};
 
 leyenda_params current_params() {
     std::lock_guard<std::mutex> lk(g_param_mu);
