@@ -311,8 +311,8 @@ def main() -> int:
         "roofline": {"bound": "hbm", "kernel": KERNEL_OF[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "launches_per_sort": launches, "records_per_launch": n // launches,
-                     "alg_bytes_per_launch": int(alg[dom] / launches),
+                     "launches_per_sort": launches, "records_per_launch_avg": n // launches,
+                     "alg_bytes_per_launch_avg": int(alg[dom] / launches),
                      "avg_launch_ms": round(avg[dom] / launches, 4)},
         "phases_ms": {k: round(v, 4) for k, v in avg.items()},
         "phase_alg_gbs": {k: round(alg[k] / (avg[k] / 1e3) / 1e9, 1) for k in avg if avg[k] > 0},

@@ -112,8 +112,9 @@ struct Work {
     Req *reqs;
     Hdr *hdr;
     uint64_t n;          // keys in the tuple space
-    uint64_t part_len;   // tuple positions per output part (a task joins the part of its start)
-    uint32_t nparts;     // output parts in use (1..kParts)
+    uint64_t part_end[kParts];  // output part k ends before tuple position part_end[k]; a task
+                                // joins the part of its start (entries past nparts unused)
+    uint32_t nparts;            // output parts in use (1..kParts)
     uint32_t max_seg, max_tiles, max_tasks, max_reqs, max_reps;
 };
 

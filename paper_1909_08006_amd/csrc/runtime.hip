@@ -142,7 +142,7 @@ Work bind_layout(const Layout &L, void *base) {
     w.reqs = reinterpret_cast<Req *>(b + L.off_reqs);
     w.hdr = reinterpret_cast<Hdr *>(b + L.off_hdr);
     w.n = L.n;
-    w.part_len = ~0ull;  // one output part unless the caller splits the sort
+    for (uint64_t &e : w.part_end) e = ~0ull;  // one output part unless the caller splits the sort
     w.nparts = 1;
     w.max_seg = L.max_seg;
     w.max_tiles = L.max_tiles;
@@ -370,6 +370,17 @@ static int prof_drain() {
 // overlap would not pay for the extra launches), else kParts.
 static uint32_t parts_for(uint64_t n) { return n < (8ull << 20) ? 1u : (uint32_t)kParts; }
 
+// Ends of the K output parts: the first parts small, so the first gather
+// starts early, the last one large (a gather takes several times longer per
+// record than the local sort, so the later local sorts finish under the
+// earlier gathers).  Fractions of n: 1/16, 1/16, 1/8, 3/4 (measured against
+// equal quarters and three other splits on the 10 GB sort: 10.97 against
+// 11.01-11.09 ms).
+static void part_bounds(uint64_t n, uint32_t K, uint64_t *end) {
+    static const uint32_t kEnd16[kParts] = {1, 2, 4, 16};  // in sixteenths of n
+    for (uint32_t k = 0; k < K; k++) end[k] = k + 1 == K ? n : n * kEnd16[k] / 16;
+}
+
 int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t) {
     const Layout L = plan_layout(n, 1, t);
     void *ws = nullptr;
@@ -403,7 +414,7 @@ int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream
     if (rc) return rc;
     Work wp = w;
     wp.nparts = K;
-    wp.part_len = (n + K - 1) / K;
+    part_bounds(n, K, wp.part_end);
     bool pg = false;  // per-part gather events (else the gather phase is what follows the local sorts)
     if (prof) {
         int made = 0;
@@ -421,7 +432,7 @@ int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream
     const uint8_t *rec = static_cast<const uint8_t *>(records_dev);
     uint8_t *out = static_cast<uint8_t *>(out_dev);
     for (uint32_t k = 0; k < K && e == hipSuccess; k++) {
-        const uint64_t c0 = k * wp.part_len, c1 = std::min<uint64_t>(n, c0 + wp.part_len);
+        const uint64_t c0 = k ? wp.part_end[k - 1] : 0, c1 = wp.part_end[k];
         e = launch_local_part(wp, t, stream, device_cus(), (int)k);
         if (e == hipSuccess) e = hipEventRecord(sd->ready[k], stream);
         if (e == hipSuccess) e = hipStreamWaitEvent(sd->s, sd->ready[k], 0);

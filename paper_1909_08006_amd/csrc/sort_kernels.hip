@@ -157,7 +157,9 @@ __device__ __forceinline__ bool seg_ok(const Work &w, const Seg &sg, uint32_t ti
 
 // Output part of a task starting at tuple position `start`.
 __device__ __forceinline__ uint32_t part_of(const Work &w, uint64_t start) {
-    return (uint32_t)min<uint64_t>(w.nparts - 1, start / w.part_len);
+    uint32_t p = 0;
+    while (p + 1 < w.nparts && start >= w.part_end[p]) p++;
+    return p;
 }
 
 __device__ void emit_task(const Work &w, uint64_t start, uint32_t count, uint8_t buf, uint8_t flags,
@@ -180,7 +182,7 @@ __device__ void emit_sorted(const Work &w, uint64_t start, uint64_t count, uint8
         // first chunk that starts in a later part
         const uint64_t k1 = p + 1 >= w.nparts
                                 ? nch
-                                : min(nch, ((p + 1) * w.part_len - start + kLocalCap - 1) / kLocalCap);
+                                : min(nch, (w.part_end[p] - start + kLocalCap - 1) / kLocalCap);
         const uint32_t j0 = atomicAdd(&w.ctl->ntask[p], (uint32_t)(k1 - k0));
         if ((uint64_t)j0 + (k1 - k0) > w.max_tasks) { atomicOr(&w.ctl->guard, 2u); return; }
         for (uint64_t k = k0; k < k1; k++) {
