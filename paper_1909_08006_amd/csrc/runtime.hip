@@ -400,7 +400,11 @@ int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream
                                         static_cast<uint8_t *>(out_dev), n, tiles0);
     const uint32_t K = parts_for(n);
     if (K == 1) {
-        hipError_t e = launch_sort_core(w, t, 1, tiles0, stream, device_cus(), prof ? pc.e + 1 : nullptr);
+        // at most big_threshold records: the one level-0 bucket becomes a local
+        // task as it is, so no deeper level can hold a bucket; launch level 0 only
+        Stage st;
+        if (n <= t.big) st.lev_end = 1;
+        hipError_t e = launch_sort_core(w, t, 1, tiles0, stream, device_cus(), prof ? pc.e + 1 : nullptr, st);
         if (e != hipSuccess) return hip_fail(e, "sort kernels");
         e = launch_gather_single(static_cast<const uint8_t *>(records_dev), n, w.idx,
                                  static_cast<uint8_t *>(out_dev), n, stream);
