@@ -375,10 +375,6 @@ struct Bounce {
 // (so upload, sort and download overlap) plus the sort's workspace.
 uint64_t run_bytes(uint64_t r, const Tune &t) { return 4 * a256(r * kRec) + plan_layout(r, 1, t).total + 4096; }
 
-// Device bytes per merge chunk of c records: two staging and two output
-// buffers plus two tuple buffers (16 bytes per record each).
-uint64_t chunk_bytes(uint64_t c) { return 4 * a256(c * kRec) + 4 * a256(c * 8) + 4096; }
-
 int plan_runs_t(uint64_t n, uint64_t budget, const Tune &t, uint64_t *R, uint64_t *K) {
     if (n == 0) { *R = 0; *K = 0; return LEYENDA_OK; }
     uint64_t lo = 1, hi = std::min<uint64_t>(n, LEYENDA_MAX_RECORDS);

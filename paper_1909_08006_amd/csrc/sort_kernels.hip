@@ -923,7 +923,6 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu, int gate, 
     __shared__ uint32_t lbase[kRadix];
     __shared__ uint32_t ltot[kRadix];
     __shared__ uint32_t stk[kStack];
-    __shared__ uint32_t tmp[NW];
     __shared__ uint64_t orh[NW], andh[NW], orl[NW], andl[NW];
     __shared__ int stk_n;
     __shared__ uint32_t s_next;
