@@ -417,6 +417,17 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
     __syncthreads();
 }
 
+// Adds digit d of the valid lanes into the LDS histogram sh; called by the
+// whole wave, the valid lanes being a prefix of it.  Lanes that share the
+// first lane's digit add once, through the lowest of them: with skewed keys
+// whole waves fall on one digit, and per-lane atomics on one counter serialize.
+__device__ __forceinline__ void hist_add(uint32_t *sh, uint32_t d, bool valid) {
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+    const uint64_t same = __ballot(valid && d == d0);
+    if (valid && d != d0) atomicAdd(&sh[d], 1u);
+    if (same && __lane_id() == (uint32_t)__builtin_ctzll(same)) atomicAdd(&sh[d0], (uint32_t)__popcll(same));
+}
+
 // Adds a tile's LDS histogram and key masks into one replica of its bucket,
 // and stores the tile's digit counts.
 __device__ __forceinline__ void flush_tile_hist(uint32_t *rep, const uint32_t *sh, const unsigned long long *smask,
@@ -510,6 +521,7 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
 #pragma unroll
             for (int u = 0; u < RI; u++) {
                 const uint32_t q = (r0 + u) * kWG + threadIdx.x;
+                a[u] = b[u] = c[u] = 0;
                 if (q < nvalid) {
                     // the caller's records are device memory: global (not flat)
                     // loads, marked non-temporal (each line is read once here)
@@ -522,15 +534,16 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
 #pragma unroll
             for (int u = 0; u < RI; u++) {
                 const uint32_t q = (r0 + u) * kWG + threadIdx.x;
-                if (q < nvalid) {
-                    const uint64_t h = __builtin_bswap64(((uint64_t)b[u] << 32) | a[u]);
+                const bool valid = q < nvalid;
+                const uint64_t h = __builtin_bswap64(((uint64_t)b[u] << 32) | a[u]);
+                if (valid) {
                     const uint64_t k16 = __builtin_bswap16((uint16_t)(c[u] & 0xFFFFu));
                     // tuples: written once, read by the next pass (far beyond the caches)
                     __builtin_nontemporal_store(h, H + q);
                     __builtin_nontemporal_store((k16 << 32) | (uint32_t)(local0 + q), L + q);
-                    atomicAdd(&sh[h >> 56], 1u);
                     oh |= h; onh |= ~h; ol |= k16; onl |= (~k16) & 0xFFFFu;
                 }
+                hist_add(sh, (uint32_t)(h >> 56), valid);
             }
         }
         block_masks(oh, onh, ol, onl, smask);
@@ -590,8 +603,8 @@ __global__ __launch_bounds__(kWG) void k_hist(Work w, Tune tu, int lev) {
 #pragma unroll
             for (int u = 0; u < RI; u++) {
                 const uint32_t q = (r0 + u) * kWG + threadIdx.x;
+                hist_add(sh, digit_at(h[u], l[u], sg.pos), q < nvalid);
                 if (q < nvalid) {
-                    atomicAdd(&sh[digit_at(h[u], l[u], sg.pos)], 1u);
                     oh |= h[u]; onh |= ~h[u];
                     if (needL) {
                         const uint64_t k16 = (l[u] >> 32) & 0xFFFFu;
