@@ -19,7 +19,7 @@ constexpr uint16_t kNoScatter = 0xFFFF;
 
 constexpr uint64_t kFlagAgg = 1ull << 62;  // look-back status: chunk aggregate published
 constexpr uint64_t kFlagInc = 2ull << 62;  // look-back status: inclusive prefix published
-constexpr int kChunkTiles = 128;           // tiles per chunk of the tile-offset scan
+constexpr int kChunkTiles = 64;            // tiles per chunk of the tile-offset scan
 constexpr uint64_t kCountMask = (1ull << 62) - 1;
 
 constexpr uint8_t kTaskSorted = 1;  // task range is already in final order

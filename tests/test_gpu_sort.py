@@ -169,7 +169,7 @@ def test_small_config_full_compare(gpu):
 
 @pytest.mark.parametrize("kind", ["uniform", "skewed"])
 def test_tile_offsets_across_scan_chunks(gpu, kind):
-    """3,000,000 records: the level-0 bucket spans three chunks of the tile-offset
+    """3,000,000 records: the level-0 bucket spans six chunks of the tile-offset
     scan (carries between chunks) and level-1 chunks hold many buckets."""
     n = 3_000_000
     rec = datagen.uniform(n, 91) if kind == "uniform" else datagen.skewed(n, 92)
@@ -177,7 +177,7 @@ def test_tile_offsets_across_scan_chunks(gpu, kind):
 
 
 def test_small_tiles_many_chunks(gpu):
-    """2,048-key tiles: 1,200,000 records make 586 level-0 tiles (five scan chunks)."""
+    """2,048-key tiles: 1,200,000 records make 586 level-0 tiles (ten scan chunks)."""
     rec = datagen.skewed(1_200_000, 93, nvals=256, dup_frac=0.1)
     want = oracle.sort(rec)
     old = gpu.get_params()
