@@ -394,11 +394,16 @@ int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream
     const Layout L = plan_layout(n, 1, t);
     const Work w = bind_layout(L, ws);
     const uint32_t tiles0 = (uint32_t)((n + t.tile - 1) / t.tile);
+    const uint32_t K = parts_for(n);
+    Side *sd = nullptr;  // K output parts: the gathers run on the side stream
+    if (K > 1) {
+        const int rc = get_side(stream, &sd);
+        if (rc) return rc;
+    }
     ProfCall pc;
     const bool prof = prof_start(&pc, stream);
     k_setup_single<<<1, 1, 0, stream>>>(w.reqs, w.hdr, static_cast<const uint8_t *>(records_dev),
                                         static_cast<uint8_t *>(out_dev), n, tiles0);
-    const uint32_t K = parts_for(n);
     if (K == 1) {
         // at most big_threshold records: the one level-0 bucket becomes a local
         // task as it is, so no deeper level can hold a bucket; launch level 0 only
@@ -413,9 +418,6 @@ int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream
         return LEYENDA_OK;
     }
     // K output parts: the local sorts of part k, then (side stream) its gather
-    Side *sd = nullptr;
-    int rc = get_side(stream, &sd);
-    if (rc) return rc;
     Work wp = w;
     wp.nparts = K;
     part_bounds(n, K, wp.part_end);
