@@ -43,6 +43,22 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def pmc_fields(n: int):
+    """Fields of the committed rocprofv3 counter summary, or None if it is
+    absent, for another size or taken on a different kernel source."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    fields = {}
+    for line in open(PMC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, _, v = line.strip().partition("=")
+            fields[k.strip()] = v.strip()
+    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    if fields.get("kernel_source_sha256_16") != src_hash or int(fields.get("n_records", -1)) != n:
+        return None
+    return fields
+
+
 def pmc_traffic(n: int, kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None if absent, for another kernel, or taken on a different
@@ -322,6 +338,12 @@ def main() -> int:
         "floor_frac_210B": round(210 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "output_keys_ordered": ordered,
     }
+    pf = pmc_fields(n)
+    if pf and "sort_hbm_bytes_per_record" in pf:
+        # every kernel's counted HBM bytes of one sort, over the measured wall time
+        bpr = float(pf["sort_hbm_bytes_per_record"])
+        res["sort_hbm_traffic"] = {"bytes_per_record": bpr, "gbs": round(bpr * n / (ms / 1e3) / 1e9, 1),
+                                   "source": os.path.relpath(PMC_FILE, ROOT)}
     if not args.no_serve:
         del out
         torch.cuda.empty_cache()
