@@ -188,11 +188,12 @@ def test_small_tiles_many_chunks(gpu):
         gpu.set_params(**old)
 
 
-@pytest.mark.parametrize("name", ["uniform", "few_distinct", "all_equal"])
+@pytest.mark.parametrize("name", ["uniform", "few_distinct", "all_equal", "one_big_bucket", "skewed_narrow"])
 def test_output_parts(gpu, name):
     """8,400,953 records: above the 8 Mi threshold the local sorts run per output
     part (four) with each part's gather on a side stream.  Equal-key ranges
-    (16 keys; one key) span part boundaries."""
+    (16 keys; one key) span part boundaries; one bucket of 90% of the keys and
+    Zipf prefixes put tasks of deep levels on both sides of them."""
     import torch
     n = 8_388_608 + 12_345
     rec = datagen.uniform(n, 94) if name == "uniform" else pattern(name, n)
