@@ -21,6 +21,10 @@
 //   k_gather    record scatter by the sorted tuples (Section 3.2):
 //               out[j] = in[idx[j]]
 //
+// A large single sort files its local-sort tasks under output parts (by the
+// task's start) and launches the local sorts once per part, so each part's
+// gather can start on another stream while later parts are sorted.
+//
 // Tuples are kept as two arrays (struct of arrays): H = key bytes 0..7 as a
 // big-endian u64, L = key bytes 8..9 (big-endian) << 32 | record index.
 // (H, L) compared as an unsigned 128-bit number is the key order with ties
