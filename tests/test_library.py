@@ -96,3 +96,14 @@ def test_plan_runs_budget_math():
         ley.plan_runs(10**6, 1000)
     assert ei.value.status == -3
     assert ley.plan_runs(0, 1000) == (0, 0)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py sorts on one GPU: --gpus above 1 exits with status 2 and says so."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
