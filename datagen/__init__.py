@@ -9,6 +9,8 @@ distributions of the five workload configurations:
 * uniform keys and payload (internal 10 GB and external 60 GB workloads),
 * Zipf(s=1.2) 4-byte key prefixes over 65,536 values plus 5% exact-duplicate
   keys (the skewed 20 GB workload),
+* keys of ten printable ASCII bytes, each uniform over 0x20..0x7E (the key
+  format the paper gives its 20 GB dataset),
 * log-uniform request sizes and Poisson arrivals (the serving workload).
 
 Nothing here sorts or compares keys.  The C library ``libdatagen.so`` is built
@@ -34,6 +36,8 @@ KEY_BYTES = 10
 # Workload seeds (one per configuration; request r of the serving stream uses 1000 + r).
 SEED_SMALL, SEED_INTERNAL, SEED_SKEWED, SEED_EXTERNAL = 1, 2, 3, 4
 SEED_ARRIVALS, SEED_SIZES, SEED_REQUEST_BASE = 5, 6, 1000
+SEED_ASCII = 7
+ASCII_LO, ASCII_VALUES = 0x20, 95
 ZIPF_VALUES, ZIPF_S, DUP_FRAC = 65536, 1.2, 0.05
 
 
@@ -58,6 +62,7 @@ def _load():
     lib.dg_records_indexed.argtypes = [vp, u64, u64, u64]
     lib.dg_records_skewed.argtypes = [vp, u64, u64, u64, ctypes.c_uint32, ctypes.c_double, ctypes.c_double]
     lib.dg_records_skewed.restype = ctypes.c_int
+    lib.dg_records_ascii.argtypes = [vp, u64, u64, u64]
     lib.dg_word.argtypes = [u64, u64, u64]
     lib.dg_word.restype = u64
     lib.dg_zipf_pmf.argtypes = [ctypes.c_uint32, ctypes.c_double, ctypes.c_uint32]
@@ -76,6 +81,10 @@ def fill_uniform(ptr: int, count: int, seed: int, first: int = 0) -> None:
 
 def fill_indexed(ptr: int, count: int, seed: int, first: int = 0) -> None:
     _load().dg_records_indexed(ctypes.c_void_p(ptr), count, seed, first)
+
+
+def fill_ascii(ptr: int, count: int, seed: int, first: int = 0) -> None:
+    _load().dg_records_ascii(ctypes.c_void_p(ptr), count, seed, first)
 
 
 def fill_skewed(ptr: int, count: int, seed: int, first: int = 0, nvals: int = ZIPF_VALUES,
@@ -110,6 +119,13 @@ def skewed(count: int, seed: int, first: int = 0, nvals: int = ZIPF_VALUES, s: f
     a = _empty(count)
     if count:
         fill_skewed(a.ctypes.data, count, seed, first, nvals, s, dup_frac)
+    return a
+
+
+def ascii(count: int, seed: int, first: int = 0) -> np.ndarray:
+    a = _empty(count)
+    if count:
+        fill_ascii(a.ctypes.data, count, seed, first)
     return a
 
 

@@ -151,3 +151,25 @@ uint32_t dg_zipf_value(uint64_t seed, uint32_t r) {
     const uint64_t key = seed_key(seed);
     return fmix32(r ^ (uint32_t)(key >> 32));
 }
+
+/* ---- printable (ASCII) keys ------------------------------------------------- */
+
+/* Printable-key records: the payload as in the uniform generator, the key ten
+ * bytes each uniform over the 95 printable ASCII values 0x20..0x7E (the
+ * key format of the paper's 20 GB dataset, Section 4.1).  Byte b of the key is
+ * 0x20 + floor(95 * c / 65536) for the 16-bit chunk c = bits 16*(b%4)..+15 of
+ * word 13 + b/4. */
+void dg_records_ascii(uint8_t *out, uint64_t count, uint64_t seed, uint64_t first) {
+    const uint64_t key = seed_key(seed);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < (int64_t)count; j++) {
+        uint8_t *dst = out + (uint64_t)j * 100u;
+        const uint64_t i = first + (uint64_t)j;
+        fill_uniform_one(dst, key, i);
+        uint64_t w[3] = {word_at(key, i, 13), word_at(key, i, 14), word_at(key, i, 15)};
+        for (int b = 0; b < 10; b++) {
+            const uint32_t c = (uint32_t)(w[b / 4] >> (16 * (b % 4))) & 0xFFFFu;
+            dst[b] = (uint8_t)(0x20u + ((95u * c) >> 16));
+        }
+    }
+}

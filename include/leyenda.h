@@ -200,9 +200,11 @@ int leyenda_serve_replay(const leyenda_server_config *cfg, uint64_t count, const
 
 /* ---------------------------------------------------------------------------
  * Tuning parameters.  They change speed only, never the output bytes.
- * Defaults: digit_bits 8, tile_items 32, big_threshold 2048, tiny_threshold 64,
+ * Defaults: digit_bits 8, tile_items 32, big_threshold 2048, tiny_threshold 128,
  * local_capacity 2048, scatter_threads 1024, local_threads 512 (the fastest of
- * the autotuner's sweep on the 10 GB uniform and 20 GB skewed workloads).
+ * the autotuner's sweep on the 10 GB uniform and 20 GB skewed workloads; the
+ * tiny threshold also on printable-key workloads, whose local-sort tasks pack
+ * sub-buckets of about a hundred keys).
  * digit_bits     radix digit width in bits (8: 256 buckets per pass, Algorithm 1).
  * tile_items     keys per thread in a device-wide partition tile (8, 16 or 32;
  *                a tile is 256 * tile_items keys).
@@ -211,7 +213,7 @@ int leyenda_serve_replay(const leyenda_server_config *cfg, uint64_t count, const
  *                1 <= big_threshold <= local_capacity.
  * tiny_threshold buckets of at most this many keys inside a local sort are
  *                ordered by comparisons instead of another radix partition
- *                (Algorithm 1's tinyBucketThreshold); 1..64.
+ *                (Algorithm 1's tinyBucketThreshold); 1..256.
  * local_capacity keys one workgroup sorts in LDS (2048).
  * scatter_threads threads per device-wide partition workgroup (256, 512 or
  *                1024; the tile stays 256 * tile_items keys).

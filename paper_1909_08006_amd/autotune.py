@@ -27,7 +27,7 @@ DEFAULT_SPACE = {
     "digit_bits": [8],
     "tile_items": [16, 32],
     "big_threshold": [1024, 2048],
-    "tiny_threshold": [16, 32, 64],
+    "tiny_threshold": [32, 64, 128, 192],
     "scatter_threads": [512, 1024],
     "local_threads": [256, 512],
 }

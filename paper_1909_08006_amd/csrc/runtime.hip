@@ -40,7 +40,7 @@ int hip_fail(hipError_t e, const char *what) {
 // parameters
 
 static std::mutex g_param_mu;
-static leyenda_params g_params = {8, 32, 2048, 64, 2048, 1024, 512};
+static leyenda_params g_params = {8, 32, 2048, 128, 2048, 1024, 512};
 
 leyenda_params current_params() {
     std::lock_guard<std::mutex> lk(g_param_mu);
@@ -62,7 +62,7 @@ static bool params_ok(const leyenda_params &p) {
     return p.digit_bits == 8 && (p.tile_items == 8 || p.tile_items == 16 || p.tile_items == 32) &&
            p.local_capacity == kLocalCap &&
            p.big_threshold >= 1 && p.big_threshold <= p.local_capacity && p.tiny_threshold >= 1 &&
-           p.tiny_threshold <= 64 && (p.scatter_threads == 256 || p.scatter_threads == 512 || p.scatter_threads == 1024) &&
+           p.tiny_threshold <= 256 && (p.scatter_threads == 256 || p.scatter_threads == 512 || p.scatter_threads == 1024) &&
            (p.local_threads == 256 || p.local_threads == 512);
 }
 

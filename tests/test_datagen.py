@@ -82,3 +82,20 @@ def test_request_sizes_and_arrivals():
     t = datagen.arrival_times(20000, rate_per_s=50.0)
     assert np.all(np.diff(t) > 0)
     assert abs(t[-1] / 20000 - 1 / 50.0) < 0.002
+
+
+def test_ascii_keys_printable_and_uniform():
+    n = 200000
+    a = datagen.ascii(n, datagen.SEED_ASCII)
+    k = a[:, :10]
+    assert k.min() == datagen.ASCII_LO and k.max() == datagen.ASCII_LO + datagen.ASCII_VALUES - 1
+    # the payload is the uniform generator's; the range of records is independent
+    np.testing.assert_array_equal(a[:, 10:], datagen.uniform(n, datagen.SEED_ASCII)[:, 10:])
+    np.testing.assert_array_equal(a[500:900], datagen.ascii(400, datagen.SEED_ASCII, first=500))
+    exp = n / datagen.ASCII_VALUES
+    for b in (0, 3, 4, 9):  # chunks from each of the three words and both ends of one
+        counts = np.bincount(k[:, b], minlength=256)[datagen.ASCII_LO:datagen.ASCII_LO + datagen.ASCII_VALUES]
+        chi2 = float(((counts - exp) ** 2 / exp).sum())
+        assert chi2 < 170  # 94 dof: mean 94, sd ~13.7
+    # byte positions are independent: the first two bytes take all 95 x 95 pairs
+    assert np.unique(k[:, 0].astype(np.int32) * 256 + k[:, 1]).size == 95 * 95

@@ -63,6 +63,12 @@ def test_internal_20gb_skewed(gpu):
     _internal(gpu, 200_000_000, datagen.fill_skewed, datagen.SEED_SKEWED, with_ties=True)
 
 
+@pytest.mark.timeout(1200)
+def test_internal_20gb_ascii(gpu):
+    """200,000,000 records (20 GB) with printable ASCII keys (95 values per byte)."""
+    _internal(gpu, 200_000_000, datagen.fill_ascii, datagen.SEED_ASCII, with_ties=False)
+
+
 @pytest.mark.timeout(1500)
 def test_external_60gb_30gb_budget(gpu):
     """600,000,000 records (60 GB) in pinned host memory, device budget 30 GB: runs + merge."""

@@ -108,13 +108,15 @@ def pattern(name: str, n: int) -> np.ndarray:
     elif name == "one_big_bucket":  # 90% of keys share 8 bytes, differing in bytes 8..9
         m = int(n * 0.9)
         rec[:m, :8] = 0x7E
+    elif name == "ascii":  # printable keys: 95 of the 256 digit values occur at every level
+        rec = datagen.ascii(n, datagen.SEED_ASCII)
     else:
         raise KeyError(name)
     return rec
 
 
 PATTERNS = ["all_equal", "only_byte9", "bytes_7_8_only", "sorted", "reverse", "few_distinct", "shared_prefix",
-            "extremes", "skewed", "skewed_narrow", "one_big_bucket"]
+            "extremes", "skewed", "skewed_narrow", "one_big_bucket", "ascii"]
 
 
 @pytest.mark.parametrize("name", PATTERNS)
@@ -140,7 +142,8 @@ def test_sort_worked_example(gpu):
     dict(scatter_threads=256, tile_items=8, big_threshold=1), dict(local_threads=512),
     dict(local_threads=512, tiny_threshold=1), dict(local_threads=512, tiny_threshold=64, big_threshold=2048),
     dict(tile_items=16, scatter_threads=512), dict(tile_items=32, scatter_threads=512),
-    dict(tile_items=16, scatter_threads=1024, big_threshold=100),
+    dict(tile_items=16, scatter_threads=1024, big_threshold=100), dict(tiny_threshold=256),
+    dict(tiny_threshold=160, big_threshold=300),
 ])
 def test_params_do_not_change_output(gpu, params):
     rec = pattern("skewed_narrow", 150_000)
@@ -188,7 +191,7 @@ def test_small_tiles_many_chunks(gpu):
         gpu.set_params(**old)
 
 
-@pytest.mark.parametrize("name", ["uniform", "few_distinct", "all_equal", "one_big_bucket", "skewed_narrow"])
+@pytest.mark.parametrize("name", ["uniform", "few_distinct", "all_equal", "one_big_bucket", "skewed_narrow", "ascii"])
 def test_output_parts(gpu, name):
     """8,400,953 records: above the 8 Mi threshold the local sorts run per output
     part (four) with each part's gather on a side stream.  Equal-key ranges
@@ -201,6 +204,20 @@ def test_output_parts(gpu, name):
     assert_same(got, oracle.sort(rec), f"parts {name}")
     st = gpu.stats(torch.cuda.current_stream())
     assert st["guard"] == 0 and st["tasks"] > 0
+
+
+@pytest.mark.parametrize("n", [2049, 300_001, 3_000_017, 20_000_003])
+def test_sort_ascii_levels(gpu, n):
+    """Printable keys (95 values per byte): buckets shrink 95-fold per digit, so
+    these sizes end after one, two, two and three device-wide levels (the last
+    with about 2,216 records per second-level bucket, above the 2,048 limit)."""
+    import torch
+    rec = datagen.ascii(n, datagen.SEED_ASCII + n % 5)
+    assert_same(run_sort(gpu, rec), oracle.sort(rec), f"ascii n={n}")
+    st = gpu.stats(torch.cuda.current_stream())
+    assert st["guard"] == 0
+    if n == 20_000_003:
+        assert st["moved"][2] > 0
 
 
 def test_stats_uniform(gpu):
