@@ -6,7 +6,8 @@ never imports it, and it imports nothing from the GPU library.
 
 What is computed (see ``oracle.c`` for the passages followed): the stable sort
 of 100-byte records by memcmp order on their 10-byte key (bytes 0..9), equal
-keys kept in input order.  Every schedule of the paper's method -- MSD radix
+keys kept in input order; with ``key_bytes`` the same sort on a key of the
+first K bytes (Section 5's flexible key sizes).  Every schedule of the paper's method -- MSD radix
 passes, big/small/tiny buckets, sorted runs plus a k-way merge, batching --
 reaches exactly this result.
 
@@ -49,6 +50,8 @@ def _load():
     vp, u64 = ctypes.c_void_p, ctypes.c_uint64
     lib.oracle_sort.argtypes = [vp, u64, vp, vp]
     lib.oracle_sort.restype = ctypes.c_int
+    lib.oracle_sort_key.argtypes = [vp, u64, ctypes.c_uint32, vp, vp]
+    lib.oracle_sort_key.restype = ctypes.c_int
     lib.oracle_output_rank.argtypes = [vp, u64, vp, u64, vp]
     lib.oracle_first_unsorted.argtypes = [vp, u64]
     lib.oracle_first_unsorted.restype = ctypes.c_int64
@@ -73,16 +76,22 @@ def _ptr(a: np.ndarray) -> ctypes.c_void_p:
     return ctypes.c_void_p(a.ctypes.data)
 
 
-def sort(records, return_perm: bool = False):
-    """Stable sort of records by their 10-byte key (memcmp order)."""
+def sort(records, return_perm: bool = False, key_bytes: int = KEY):
+    """Stable sort of records by their key (memcmp order): the 10-byte key, or
+    the first ``key_bytes`` bytes (1..100, the flexible key sizes of Section 5)."""
     rec = _as_records(records)
     n = rec.shape[0]
+    if not 1 <= key_bytes <= REC:
+        raise ValueError("key_bytes must be in 1..100")
     out = np.empty_like(rec)
     perm = np.empty(n, dtype=np.uint32)
     if n:
-        rc = _load().oracle_sort(_ptr(rec), n, _ptr(out), _ptr(perm))
+        if key_bytes == KEY:
+            rc = _load().oracle_sort(_ptr(rec), n, _ptr(out), _ptr(perm))
+        else:
+            rc = _load().oracle_sort_key(_ptr(rec), n, key_bytes, _ptr(out), _ptr(perm))
         if rc != 0:
-            raise MemoryError("oracle_sort failed")
+            raise MemoryError("oracle sort failed")
     return (out, perm) if return_perm else out
 
 

@@ -27,7 +27,13 @@
  *   oracle_ties_in_order  equal-key runs of an output hold their records in
  *                         input order (with the two checks above, this
  *                         pins a large output without a full oracle sort)
+ *   oracle_sort_key       the same stable sort with a key of the first K
+ *                         bytes, 1 <= K <= 100: the flexible key sizes that
+ *                         Section 5 names as the method's next step (same
+ *                         order definition: memcmp on the K key bytes, equal
+ *                         keys in input order)
  */
+#define _GNU_SOURCE
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -70,6 +76,42 @@ int oracle_sort(const uint8_t *rec, uint64_t n, uint8_t *out, uint32_t *perm) {
         if (perm) perm[j] = t[j].idx;
     }
     free(t);
+    return 0;
+}
+
+/* ---- oracle_sort_key ---------------------------------------------------------- */
+
+typedef struct {
+    const uint8_t *rec;
+    uint32_t key_bytes;
+} key_ctx;
+
+/* memcmp order on the first key_bytes bytes of two records, then input order. */
+static int cmp_prefix_idx(const void *pa, const void *pb, void *pc) {
+    const key_ctx *c = (const key_ctx *)pc;
+    const uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
+    int r = memcmp(c->rec + (uint64_t)a * REC, c->rec + (uint64_t)b * REC, c->key_bytes);
+    if (r != 0) return r;
+    return (a > b) - (a < b);
+}
+
+/* Stable sort of n records by their first key_bytes bytes (1..100); out and
+ * perm as in oracle_sort.  Returns 0, -1 if memory could not be allocated,
+ * -2 for a key size outside 1..100. */
+int oracle_sort_key(const uint8_t *rec, uint64_t n, uint32_t key_bytes, uint8_t *out, uint32_t *perm) {
+    if (key_bytes < 1 || key_bytes > REC) return -2;
+    if (n == 0) return 0;
+    if (n >= 0xFFFFFFFFull) return -1;
+    uint32_t *ix = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    if (!ix) return -1;
+    for (uint64_t i = 0; i < n; i++) ix[i] = (uint32_t)i;
+    key_ctx c = {rec, key_bytes};
+    qsort_r(ix, n, sizeof(uint32_t), cmp_prefix_idx, &c);
+    for (uint64_t j = 0; j < n; j++) {
+        memcpy(out + j * REC, rec + (uint64_t)ix[j] * REC, REC);
+        if (perm) perm[j] = ix[j];
+    }
+    free(ix);
     return 0;
 }
 

@@ -208,3 +208,73 @@ def test_corank_brute_small():
     assert oracle.corank_brute(runs, 5) == [3, 2, 0]
     assert oracle.corank_brute(runs, 6) == [3, 2, 1]
     assert oracle.corank_brute(runs, 7) == [3, 2, 2]
+
+
+# ---- flexible key sizes (Section 5): the first K bytes are the key ----------------
+
+def _tied_records(n, seed):
+    """Records whose key bytes take few values at chosen positions, so prefixes
+    of every length tie: bytes 0..11 from {0x00, 0xFF}, byte 40 from three
+    values, byte 99 from two; the rest uniform."""
+    rec = datagen.uniform(n, seed)
+    rng = np.random.default_rng(seed)
+    rec[:, :12] = np.where(rng.integers(0, 2, (n, 12)) == 1, 0xFF, 0x00)
+    rec[:, 40] = rng.integers(0, 3, n) * 0x70
+    rec[:, 99] = rng.integers(0, 2, n)
+    return rec
+
+
+@pytest.mark.parametrize("kb", [1, 2, 7, 8, 9, 11, 12, 13, 41, 99, 100])
+def test_key_bytes_matches_python_sorted(kb):
+    rec = _tied_records(3000, 50 + kb)
+    _, perm = oracle.sort(rec, return_perm=True, key_bytes=kb)
+    ref = sorted(range(rec.shape[0]), key=lambda i: bytes(rec[i, :kb]))  # stable
+    assert list(perm) == ref
+
+
+@pytest.mark.parametrize("kb", [3, 10, 16, 100])
+def test_key_bytes_matches_numpy_lexsort(kb):
+    rec = _tied_records(5000, 70 + kb)
+    cols = tuple(rec[:, b] for b in range(kb - 1, -1, -1))  # last key is primary
+    want = np.lexsort((np.arange(rec.shape[0]),) + cols)
+    _, perm = oracle.sort(rec, return_perm=True, key_bytes=kb)
+    np.testing.assert_array_equal(perm.astype(np.int64), want)
+
+
+@pytest.mark.parametrize("n", [2, 4, 6])
+def test_key_bytes_brute_force_tiny(n):
+    rng = np.random.default_rng(200 + n)
+    for trial in range(20):
+        rec = _tied_records(n, 300 + trial)
+        kb = int(rng.integers(1, 101))
+        _, perm = oracle.sort(rec, return_perm=True, key_bytes=kb)
+        assert list(perm) == oracle.brute_force_order([bytes(r[:kb]) for r in rec])
+
+
+def test_key_bytes_ten_agrees_with_fixed_key_sort():
+    rec = _tied_records(4000, 9)
+    lib = oracle._load()
+    out_a = np.empty_like(rec)
+    out_b = np.empty_like(rec)
+    perm_a = np.empty(rec.shape[0], dtype=np.uint32)
+    perm_b = np.empty(rec.shape[0], dtype=np.uint32)
+    assert lib.oracle_sort(oracle._ptr(rec), rec.shape[0], oracle._ptr(out_a), oracle._ptr(perm_a)) == 0
+    assert lib.oracle_sort_key(oracle._ptr(rec), rec.shape[0], 10, oracle._ptr(out_b), oracle._ptr(perm_b)) == 0
+    np.testing.assert_array_equal(perm_a, perm_b)
+    np.testing.assert_array_equal(out_a, out_b)
+
+
+def test_key_bytes_range():
+    rec = datagen.uniform(10, 1)
+    for bad in (0, 101):
+        with pytest.raises(ValueError):
+            oracle.sort(rec, key_bytes=bad)
+    assert oracle._load().oracle_sort_key(oracle._ptr(rec), 10, 0, oracle._ptr(rec.copy()), None) == -2
+    # a key of all 100 bytes orders whole records; a 1-byte key keeps input order inside each byte value
+    out = oracle.sort(_tied_records(500, 4), key_bytes=100)
+    assert all(bytes(out[i]) <= bytes(out[i + 1]) for i in range(499))
+    rec = _tied_records(500, 5)
+    _, perm = oracle.sort(rec, return_perm=True, key_bytes=1)
+    for v in (0x00, 0xFF):
+        p = perm[rec[perm, 0] == v]
+        assert np.all(np.diff(p.astype(np.int64)) > 0)
