@@ -69,6 +69,23 @@ typedef enum {
  * ------------------------------------------------------------------------- */
 int leyenda_sort(const void *records_dev, uint64_t n, void *out_dev, void *stream);
 
+/* Flexible key sizes (Section 5 names keys of any size as the method's next
+ * step: a prefix sort combined with comparisons of the full keys where the
+ * prefixes tie).  Stable sort of n device-resident records by a key of their
+ * first key_bytes bytes, 1 <= key_bytes <= 100, in memcmp order; equal keys
+ * keep input order.  key_bytes == 10 is leyenda_sort.  key_bytes < 10: the
+ * prefix sort with the prefix bytes past the key ignored.  key_bytes > 10: the
+ * prefix sort, then rounds over the runs of output records whose leading bytes
+ * tie, each round ordering every run by its next six key bytes with one
+ * stable sort of (run number, next bytes, position) entries and permuting the
+ * runs' records to match; rounds end when no tie is left or the key is used
+ * up.  Buffers and errors as leyenda_sort, plus LEYENDA_EINVAL for key_bytes
+ * outside 1..100 and LEYENDA_ENOMEM when the rounds' scratch (200 bytes per
+ * record inside a tie run, plus 24 bytes per 1,024 records) cannot be
+ * allocated.  With key_bytes > 10 the call returns after the stream has
+ * drained (it reads each round's tie count on the host). */
+int leyenda_sort_keyed(const void *records_dev, uint64_t n, uint32_t key_bytes, void *out_dev, void *stream);
+
 /* Device bytes of scratch memory leyenda_sort uses for n records under the
  * current parameters (tuple buffers, index array, bucket tables). */
 uint64_t leyenda_workspace_bytes(uint64_t n);

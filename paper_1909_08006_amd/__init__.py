@@ -73,6 +73,7 @@ def load():
     P64 = ctypes.POINTER(ctypes.c_uint64)
     sig = {
         "leyenda_sort": ([vp, u64, vp, vp], i32),
+        "leyenda_sort_keyed": ([vp, u64, ctypes.c_uint32, vp, vp], i32),
         "leyenda_workspace_bytes": ([u64], u64),
         "leyenda_sort_parts": ([u64], ctypes.c_uint32),
         "leyenda_sort_runs": ([vp, u64, u64, vp, P64, u64, P64, vp], i32),
@@ -144,6 +145,23 @@ def sort(records, out=None, stream=None):
     elif _nrec(out) != n or not out.is_cuda:
         raise ValueError("out must be a device tensor of the same size")
     _check(load().leyenda_sort(records.data_ptr(), n, out.data_ptr(), _stream_ptr(stream)), "leyenda_sort")
+    return out
+
+
+def sort_keyed(records, key_bytes: int, out=None, stream=None):
+    """Stable sort of device-resident records by a key of their first
+    ``key_bytes`` bytes (1..100); returns ``out``.  For key_bytes > 10 the call
+    returns after ``stream`` has drained."""
+    import torch
+    n = _nrec(records)
+    if not records.is_cuda:
+        raise ValueError("sort_keyed() takes a device tensor")
+    if out is None:
+        out = torch.empty_like(records)
+    elif _nrec(out) != n or not out.is_cuda:
+        raise ValueError("out must be a device tensor of the same size")
+    _check(load().leyenda_sort_keyed(records.data_ptr(), n, key_bytes, out.data_ptr(), _stream_ptr(stream)),
+           "leyenda_sort_keyed")
     return out
 
 

@@ -7,6 +7,7 @@ namespace ley {
 
 constexpr int kRec = 100;          // record bytes (Section 4.1)
 constexpr int kKeyBits = 80;       // 10-byte key
+constexpr uint32_t kKeyBytes = 10;
 constexpr int kRB = 8;             // digit width: 256-way buckets per pass (Algorithm 1)
 constexpr int kRadix = 1 << kRB;
 constexpr int kWG = 256;           // threads per workgroup, all kernels (4 wave64)
@@ -116,6 +117,11 @@ struct Work {
                                 // joins the part of its start (entries past nparts unused)
     uint32_t nparts;            // output parts in use (1..kParts)
     uint32_t max_seg, max_tiles, max_tasks, max_reqs, max_reps;
+    // key bytes that take part in the order: extraction ANDs the tuple's key
+    // words with these (all ones for the 10-byte key; a shorter key clears
+    // the bytes past it, so records equal on it tie and keep index order)
+    uint64_t kmask_h;
+    uint32_t kmask_l;
 };
 
 // Workspace sizing for a tuple space of n keys and up to `reqs` requests.

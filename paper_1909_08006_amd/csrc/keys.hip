@@ -1,0 +1,263 @@
+// Flexible key sizes.  The method sorts records by a fixed-size key; Section 5
+// names keys of any size as its next step, through a prefix sort combined with
+// comparisons of the full keys where prefixes tie.  Here the key is the first
+// K bytes of each 100-byte record, 1 <= K <= 100, in the same order as the
+// 10-byte key (unsigned bytes, most significant first; equal keys keep input
+// order).
+//
+// K <= 10: the prefix sort itself, with the tuple bytes past the key cleared
+// at extraction, so records equal on the key tie and keep index order.
+//
+// K > 10: the prefix sort on bytes [0, 10), then rounds that resolve the runs
+// of adjacent output records whose bytes [0, P) tie (P = 10, 16, 22, ...).  A
+// round counts and numbers the runs (two passes over the output and one scan
+// of per-block counts), then writes for every record inside a run a 100-byte
+// entry whose 10-byte key is the run number (big-endian 32 bits) followed by
+// key bytes [P, P + 6) of the record (bytes at or past K read as zero), with
+// the record's output position in entry bytes 12..19.  One stable sort of the
+// entries (the in-HBM sort) orders every run by its next six key bytes at
+// once: the run number keeps runs apart and in place, and equal entries keep
+// position order, which is input order.  The records of the runs are then
+// gathered in the entries' order and written back over their runs.  A tie on
+// [0, P + 6) implies a tie on [0, P), so each round holds at most as many
+// entries as the one before; rounds stop when no run is left or P reaches K.
+// The host reads the entry count of each round (one stream synchronisation
+// per round).
+#include <hip/hip_runtime.h>
+
+#include "runtime.h"
+
+namespace ley {
+namespace {
+
+constexpr int kTB = 256;                // threads per block
+constexpr int kTPer = 4;                // positions per thread
+constexpr int kTSpan = kTB * kTPer;     // positions per block
+constexpr int kRecWords = kRec / 4;     // dwords per record
+constexpr uint32_t kWindow = 6;         // key bytes resolved per round
+
+// Records j1 and j2 of A agree on bytes [0, p), p <= 100 (records are
+// 4-byte aligned; a dword holds bytes 4d..4d+3, byte 4d in its low 8 bits).
+__device__ __forceinline__ bool same_prefix(const uint32_t *A, uint64_t j1, uint64_t j2, uint32_t p) {
+    const uint32_t *a = A + j1 * kRecWords, *b = A + j2 * kRecWords;
+    const uint32_t full = p >> 2, rem = p & 3u;
+    uint32_t diff = 0;
+    for (uint32_t d = 0; d < full; d++) diff |= a[d] ^ b[d];
+    if (rem) diff |= (a[full] ^ b[full]) & ((1u << (8 * rem)) - 1u);
+    return diff == 0;
+}
+
+// Position j (< n): is it inside a run of at least two records tying on
+// [0, p), and does such a run start there.
+__device__ __forceinline__ void run_flags(const uint32_t *A, uint64_t n, uint64_t j, uint32_t p, bool *in_run,
+                                          bool *starts) {
+    const bool eq_prev = j > 0 && same_prefix(A, j - 1, j, p);
+    const bool eq_next = j + 1 < n && same_prefix(A, j, j + 1, p);
+    *in_run = eq_prev || eq_next;
+    *starts = eq_next && !eq_prev;
+}
+
+// Exclusive scan over the block's threads (one value each); *total gets the sum.
+__device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *total) {
+    __shared__ uint32_t s[kTB];
+    const uint32_t t = threadIdx.x;
+    s[t] = v;
+    __syncthreads();
+    for (uint32_t off = 1; off < (uint32_t)kTB; off <<= 1) {
+        const uint32_t add = t >= off ? s[t - off] : 0u;
+        __syncthreads();
+        s[t] += add;
+        __syncthreads();
+    }
+    const uint32_t incl = s[t];
+    *total = s[kTB - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// Per block of kTSpan positions: positions inside runs and run starts.
+__global__ __launch_bounds__(kTB) void k_tie_count(const uint32_t *A, uint64_t n, uint32_t p, uint32_t *cnt_in,
+                                                   uint32_t *cnt_start) {
+    const uint64_t base = (uint64_t)blockIdx.x * kTSpan;
+    uint32_t ci = 0, cs = 0;
+    for (int u = 0; u < kTPer; u++) {
+        const uint64_t j = base + (uint64_t)u * kTB + threadIdx.x;
+        if (j < n) {
+            bool r, s;
+            run_flags(A, n, j, p, &r, &s);
+            ci += r;
+            cs += s;
+        }
+    }
+    uint32_t ti, ts;
+    (void)block_scan_excl(ci, &ti);
+    (void)block_scan_excl(cs, &ts);
+    if (threadIdx.x == 0) {
+        cnt_in[blockIdx.x] = ti;
+        cnt_start[blockIdx.x] = ts;
+    }
+}
+
+// One block: exclusive scans of both per-block counts; totals[0] = positions
+// inside runs, totals[1] = runs.
+__global__ __launch_bounds__(kTB) void k_tie_scan(const uint32_t *cnt_in, const uint32_t *cnt_start, uint64_t nb,
+                                                  uint64_t *off_in, uint64_t *off_start, uint64_t *totals) {
+    uint64_t ci = 0, cs = 0;
+    for (uint64_t b0 = 0; b0 < nb; b0 += kTB) {
+        const uint64_t b = b0 + threadIdx.x;
+        const uint32_t vi = b < nb ? cnt_in[b] : 0u, vs = b < nb ? cnt_start[b] : 0u;
+        uint32_t ti, ts;
+        const uint32_t ei = block_scan_excl(vi, &ti);
+        const uint32_t es = block_scan_excl(vs, &ts);
+        if (b < nb) {
+            off_in[b] = ci + ei;
+            off_start[b] = cs + es;
+        }
+        ci += ti;
+        cs += ts;
+    }
+    if (threadIdx.x == 0) {
+        totals[0] = ci;
+        totals[1] = cs;
+    }
+}
+
+// Entries of the round: for position j inside a run, entry t (its rank among
+// such positions) gets key = run number (big-endian) + key bytes [p, p + 6)
+// masked to the key, position j in bytes 12..19; dest[t] = j.
+__global__ __launch_bounds__(kTB) void k_tie_emit(const uint32_t *A, uint64_t n, uint32_t p, uint32_t key_bytes,
+                                                  const uint64_t *off_in, const uint64_t *off_start, uint32_t *E,
+                                                  uint64_t *dest) {
+    const uint64_t base = (uint64_t)blockIdx.x * kTSpan;
+    uint64_t ci = off_in[blockIdx.x], cs = off_start[blockIdx.x];
+    const uint8_t *Ab = reinterpret_cast<const uint8_t *>(A);
+    for (int u = 0; u < kTPer; u++) {
+        const uint64_t j = base + (uint64_t)u * kTB + threadIdx.x;
+        bool r = false, s = false;
+        if (j < n) run_flags(A, n, j, p, &r, &s);
+        uint32_t ti, ts;
+        const uint32_t ei = block_scan_excl(r ? 1u : 0u, &ti);
+        const uint32_t es = block_scan_excl(s ? 1u : 0u, &ts);
+        if (r) {
+            const uint64_t t = ci + ei;
+            // the run holding j began at the latest start at or before j
+            const uint32_t run = (uint32_t)(cs + es + (s ? 1u : 0u) - 1u);
+            uint8_t kb[kWindow];
+            for (uint32_t k = 0; k < kWindow; k++) {
+                const uint32_t b = p + k;
+                kb[k] = b < key_bytes ? Ab[j * kRec + b] : (uint8_t)0;
+            }
+            uint32_t *e = E + t * kRecWords;
+            e[0] = __builtin_bswap32(run);
+            e[1] = (uint32_t)kb[0] | ((uint32_t)kb[1] << 8) | ((uint32_t)kb[2] << 16) | ((uint32_t)kb[3] << 24);
+            e[2] = (uint32_t)kb[4] | ((uint32_t)kb[5] << 8);
+            e[3] = (uint32_t)j;
+            e[4] = (uint32_t)(j >> 32);
+            for (int d = 5; d < kRecWords; d++) e[d] = 0;
+            dest[t] = j;
+        }
+        ci += ti;
+        cs += ts;
+    }
+}
+
+// out[t] = A[position held by sorted entry t], one dword per thread.
+__global__ __launch_bounds__(kTB) void k_tie_gather(const uint32_t *A, const uint32_t *E2, uint64_t m,
+                                                    uint32_t *out) {
+    const uint64_t g = (uint64_t)blockIdx.x * kTB + threadIdx.x;
+    if (g >= m * kRecWords) return;
+    const uint64_t t = g / kRecWords, d = g - t * kRecWords;
+    const uint64_t j = (uint64_t)E2[t * kRecWords + 3] | ((uint64_t)E2[t * kRecWords + 4] << 32);
+    out[g] = A[j * kRecWords + d];
+}
+
+// A[dest[t]] = R[t], one dword per thread.
+__global__ __launch_bounds__(kTB) void k_tie_scatter(const uint32_t *R, const uint64_t *dest, uint64_t m,
+                                                     uint32_t *A) {
+    const uint64_t g = (uint64_t)blockIdx.x * kTB + threadIdx.x;
+    if (g >= m * kRecWords) return;
+    const uint64_t t = g / kRecWords, d = g - t * kRecWords;
+    A[dest[t] * kRecWords + d] = R[g];
+}
+
+struct Scratch {
+    void *p[7] = {};
+    ~Scratch() {
+        for (void *q : p)
+            if (q) (void)hipFree(q);
+    }
+};
+
+int alloc(void **p, size_t bytes) {
+    const hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(LEYENDA_ENOMEM, "leyenda_sort_keyed: hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return LEYENDA_OK;
+}
+
+// Rounds over the tie runs of the prefix-sorted records in A (n records).
+int resolve_ties(uint32_t *A, uint64_t n, uint32_t key_bytes, hipStream_t s, const Tune &t) {
+    const uint64_t nb = (n + kTSpan - 1) / kTSpan;
+    Scratch sc;  // freed after the stream drains (hipFree waits for the device)
+    int rc;
+    if ((rc = alloc(&sc.p[0], nb * 4)) || (rc = alloc(&sc.p[1], nb * 4)) || (rc = alloc(&sc.p[2], nb * 8)) ||
+        (rc = alloc(&sc.p[3], nb * 8)) || (rc = alloc(&sc.p[4], 16)))
+        return rc;
+    uint32_t *cnt_in = static_cast<uint32_t *>(sc.p[0]), *cnt_start = static_cast<uint32_t *>(sc.p[1]);
+    uint64_t *off_in = static_cast<uint64_t *>(sc.p[2]), *off_start = static_cast<uint64_t *>(sc.p[3]);
+    uint64_t *totals = static_cast<uint64_t *>(sc.p[4]);
+    uint32_t *E = nullptr, *E2 = nullptr;  // entries, then sorted entries (room for the first round's count)
+    uint64_t *dest = nullptr;
+    uint64_t cap = 0;
+    for (uint32_t p = kKeyBytes; p < key_bytes; p += kWindow) {
+        k_tie_count<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(A, n, p, cnt_in, cnt_start);
+        k_tie_scan<<<dim3(1), dim3(kTB), 0, s>>>(cnt_in, cnt_start, nb, off_in, off_start, totals);
+        uint64_t h[2] = {0, 0};
+        hipError_t e = hipMemcpyAsync(h, totals, sizeof(h), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: tie count");
+        const uint64_t m = h[0];
+        if (m == 0) break;
+        if (m > n || h[1] > m / 2) return fail(LEYENDA_EHIP, "leyenda_sort_keyed: inconsistent tie count");
+        if (!E) {
+            cap = m;
+            if ((rc = alloc(&sc.p[5], cap * kRec * 2)) || (rc = alloc(&sc.p[6], cap * 8))) return rc;
+            E = static_cast<uint32_t *>(sc.p[5]);
+            E2 = E + cap * kRecWords;
+            dest = static_cast<uint64_t *>(sc.p[6]);
+        }
+        if (m > cap) return fail(LEYENDA_EHIP, "leyenda_sort_keyed: tie count grew");
+        k_tie_emit<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(A, n, p, key_bytes, off_in, off_start, E, dest);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: entries");
+        if ((rc = sort_device(E, m, E2, s, t))) return rc;
+        const uint64_t blocks = (m * kRecWords + kTB - 1) / kTB;
+        k_tie_gather<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(A, E2, m, E);  // E is free again
+        k_tie_scatter<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(E, dest, m, A);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: permute");
+    }
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "leyenda_sort_keyed");
+    return LEYENDA_OK;
+}
+
+}  // namespace
+}  // namespace ley
+
+using namespace ley;
+
+extern "C" int leyenda_sort_keyed(const void *records_dev, uint64_t n, uint32_t key_bytes, void *out_dev,
+                                  void *stream) {
+    if (key_bytes < 1 || key_bytes > (uint32_t)kRec)
+        return fail(LEYENDA_EINVAL, "leyenda_sort_keyed: key_bytes %u outside 1..100", key_bytes);
+    if (n == 0) return LEYENDA_OK;
+    int rc = check_records(records_dev, out_dev, n, "leyenda_sort_keyed");
+    if (rc) return rc;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const Tune t = tune_of(current_params());
+    if ((rc = sort_device(records_dev, n, out_dev, s, t, key_bytes < kKeyBytes ? key_bytes : kKeyBytes))) return rc;
+    if (key_bytes <= kKeyBytes || n < 2) return LEYENDA_OK;
+    return resolve_ties(static_cast<uint32_t *>(out_dev), n, key_bytes, s, t);
+}

@@ -149,6 +149,8 @@ Work bind_layout(const Layout &L, void *base) {
     w.max_tasks = L.max_tasks;
     w.max_reqs = L.max_reqs;
     w.max_reps = L.max_reps;
+    w.kmask_h = ~0ull;
+    w.kmask_l = 0xFFFFu;
     return w;
 }
 
@@ -381,18 +383,24 @@ static void part_bounds(uint64_t n, uint32_t K, uint64_t *end) {
     for (uint32_t k = 0; k < K; k++) end[k] = k + 1 == K ? n : n * kEnd16[k] / 16;
 }
 
-int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t) {
+int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t,
+                uint32_t key_bytes) {
     const Layout L = plan_layout(n, 1, t);
     void *ws = nullptr;
     int rc = get_workspace(stream, L.total, &ws);
     if (rc) return rc;
     remember_layout(stream, L);
-    return sort_device_ws(records_dev, n, out_dev, stream, t, ws);
+    return sort_device_ws(records_dev, n, out_dev, stream, t, ws, key_bytes);
 }
 
-int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t, void *ws) {
+int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t, void *ws,
+                   uint32_t key_bytes) {
     const Layout L = plan_layout(n, 1, t);
-    const Work w = bind_layout(L, ws);
+    Work w = bind_layout(L, ws);
+    if (key_bytes < kKeyBytes) {  // bytes key_bytes..9 of the prefix do not take part
+        w.kmask_h = key_bytes >= 8 ? ~0ull : ~0ull << (64 - 8 * key_bytes);
+        w.kmask_l = key_bytes == 9 ? 0xFF00u : 0u;
+    }
     const uint32_t tiles0 = (uint32_t)((n + t.tile - 1) / t.tile);
     const uint32_t K = parts_for(n);
     Side *sd = nullptr;  // K output parts: the gathers run on the side stream

@@ -539,9 +539,9 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
             for (int u = 0; u < RI; u++) {
                 const uint32_t q = (r0 + u) * kWG + threadIdx.x;
                 const bool valid = q < nvalid;
-                const uint64_t h = __builtin_bswap64(((uint64_t)b[u] << 32) | a[u]);
+                const uint64_t h = __builtin_bswap64(((uint64_t)b[u] << 32) | a[u]) & w.kmask_h;
                 if (valid) {
-                    const uint64_t k16 = __builtin_bswap16((uint16_t)(c[u] & 0xFFFFu));
+                    const uint64_t k16 = __builtin_bswap16((uint16_t)(c[u] & 0xFFFFu)) & w.kmask_l;
                     // tuples: written once, read by the next pass (far beyond the caches)
                     __builtin_nontemporal_store(h, H + q);
                     __builtin_nontemporal_store((k16 << 32) | (uint32_t)(local0 + q), L + q);
