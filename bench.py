@@ -170,6 +170,63 @@ def keys_ordered(torch, out, n: int) -> bool:
     return ok
 
 
+def prefix_ordered(torch, out, n: int, kb: int) -> bool:
+    """Adjacent records in memcmp order on their first kb bytes (device-side)."""
+    o = out.view(n, 100)
+    ok = True
+    for a in range(0, n - 1, 25_000_000):
+        b = min(n - 1, a + 25_000_000)
+        x, y = o[a:b, :kb], o[a + 1:b + 1, :kb]
+        ne = x != y
+        col = ne.to(torch.uint8).argmax(dim=1, keepdim=True)
+        xd, yd = x.gather(1, col).squeeze(1), y.gather(1, col).squeeze(1)
+        ok = ok and bool((~ne.any(dim=1) | (xd < yd)).all().item())
+    return ok
+
+
+def flexible_keys(ley, torch, datagen, dev, steps: int) -> dict:
+    """Keys of the first K bytes (leyenda_sort_keyed) on the 10 GB uniform
+    records already in HBM (K = 4: a masked prefix; K = 20: one tie round,
+    which finds no tie) and on 200,000,000 skewed records (Zipf prefixes and 5%
+    duplicate 10-byte keys: K = 20 resolves the duplicates' runs by bytes
+    10..15, then 16..19)."""
+    res = {}
+    n = dev.numel() // 100
+    out = torch.empty_like(dev)
+
+    def timed(src, dst, kb):
+        ley.sort_keyed(src, kb, dst)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ley.sort_keyed(src, kb, dst)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    for kb in (4, 20):
+        ms = timed(dev, out, kb)
+        res[f"uniform_1e8_k{kb}"] = {"ms_per_sort": round(ms, 3), "gbs": round(n * 100 / (ms / 1e3) / 1e9, 2),
+                                      "ordered": prefix_ordered(torch, out, n, kb)}
+    del out
+    torch.cuda.empty_cache()
+    m = 200_000_000
+    log(f"keys: generating {m:,} skewed records (20 GB, seed {datagen.SEED_SKEWED}) ...")
+    host = ley.pinned_empty(m * 100)
+    datagen.fill_skewed(host.data_ptr(), m, datagen.SEED_SKEWED)
+    sk = host.to("cuda:0", non_blocking=True)
+    torch.cuda.synchronize()
+    ley.pinned_free(host)
+    out = torch.empty_like(sk)
+    ms10 = timed(sk, out, 10)
+    ms = timed(sk, out, 20)
+    res["skewed_2e8_k20"] = {"ms_per_sort": round(ms, 3), "gbs": round(m * 100 / (ms / 1e3) / 1e9, 2),
+                             "ms_per_sort_k10": round(ms10, 3), "ordered": prefix_ordered(torch, out, m, 20)}
+    del sk, out
+    torch.cuda.empty_cache()
+    res["steps"] = steps
+    return res
+
+
 def ascii_keys(ley, torch, datagen, steps: int) -> dict:
     """The paper's 20 GB dataset format: 200,000,000 records whose keys are ten
     printable ASCII bytes (95 values each), in HBM, sorted like the 10 GB
@@ -287,6 +344,7 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-external", action="store_true", help="skip the 60 GB runs + merge workload")
     ap.add_argument("--no-ascii", action="store_true", help="skip the 20 GB printable-key workload")
+    ap.add_argument("--no-keys", action="store_true", help="skip the flexible key size (leyenda_sort_keyed) runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 2 GB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -391,6 +449,9 @@ def main() -> int:
     del host
     if hasattr(torch._C, "_host_emptyCache"):  # return the cached pinned block (host pinned limit)
         torch._C._host_emptyCache()
+    if not args.no_keys:
+        res["flexible_keys"] = flexible_keys(ley, torch, datagen, dev, min(args.steps, 5))
+        ordered = ordered and all(v["ordered"] for k, v in res["flexible_keys"].items() if k != "steps")
     if not args.no_ascii:
         res["ascii_keys"] = ascii_keys(ley, torch, datagen, args.steps)
         ordered = ordered and res["ascii_keys"]["output_keys_ordered"]

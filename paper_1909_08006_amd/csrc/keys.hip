@@ -10,19 +10,23 @@
 //
 // K > 10: the prefix sort on bytes [0, 10), then rounds that resolve the runs
 // of adjacent output records whose bytes [0, P) tie (P = 10, 16, 22, ...).  A
-// round counts and numbers the runs (two passes over the output and one scan
-// of per-block counts), then writes for every record inside a run a 100-byte
+// round marks which neighbours tie, counts and numbers the runs (a scan of
+// per-block counts), then writes for every record inside a run a 100-byte
 // entry whose 10-byte key is the run number (big-endian 32 bits) followed by
 // key bytes [P, P + 6) of the record (bytes at or past K read as zero), with
-// the record's output position in entry bytes 12..19.  One stable sort of the
+// the record's output position in entry bytes 12..19 (the rest of the entry is
+// left unwritten).  One stable sort of the
 // entries (the in-HBM sort) orders every run by its next six key bytes at
 // once: the run number keeps runs apart and in place, and equal entries keep
 // position order, which is input order.  The records of the runs are then
 // gathered in the entries' order and written back over their runs.  A tie on
-// [0, P + 6) implies a tie on [0, P), so each round holds at most as many
-// entries as the one before; rounds stop when no run is left or P reaches K.
-// The host reads the entry count of each round (one stream synchronisation
-// per round).
+// [0, P + 6) implies a tie on [0, P), so a round looks only at the previous
+// round's entries: in sorted order they describe the records now at
+// consecutive positions of each run, and two neighbours tie exactly when their
+// entries agree on run number and window bytes, so only the first round reads
+// records to find ties.  Rounds stop when no run is left or P reaches K.  The
+// host reads the entry count of each round (one stream synchronisation per
+// round).
 #include <hip/hip_runtime.h>
 
 #include "runtime.h"
@@ -47,16 +51,6 @@ __device__ __forceinline__ bool same_prefix(const uint32_t *A, uint64_t j1, uint
     return diff == 0;
 }
 
-// Position j (< n): is it inside a run of at least two records tying on
-// [0, p), and does such a run start there.
-__device__ __forceinline__ void run_flags(const uint32_t *A, uint64_t n, uint64_t j, uint32_t p, bool *in_run,
-                                          bool *starts) {
-    const bool eq_prev = j > 0 && same_prefix(A, j - 1, j, p);
-    const bool eq_next = j + 1 < n && same_prefix(A, j, j + 1, p);
-    *in_run = eq_prev || eq_next;
-    *starts = eq_next && !eq_prev;
-}
-
 // Exclusive scan over the block's threads (one value each); *total gets the sum.
 __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *total) {
     __shared__ uint32_t s[kTB];
@@ -75,16 +69,50 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *total)
     return incl - v;
 }
 
-// Per block of kTSpan positions: positions inside runs and run starts.
-__global__ __launch_bounds__(kTB) void k_tie_count(const uint32_t *A, uint64_t n, uint32_t p, uint32_t *cnt_in,
+// Candidates c = 0..nc-1 of a round, in output-position order.  F[c] = 1 if
+// candidates c and c + 1 hold adjacent records that tie on the key bytes
+// sorted so far.  First round (E2 == nullptr): candidate c is position c and
+// the test compares bytes [0, 10) of records c and c + 1.  Later rounds: the
+// candidates are the previous round's entries in sorted order (E2), whose
+// records now sit at consecutive positions within each run; c and c + 1 tie
+// when their entries agree on run number and window bytes (entry bytes 0..9).
+__global__ __launch_bounds__(kTB) void k_tie_eq(const uint32_t *A, const uint32_t *E2, uint64_t nc, uint8_t *F) {
+    const uint64_t base = (uint64_t)blockIdx.x * kTSpan;
+    for (int u = 0; u < kTPer; u++) {
+        const uint64_t c = base + (uint64_t)u * kTB + threadIdx.x;
+        if (c >= nc) continue;
+        bool eq = false;
+        if (c + 1 < nc) {
+            if (!E2) {
+                eq = same_prefix(A, c, c + 1, kKeyBytes);
+            } else {
+                const uint32_t *a = E2 + c * kRecWords, *b = a + kRecWords;
+                eq = ((a[0] ^ b[0]) | (a[1] ^ b[1]) | ((a[2] ^ b[2]) & 0xFFFFu)) == 0;
+            }
+        }
+        F[c] = eq ? 1 : 0;
+    }
+}
+
+// Candidate c is inside a run of at least two (it ties with a neighbour) and
+// whether such a run starts there.
+__device__ __forceinline__ void run_flags(const uint8_t *F, uint64_t c, bool *in_run, bool *starts) {
+    const bool eq_next = F[c] != 0;
+    const bool eq_prev = c > 0 && F[c - 1] != 0;
+    *in_run = eq_prev || eq_next;
+    *starts = eq_next && !eq_prev;
+}
+
+// Per block of kTSpan candidates: candidates inside runs and run starts.
+__global__ __launch_bounds__(kTB) void k_tie_count(const uint8_t *F, uint64_t nc, uint32_t *cnt_in,
                                                    uint32_t *cnt_start) {
     const uint64_t base = (uint64_t)blockIdx.x * kTSpan;
     uint32_t ci = 0, cs = 0;
     for (int u = 0; u < kTPer; u++) {
-        const uint64_t j = base + (uint64_t)u * kTB + threadIdx.x;
-        if (j < n) {
+        const uint64_t c = base + (uint64_t)u * kTB + threadIdx.x;
+        if (c < nc) {
             bool r, s;
-            run_flags(A, n, j, p, &r, &s);
+            run_flags(F, c, &r, &s);
             ci += r;
             cs += s;
         }
@@ -98,49 +126,67 @@ __global__ __launch_bounds__(kTB) void k_tie_count(const uint32_t *A, uint64_t n
     }
 }
 
-// One block: exclusive scans of both per-block counts; totals[0] = positions
-// inside runs, totals[1] = runs.
-__global__ __launch_bounds__(kTB) void k_tie_scan(const uint32_t *cnt_in, const uint32_t *cnt_start, uint64_t nb,
+// One block: exclusive scans of both per-block counts (each thread sums a
+// contiguous range of blocks, the range totals are scanned in LDS, then each
+// thread writes its range's offsets); totals[0] = positions inside runs,
+// totals[1] = runs.
+constexpr int kSB = 1024;
+__global__ __launch_bounds__(kSB) void k_tie_scan(const uint32_t *cnt_in, const uint32_t *cnt_start, uint64_t nb,
                                                   uint64_t *off_in, uint64_t *off_start, uint64_t *totals) {
-    uint64_t ci = 0, cs = 0;
-    for (uint64_t b0 = 0; b0 < nb; b0 += kTB) {
-        const uint64_t b = b0 + threadIdx.x;
-        const uint32_t vi = b < nb ? cnt_in[b] : 0u, vs = b < nb ? cnt_start[b] : 0u;
-        uint32_t ti, ts;
-        const uint32_t ei = block_scan_excl(vi, &ti);
-        const uint32_t es = block_scan_excl(vs, &ts);
-        if (b < nb) {
-            off_in[b] = ci + ei;
-            off_start[b] = cs + es;
-        }
-        ci += ti;
-        cs += ts;
+    __shared__ uint64_t si[kSB], ss[kSB];
+    const uint32_t t = threadIdx.x;
+    const uint64_t per = (nb + kSB - 1) / kSB;
+    const uint64_t b0 = min(nb, (uint64_t)t * per), b1 = min(nb, b0 + per);
+    uint64_t ti = 0, ts = 0;
+    for (uint64_t b = b0; b < b1; b++) {
+        ti += cnt_in[b];
+        ts += cnt_start[b];
     }
-    if (threadIdx.x == 0) {
-        totals[0] = ci;
-        totals[1] = cs;
+    si[t] = ti;
+    ss[t] = ts;
+    __syncthreads();
+    for (uint32_t off = 1; off < (uint32_t)kSB; off <<= 1) {
+        const uint64_t ai = t >= off ? si[t - off] : 0ull, as = t >= off ? ss[t - off] : 0ull;
+        __syncthreads();
+        si[t] += ai;
+        ss[t] += as;
+        __syncthreads();
+    }
+    uint64_t ci = si[t] - ti, cs = ss[t] - ts;
+    for (uint64_t b = b0; b < b1; b++) {
+        off_in[b] = ci;
+        off_start[b] = cs;
+        ci += cnt_in[b];
+        cs += cnt_start[b];
+    }
+    if (t == kSB - 1) {
+        totals[0] = si[t];
+        totals[1] = ss[t];
     }
 }
 
-// Entries of the round: for position j inside a run, entry t (its rank among
-// such positions) gets key = run number (big-endian) + key bytes [p, p + 6)
-// masked to the key, position j in bytes 12..19; dest[t] = j.
-__global__ __launch_bounds__(kTB) void k_tie_emit(const uint32_t *A, uint64_t n, uint32_t p, uint32_t key_bytes,
+// Entries of the round: for candidate c inside a run, entry t (its rank among
+// such candidates) gets key = run number (big-endian) + key bytes [p, p + 6)
+// of the record at its position j, masked to the key, and j in bytes 12..19;
+// dest[t] = j.  j = c in the first round, else the previous round's dest[c].
+__global__ __launch_bounds__(kTB) void k_tie_emit(const uint32_t *A, const uint8_t *F, uint64_t nc,
+                                                  const uint64_t *cand, uint32_t p, uint32_t key_bytes,
                                                   const uint64_t *off_in, const uint64_t *off_start, uint32_t *E,
                                                   uint64_t *dest) {
     const uint64_t base = (uint64_t)blockIdx.x * kTSpan;
     uint64_t ci = off_in[blockIdx.x], cs = off_start[blockIdx.x];
     const uint8_t *Ab = reinterpret_cast<const uint8_t *>(A);
     for (int u = 0; u < kTPer; u++) {
-        const uint64_t j = base + (uint64_t)u * kTB + threadIdx.x;
+        const uint64_t c = base + (uint64_t)u * kTB + threadIdx.x;
         bool r = false, s = false;
-        if (j < n) run_flags(A, n, j, p, &r, &s);
+        if (c < nc) run_flags(F, c, &r, &s);
         uint32_t ti, ts;
         const uint32_t ei = block_scan_excl(r ? 1u : 0u, &ti);
         const uint32_t es = block_scan_excl(s ? 1u : 0u, &ts);
         if (r) {
             const uint64_t t = ci + ei;
-            // the run holding j began at the latest start at or before j
+            const uint64_t j = cand ? cand[c] : c;
+            // the run holding c began at the latest start at or before c
             const uint32_t run = (uint32_t)(cs + es + (s ? 1u : 0u) - 1u);
             uint8_t kb[kWindow];
             for (uint32_t k = 0; k < kWindow; k++) {
@@ -153,8 +199,7 @@ __global__ __launch_bounds__(kTB) void k_tie_emit(const uint32_t *A, uint64_t n,
             e[2] = (uint32_t)kb[4] | ((uint32_t)kb[5] << 8);
             e[3] = (uint32_t)j;
             e[4] = (uint32_t)(j >> 32);
-            for (int d = 5; d < kRecWords; d++) e[d] = 0;
-            dest[t] = j;
+            dest[t] = j;  // entry bytes 20..99 are not written: the sort carries them, nothing reads them
         }
         ci += ti;
         cs += ts;
@@ -181,7 +226,7 @@ __global__ __launch_bounds__(kTB) void k_tie_scatter(const uint32_t *R, const ui
 }
 
 struct Scratch {
-    void *p[7] = {};
+    void *p[8] = {};
     ~Scratch() {
         for (void *q : p)
             if (q) (void)hipFree(q);
@@ -200,43 +245,50 @@ int alloc(void **p, size_t bytes) {
 
 // Rounds over the tie runs of the prefix-sorted records in A (n records).
 int resolve_ties(uint32_t *A, uint64_t n, uint32_t key_bytes, hipStream_t s, const Tune &t) {
-    const uint64_t nb = (n + kTSpan - 1) / kTSpan;
+    const uint64_t nb_max = (n + kTSpan - 1) / kTSpan;
     Scratch sc;  // freed after the stream drains (hipFree waits for the device)
     int rc;
-    if ((rc = alloc(&sc.p[0], nb * 4)) || (rc = alloc(&sc.p[1], nb * 4)) || (rc = alloc(&sc.p[2], nb * 8)) ||
-        (rc = alloc(&sc.p[3], nb * 8)) || (rc = alloc(&sc.p[4], 16)))
+    if ((rc = alloc(&sc.p[0], nb_max * 4)) || (rc = alloc(&sc.p[1], nb_max * 4)) ||
+        (rc = alloc(&sc.p[2], nb_max * 8)) || (rc = alloc(&sc.p[3], nb_max * 8)) || (rc = alloc(&sc.p[4], 16)) ||
+        (rc = alloc(&sc.p[5], n)))
         return rc;
     uint32_t *cnt_in = static_cast<uint32_t *>(sc.p[0]), *cnt_start = static_cast<uint32_t *>(sc.p[1]);
     uint64_t *off_in = static_cast<uint64_t *>(sc.p[2]), *off_start = static_cast<uint64_t *>(sc.p[3]);
     uint64_t *totals = static_cast<uint64_t *>(sc.p[4]);
+    uint8_t *F = static_cast<uint8_t *>(sc.p[5]);
     uint32_t *E = nullptr, *E2 = nullptr;  // entries, then sorted entries (room for the first round's count)
-    uint64_t *dest = nullptr;
-    uint64_t cap = 0;
-    for (uint32_t p = kKeyBytes; p < key_bytes; p += kWindow) {
-        k_tie_count<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(A, n, p, cnt_in, cnt_start);
-        k_tie_scan<<<dim3(1), dim3(kTB), 0, s>>>(cnt_in, cnt_start, nb, off_in, off_start, totals);
+    uint64_t *dest[2] = {nullptr, nullptr};  // positions of the entries, by round parity
+    uint64_t cap = 0, nc = n;
+    int r = 0;
+    for (uint32_t p = kKeyBytes; p < key_bytes; p += kWindow, r++) {
+        const uint64_t nb = (nc + kTSpan - 1) / kTSpan;
+        k_tie_eq<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(A, r ? E2 : nullptr, nc, F);
+        k_tie_count<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(F, nc, cnt_in, cnt_start);
+        k_tie_scan<<<dim3(1), dim3(kSB), 0, s>>>(cnt_in, cnt_start, nb, off_in, off_start, totals);
         uint64_t h[2] = {0, 0};
         hipError_t e = hipMemcpyAsync(h, totals, sizeof(h), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: tie count");
         const uint64_t m = h[0];
         if (m == 0) break;
-        if (m > n || h[1] > m / 2) return fail(LEYENDA_EHIP, "leyenda_sort_keyed: inconsistent tie count");
+        if (m > nc || h[1] > m / 2) return fail(LEYENDA_EHIP, "leyenda_sort_keyed: inconsistent tie count");
         if (!E) {
             cap = m;
-            if ((rc = alloc(&sc.p[5], cap * kRec * 2)) || (rc = alloc(&sc.p[6], cap * 8))) return rc;
-            E = static_cast<uint32_t *>(sc.p[5]);
+            if ((rc = alloc(&sc.p[6], cap * kRec * 2)) || (rc = alloc(&sc.p[7], cap * 16))) return rc;
+            E = static_cast<uint32_t *>(sc.p[6]);
             E2 = E + cap * kRecWords;
-            dest = static_cast<uint64_t *>(sc.p[6]);
+            dest[0] = static_cast<uint64_t *>(sc.p[7]);
+            dest[1] = dest[0] + cap;
         }
-        if (m > cap) return fail(LEYENDA_EHIP, "leyenda_sort_keyed: tie count grew");
-        k_tie_emit<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(A, n, p, key_bytes, off_in, off_start, E, dest);
+        k_tie_emit<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(A, F, nc, r ? dest[(r - 1) & 1] : nullptr, p, key_bytes,
+                                                             off_in, off_start, E, dest[r & 1]);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: entries");
         if ((rc = sort_device(E, m, E2, s, t))) return rc;
         const uint64_t blocks = (m * kRecWords + kTB - 1) / kTB;
         k_tie_gather<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(A, E2, m, E);  // E is free again
-        k_tie_scatter<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(E, dest, m, A);
+        k_tie_scatter<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(E, dest[r & 1], m, A);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: permute");
+        nc = m;  // the next round looks only inside these runs
     }
     const hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "leyenda_sort_keyed");
