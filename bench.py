@@ -262,7 +262,8 @@ def external(ley, torch, datagen) -> dict:
     """The 60 GB limited-memory workload: 600,000,000 records in pinned host
     memory, 30 GB device budget, sorted runs written over the input, then the
     k-way merge into pageable host memory (the pinned limit of the host holds
-    the input only).  Bound: PCIe, 200 B/record each way.  The merge runs twice
+    the input only).  Bound: PCIe, 200 B/record each way, the two directions
+    overlapped at their measured single-direction rates.  The merge runs twice
     into the same output: first into fresh memory (its first-touch page faults
     included), then into the now resident buffer (a reused output)."""
     import numpy as np
@@ -319,7 +320,11 @@ def external(ley, torch, datagen) -> dict:
     ok = bool(all(bytes(keys[i]) <= bytes(keys[i + 1]) for i in range(len(keys) - 1)))
     del keys, out, runs
     ley.pinned_free(a)
-    both_bound = n * 400 / (rates["both_ways"] * 1e9)  # 200 B/record each way, both ways at once
+    # 200 B/record each way (runs: up + down; merge: up + down); the two directions
+    # at their own single-direction rates, fully overlapped, is a lower bound on
+    # any box (the rate of two concurrent copies issued from torch has varied
+    # from box to box, 57-97 GB/s, while the runs moved 89 GB/s both ways)
+    both_bound = max(n * 200 / (rates["h2d"] * 1e9), n * 200 / (rates["d2h"] * 1e9))
     return {"workload": "600,000,000 x 100-byte records (60 GB) in pinned host memory, 30 GB device budget, "
                         "uniform keys; runs over the input, merge into pageable host memory",
             "runs": len(bounds) - 1, "t_runs_s": round(t_runs, 3),
@@ -327,7 +332,7 @@ def external(ley, torch, datagen) -> dict:
             "gbs_records_end_to_end": round(n * 100 / (t_runs + t_merge[1]) / 1e9, 2),
             "gbs_records_end_to_end_first_touch": round(n * 100 / (t_runs + t_merge[0]) / 1e9, 2),
             "pcie_measured_gbs": rates,
-            "pcie_bound": {"bytes_per_record_each_way": 200, "bound_s_both_ways_at_measured": round(both_bound, 3),
+            "pcie_bound": {"bytes_per_record_each_way": 200, "bound_s_each_way_rates_overlapped": round(both_bound, 3),
                            "frac": round(both_bound / (t_runs + t_merge[1]), 3)},
             "sampled_order_ok": ok}
 
