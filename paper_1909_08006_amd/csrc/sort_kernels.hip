@@ -359,9 +359,37 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
         // registers (lane l: digits 4l..4l+3) and walks them with lane reads,
         // so the sequential walk costs no memory round trips
         uint32_t c4[4], b4[4];
+        bool big4 = false;
 #pragma unroll
-        for (int k = 0; k < 4; k++) { c4[k] = p_cnt[4 * d + k]; b4[k] = p_base[4 * d + k]; }
+        for (int k = 0; k < 4; k++) {
+            c4[k] = p_cnt[4 * d + k];
+            b4[k] = p_base[4 * d + k];
+            big4 = big4 || c4[k] > tu.big;
+        }
         uint32_t nt = 0, cur_start = 0, cur = 0;
+        if (__ballot(big4) == 0 && sg.count <= 16u * kLocalCap) {
+            // no big sub-bucket and few tasks: the same greedy cuts a task at a
+            // time.  A task starting at offset `base` ends at the last digit
+            // whose inclusive prefix count stays within base + capacity; those
+            // digits form a prefix of the 256, counted with four ballots.
+            uint32_t s4[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) s4[k] = b4[k] + c4[k];
+            uint32_t base = 0;
+            while (base < sg.count) {
+                const uint32_t lim = base + (uint32_t)kLocalCap;
+                uint32_t nle = 0;
+#pragma unroll
+                for (int k = 0; k < 4; k++) nle += (uint32_t)__popcll(__ballot(s4[k] <= lim));
+                const uint32_t e = nle - 1u;  // >= the next non-empty digit: it fits alone
+                const uint32_t v0 = __builtin_amdgcn_readlane(s4[0], e >> 2), v1 = __builtin_amdgcn_readlane(s4[1], e >> 2),
+                               v2 = __builtin_amdgcn_readlane(s4[2], e >> 2), v3 = __builtin_amdgcn_readlane(s4[3], e >> 2);
+                const uint32_t se = (e & 3u) == 0 ? v0 : (e & 3u) == 1 ? v1 : (e & 3u) == 2 ? v2 : v3;
+                if (d == 0) { p_tstart[nt] = base; p_tcnt[nt] = se - base; }
+                nt++;
+                base = se;
+            }
+        } else
         for (int e4 = 0; e4 < kRadix / 4; e4++) {
 #pragma unroll
             for (int k = 0; k < 4; k++) {
