@@ -155,7 +155,7 @@ hipError_t launch_sort_core(const Work &w, const Tune &t, uint32_t nreq, uint32_
 // with Stage::tail false and w.nparts > 1, one launch per part in order).
 hipError_t launch_local_part(const Work &w, const Tune &t, hipStream_t s, int cus, int part);
 hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,
-                                uint64_t n, hipStream_t s);
+                                uint64_t n, hipStream_t s, uint8_t *ties = nullptr, bool has_prev = false);
 // The batch gather (sizes from the device header); exits like the tail of a
 // Stage when level `gate` has big buckets.
 hipError_t launch_gather_batch(const Work &w, hipStream_t s, int gate = kMaxLev);

@@ -23,8 +23,10 @@
 // [0, P + 6) implies a tie on [0, P), so a round looks only at the previous
 // round's entries: in sorted order they describe the records now at
 // consecutive positions of each run, and two neighbours tie exactly when their
-// entries agree on run number and window bytes, so only the first round reads
-// records to find ties.  Rounds stop when no run is left or P reaches K.  The
+// entries agree on run number and window bytes.  The first round's ties come
+// from the prefix sort itself: its record gather marks every output record
+// whose key bytes 0..9 equal those of the record before it, so no round reads
+// the records to find ties.  Rounds stop when no run is left or P reaches K.  The
 // host reads the entry count of each round (one stream synchronisation per
 // round).
 #include <hip/hip_runtime.h>
@@ -39,17 +41,6 @@ constexpr int kTPer = 4;                // positions per thread
 constexpr int kTSpan = kTB * kTPer;     // positions per block
 constexpr int kRecWords = kRec / 4;     // dwords per record
 constexpr uint32_t kWindow = 6;         // key bytes resolved per round
-
-// Records j1 and j2 of A agree on bytes [0, p), p <= 100 (records are
-// 4-byte aligned; a dword holds bytes 4d..4d+3, byte 4d in its low 8 bits).
-__device__ __forceinline__ bool same_prefix(const uint32_t *A, uint64_t j1, uint64_t j2, uint32_t p) {
-    const uint32_t *a = A + j1 * kRecWords, *b = A + j2 * kRecWords;
-    const uint32_t full = p >> 2, rem = p & 3u;
-    uint32_t diff = 0;
-    for (uint32_t d = 0; d < full; d++) diff |= a[d] ^ b[d];
-    if (rem) diff |= (a[full] ^ b[full]) & ((1u << (8 * rem)) - 1u);
-    return diff == 0;
-}
 
 // Exclusive scan over the block's threads (one value each); *total gets the sum.
 __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *total) {
@@ -69,42 +60,38 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *total)
     return incl - v;
 }
 
-// Candidates c = 0..nc-1 of a round, in output-position order.  F[c] = 1 if
-// candidates c and c + 1 hold adjacent records that tie on the key bytes
-// sorted so far.  First round (E2 == nullptr): candidate c is position c and
-// the test compares bytes [0, 10) of records c and c + 1.  Later rounds: the
-// candidates are the previous round's entries in sorted order (E2), whose
-// records now sit at consecutive positions within each run; c and c + 1 tie
+// Candidates c = 0..nc-1 of a round, in output-position order; P[c] = 1 if
+// candidate c holds the record right after candidate c - 1's and ties with it
+// on the key bytes sorted so far.  First round: candidate c is output position
+// c and the prefix sort's record gather writes P.  Later rounds (this kernel):
+// the candidates are the previous round's entries in sorted order (E2), whose
+// records now sit at consecutive positions within each run; c ties with c - 1
 // when their entries agree on run number and window bytes (entry bytes 0..9).
-__global__ __launch_bounds__(kTB) void k_tie_eq(const uint32_t *A, const uint32_t *E2, uint64_t nc, uint8_t *F) {
+__global__ __launch_bounds__(kTB) void k_tie_eq(const uint32_t *E2, uint64_t nc, uint8_t *P) {
     const uint64_t base = (uint64_t)blockIdx.x * kTSpan;
     for (int u = 0; u < kTPer; u++) {
         const uint64_t c = base + (uint64_t)u * kTB + threadIdx.x;
         if (c >= nc) continue;
         bool eq = false;
-        if (c + 1 < nc) {
-            if (!E2) {
-                eq = same_prefix(A, c, c + 1, kKeyBytes);
-            } else {
-                const uint32_t *a = E2 + c * kRecWords, *b = a + kRecWords;
-                eq = ((a[0] ^ b[0]) | (a[1] ^ b[1]) | ((a[2] ^ b[2]) & 0xFFFFu)) == 0;
-            }
+        if (c > 0) {
+            const uint32_t *b = E2 + c * kRecWords, *a = b - kRecWords;
+            eq = ((a[0] ^ b[0]) | (a[1] ^ b[1]) | ((a[2] ^ b[2]) & 0xFFFFu)) == 0;
         }
-        F[c] = eq ? 1 : 0;
+        P[c] = eq ? 1 : 0;
     }
 }
 
 // Candidate c is inside a run of at least two (it ties with a neighbour) and
 // whether such a run starts there.
-__device__ __forceinline__ void run_flags(const uint8_t *F, uint64_t c, bool *in_run, bool *starts) {
-    const bool eq_next = F[c] != 0;
-    const bool eq_prev = c > 0 && F[c - 1] != 0;
+__device__ __forceinline__ void run_flags(const uint8_t *P, uint64_t nc, uint64_t c, bool *in_run, bool *starts) {
+    const bool eq_prev = c > 0 && P[c] != 0;
+    const bool eq_next = c + 1 < nc && P[c + 1] != 0;
     *in_run = eq_prev || eq_next;
     *starts = eq_next && !eq_prev;
 }
 
 // Per block of kTSpan candidates: candidates inside runs and run starts.
-__global__ __launch_bounds__(kTB) void k_tie_count(const uint8_t *F, uint64_t nc, uint32_t *cnt_in,
+__global__ __launch_bounds__(kTB) void k_tie_count(const uint8_t *P, uint64_t nc, uint32_t *cnt_in,
                                                    uint32_t *cnt_start) {
     const uint64_t base = (uint64_t)blockIdx.x * kTSpan;
     uint32_t ci = 0, cs = 0;
@@ -112,7 +99,7 @@ __global__ __launch_bounds__(kTB) void k_tie_count(const uint8_t *F, uint64_t nc
         const uint64_t c = base + (uint64_t)u * kTB + threadIdx.x;
         if (c < nc) {
             bool r, s;
-            run_flags(F, c, &r, &s);
+            run_flags(P, nc, c, &r, &s);
             ci += r;
             cs += s;
         }
@@ -169,7 +156,7 @@ __global__ __launch_bounds__(kSB) void k_tie_scan(const uint32_t *cnt_in, const 
 // such candidates) gets key = run number (big-endian) + key bytes [p, p + 6)
 // of the record at its position j, masked to the key, and j in bytes 12..19;
 // dest[t] = j.  j = c in the first round, else the previous round's dest[c].
-__global__ __launch_bounds__(kTB) void k_tie_emit(const uint32_t *A, const uint8_t *F, uint64_t nc,
+__global__ __launch_bounds__(kTB) void k_tie_emit(const uint32_t *A, const uint8_t *P, uint64_t nc,
                                                   const uint64_t *cand, uint32_t p, uint32_t key_bytes,
                                                   const uint64_t *off_in, const uint64_t *off_start, uint32_t *E,
                                                   uint64_t *dest) {
@@ -179,7 +166,7 @@ __global__ __launch_bounds__(kTB) void k_tie_emit(const uint32_t *A, const uint8
     for (int u = 0; u < kTPer; u++) {
         const uint64_t c = base + (uint64_t)u * kTB + threadIdx.x;
         bool r = false, s = false;
-        if (c < nc) run_flags(F, c, &r, &s);
+        if (c < nc) run_flags(P, nc, c, &r, &s);
         uint32_t ti, ts;
         const uint32_t ei = block_scan_excl(r ? 1u : 0u, &ti);
         const uint32_t es = block_scan_excl(s ? 1u : 0u, &ts);
@@ -243,27 +230,26 @@ int alloc(void **p, size_t bytes) {
     return LEYENDA_OK;
 }
 
-// Rounds over the tie runs of the prefix-sorted records in A (n records).
-int resolve_ties(uint32_t *A, uint64_t n, uint32_t key_bytes, hipStream_t s, const Tune &t) {
+// Rounds over the tie runs of the prefix-sorted records in A (n records); P
+// (n bytes) holds the first round's tie marks and is reused by later rounds.
+int resolve_ties(uint32_t *A, uint64_t n, uint32_t key_bytes, hipStream_t s, const Tune &t, uint8_t *P) {
     const uint64_t nb_max = (n + kTSpan - 1) / kTSpan;
     Scratch sc;  // freed after the stream drains (hipFree waits for the device)
     int rc;
     if ((rc = alloc(&sc.p[0], nb_max * 4)) || (rc = alloc(&sc.p[1], nb_max * 4)) ||
-        (rc = alloc(&sc.p[2], nb_max * 8)) || (rc = alloc(&sc.p[3], nb_max * 8)) || (rc = alloc(&sc.p[4], 16)) ||
-        (rc = alloc(&sc.p[5], n)))
+        (rc = alloc(&sc.p[2], nb_max * 8)) || (rc = alloc(&sc.p[3], nb_max * 8)) || (rc = alloc(&sc.p[4], 16)))
         return rc;
     uint32_t *cnt_in = static_cast<uint32_t *>(sc.p[0]), *cnt_start = static_cast<uint32_t *>(sc.p[1]);
     uint64_t *off_in = static_cast<uint64_t *>(sc.p[2]), *off_start = static_cast<uint64_t *>(sc.p[3]);
     uint64_t *totals = static_cast<uint64_t *>(sc.p[4]);
-    uint8_t *F = static_cast<uint8_t *>(sc.p[5]);
     uint32_t *E = nullptr, *E2 = nullptr;  // entries, then sorted entries (room for the first round's count)
     uint64_t *dest[2] = {nullptr, nullptr};  // positions of the entries, by round parity
     uint64_t cap = 0, nc = n;
     int r = 0;
     for (uint32_t p = kKeyBytes; p < key_bytes; p += kWindow, r++) {
         const uint64_t nb = (nc + kTSpan - 1) / kTSpan;
-        k_tie_eq<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(A, r ? E2 : nullptr, nc, F);
-        k_tie_count<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(F, nc, cnt_in, cnt_start);
+        if (r) k_tie_eq<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(E2, nc, P);
+        k_tie_count<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(P, nc, cnt_in, cnt_start);
         k_tie_scan<<<dim3(1), dim3(kSB), 0, s>>>(cnt_in, cnt_start, nb, off_in, off_start, totals);
         uint64_t h[2] = {0, 0};
         hipError_t e = hipMemcpyAsync(h, totals, sizeof(h), hipMemcpyDeviceToHost, s);
@@ -280,7 +266,7 @@ int resolve_ties(uint32_t *A, uint64_t n, uint32_t key_bytes, hipStream_t s, con
             dest[0] = static_cast<uint64_t *>(sc.p[7]);
             dest[1] = dest[0] + cap;
         }
-        k_tie_emit<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(A, F, nc, r ? dest[(r - 1) & 1] : nullptr, p, key_bytes,
+        k_tie_emit<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(A, P, nc, r ? dest[(r - 1) & 1] : nullptr, p, key_bytes,
                                                              off_in, off_start, E, dest[r & 1]);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: entries");
         if ((rc = sort_device(E, m, E2, s, t))) return rc;
@@ -309,7 +295,11 @@ extern "C" int leyenda_sort_keyed(const void *records_dev, uint64_t n, uint32_t 
     if (rc) return rc;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const Tune t = tune_of(current_params());
-    if ((rc = sort_device(records_dev, n, out_dev, s, t, key_bytes < kKeyBytes ? key_bytes : kKeyBytes))) return rc;
-    if (key_bytes <= kKeyBytes || n < 2) return LEYENDA_OK;
-    return resolve_ties(static_cast<uint32_t *>(out_dev), n, key_bytes, s, t);
+    if (key_bytes <= kKeyBytes || n < 2)
+        return sort_device(records_dev, n, out_dev, s, t, key_bytes < kKeyBytes ? key_bytes : kKeyBytes);
+    Scratch sc;  // the prefix sort's tie marks (one byte per output record)
+    if ((rc = alloc(&sc.p[0], n))) return rc;
+    uint8_t *P = static_cast<uint8_t *>(sc.p[0]);
+    if ((rc = sort_device(records_dev, n, out_dev, s, t, kKeyBytes, P))) return rc;
+    return resolve_ties(static_cast<uint32_t *>(out_dev), n, key_bytes, s, t, P);
 }

@@ -19,11 +19,13 @@ void pool_forget(hipStream_t stream);
 bool overlaps(const void *a, uint64_t abytes, const void *b, uint64_t bbytes);
 int check_records(const void *in, const void *out, uint64_t n, const char *who);
 // key_bytes (1..10): the key is that many leading bytes (10: the whole prefix).
+// ties (n bytes, optional): ties[g] = 1 if output record g has the same key
+// bytes 0..9 as output record g - 1, written by the record gather.
 int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t,
-                uint32_t key_bytes = kKeyBytes);
+                uint32_t key_bytes = kKeyBytes, uint8_t *ties = nullptr);
 // Same sort with a caller-provided workspace of plan_layout(n, 1, t).total bytes.
 int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t, void *ws,
-                   uint32_t key_bytes = kKeyBytes);
+                   uint32_t key_bytes = kKeyBytes, uint8_t *ties = nullptr);
 
 // batch.hip
 int batch_sort(const leyenda_segment *segs, uint64_t count, hipStream_t s);

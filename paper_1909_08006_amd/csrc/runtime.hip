@@ -384,17 +384,17 @@ static void part_bounds(uint64_t n, uint32_t K, uint64_t *end) {
 }
 
 int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t,
-                uint32_t key_bytes) {
+                uint32_t key_bytes, uint8_t *ties) {
     const Layout L = plan_layout(n, 1, t);
     void *ws = nullptr;
     int rc = get_workspace(stream, L.total, &ws);
     if (rc) return rc;
     remember_layout(stream, L);
-    return sort_device_ws(records_dev, n, out_dev, stream, t, ws, key_bytes);
+    return sort_device_ws(records_dev, n, out_dev, stream, t, ws, key_bytes, ties);
 }
 
 int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t, void *ws,
-                   uint32_t key_bytes) {
+                   uint32_t key_bytes, uint8_t *ties) {
     const Layout L = plan_layout(n, 1, t);
     Work w = bind_layout(L, ws);
     if (key_bytes < kKeyBytes) {  // bytes key_bytes..9 of the prefix do not take part
@@ -420,7 +420,7 @@ int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream
         hipError_t e = launch_sort_core(w, t, 1, tiles0, stream, device_cus(), prof ? pc.e + 1 : nullptr, st);
         if (e != hipSuccess) return hip_fail(e, "sort kernels");
         e = launch_gather_single(static_cast<const uint8_t *>(records_dev), n, w.idx,
-                                 static_cast<uint8_t *>(out_dev), n, stream);
+                                 static_cast<uint8_t *>(out_dev), n, stream, ties);
         if (prof) prof_finish(pc, stream);
         if (e != hipSuccess) return hip_fail(e, "gather kernel");
         return LEYENDA_OK;
@@ -451,7 +451,9 @@ int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream
         if (e == hipSuccess) e = hipEventRecord(sd->ready[k], stream);
         if (e == hipSuccess) e = hipStreamWaitEvent(sd->s, sd->ready[k], 0);
         if (e == hipSuccess && pg) e = hipEventRecord(pc.g[2 * k], sd->s);
-        if (e == hipSuccess && c1 > c0) e = launch_gather_single(rec, n, w.idx + c0, out + c0 * kRec, c1 - c0, sd->s);
+        if (e == hipSuccess && c1 > c0)
+            e = launch_gather_single(rec, n, w.idx + c0, out + c0 * kRec, c1 - c0, sd->s, ties ? ties + c0 : nullptr,
+                                     c0 > 0);
         if (e == hipSuccess && pg) e = hipEventRecord(pc.g[2 * k + 1], sd->s);
     }
     if (e == hipSuccess && prof) e = hipEventRecord(pc.e[3], stream);

@@ -1280,9 +1280,14 @@ __global__ __launch_bounds__(kWG) void k_gather(const Req *reqs, const Hdr *hdr,
 }
 
 // Plain gather for the step-level test entry point.
-__global__ __launch_bounds__(kWG) void k_gather_plain(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx,
-                                                      uint8_t *out, uint64_t n) {
+// TIES: also ties[g] = 1 if output record g has the same key bytes 0..9 as
+// output record g - 1 (0 for the first record of the sort); record -1 of a
+// launch is idx[-1] when has_prev is set (a later output part).
+template <bool TIES>
+__device__ __forceinline__ void gather_body(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,
+                                            uint64_t n, uint8_t *ties, int has_prev) {
     __shared__ uint32_t sidx[kWG];
+    __shared__ uint32_t skey[TIES ? 3 * kWG : 1];
     const uint64_t g0 = (uint64_t)blockIdx.x * kWG;
     const uint32_t nr = (uint32_t)min<uint64_t>(kWG, n - g0);
     if (threadIdx.x < nr) sidx[threadIdx.x] = idx[g0 + threadIdx.x];
@@ -1296,11 +1301,52 @@ __global__ __launch_bounds__(kWG) void k_gather_plain(const uint8_t *rec, uint64
         v[u] = 0;
         if (r < nr && sidx[r] < n_rec) v[u] = src[(uint64_t)sidx[r] * 25 + kk];
     }
+    if (TIES) {  // key bytes 0..9 of each record to LDS (dwords 0, 1 and half of 2)
+#pragma unroll
+        for (int u = 0; u < 25; u++) {
+            const uint32_t q = threadIdx.x + kWG * u, r = q / 25u, kk = q - 25u * r;
+            if (r < nr && kk < 3) skey[3 * r + kk] = kk == 2 ? (v[u] & 0xFFFFu) : v[u];
+        }
+    }
 #pragma unroll
     for (int u = 0; u < 25; u++) {
         const uint32_t q = threadIdx.x + kWG * u, r = q / 25u;
         if (r < nr) __builtin_nontemporal_store(v[u], dst + q);
     }
+    if (TIES) {
+        __syncthreads();
+        const uint32_t r = threadIdx.x;
+        if (r < nr) {
+            const uint64_t g = g0 + r;
+            uint32_t p0 = 0, p1 = 0, p2 = 0;
+            bool have = true;
+            if (r > 0) {
+                p0 = skey[3 * r - 3]; p1 = skey[3 * r - 2]; p2 = skey[3 * r - 1];
+            } else if (g > 0 || has_prev) {
+                const uint32_t j = idx[(int64_t)g - 1];  // idx[-1]: the last record of the part before
+                if (j < n_rec) {
+                    p0 = src[(uint64_t)j * 25]; p1 = src[(uint64_t)j * 25 + 1]; p2 = src[(uint64_t)j * 25 + 2] & 0xFFFFu;
+                } else {
+                    have = false;
+                }
+            } else {
+                have = false;
+            }
+            ties[g] = (have && p0 == skey[3 * r] && p1 == skey[3 * r + 1] && p2 == skey[3 * r + 2]) ? 1 : 0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_gather_plain(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx,
+                                                      uint8_t *out, uint64_t n) {
+    gather_body<false>(rec, n_rec, idx, out, n, nullptr, 0);
+}
+
+// The same gather marking ties with the previous output record (the keyed
+// sort's first tie round reads these flags instead of the records).
+__global__ __launch_bounds__(kWG) void k_gather_ties(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx,
+                                                     uint8_t *out, uint64_t n, uint8_t *ties, int has_prev) {
+    gather_body<true>(rec, n_rec, idx, out, n, ties, has_prev);
 }
 
 // Extraction alone (tuples + byte-0 histogram) for the step-level test entry point.
@@ -1417,10 +1463,13 @@ hipError_t launch_local_part(const Work &w, const Tune &t, hipStream_t s, int cu
 }
 
 hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,
-                                uint64_t n, hipStream_t s) {
+                                uint64_t n, hipStream_t s, uint8_t *ties, bool has_prev) {
     if (n == 0) return hipSuccess;
     const uint64_t blocks = (n + kWG - 1) / kWG;
-    k_gather_plain<<<dim3((uint32_t)blocks), dim3(kWG), 0, s>>>(rec, n_rec, idx, out, n);
+    if (ties)
+        k_gather_ties<<<dim3((uint32_t)blocks), dim3(kWG), 0, s>>>(rec, n_rec, idx, out, n, ties, has_prev ? 1 : 0);
+    else
+        k_gather_plain<<<dim3((uint32_t)blocks), dim3(kWG), 0, s>>>(rec, n_rec, idx, out, n);
     return hipGetLastError();
 }
 
