@@ -80,9 +80,9 @@ int leyenda_sort(const void *records_dev, uint64_t n, void *out_dev, void *strea
  * stable sort of (run number, next bytes, position) entries and permuting the
  * runs' records to match; rounds end when no tie is left or the key is used
  * up.  Buffers and errors as leyenda_sort, plus LEYENDA_EINVAL for key_bytes
- * outside 1..100 and LEYENDA_ENOMEM when the rounds' scratch (200 bytes per
- * record inside a tie run, plus 24 bytes per 1,024 records) cannot be
- * allocated.  With key_bytes > 10 the call returns after the stream has
+ * outside 1..100 and LEYENDA_ENOMEM when the rounds' scratch (216 bytes per
+ * record inside a tie run, plus one byte per record and 24 bytes per 1,024
+ * records) cannot be allocated.  With key_bytes > 10 the call returns after the stream has
  * drained (it reads each round's tie count on the host). */
 int leyenda_sort_keyed(const void *records_dev, uint64_t n, uint32_t key_bytes, void *out_dev, void *stream);
 
