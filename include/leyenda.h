@@ -220,8 +220,9 @@ int leyenda_serve_replay(const leyenda_server_config *cfg, uint64_t count, const
  * Defaults: digit_bits 8, tile_items 32, big_threshold 2048, tiny_threshold 128,
  * local_capacity 2048, scatter_threads 1024, local_threads 512 (the fastest of
  * the autotuner's sweep on the 10 GB uniform and 20 GB skewed workloads; the
- * tiny threshold also on printable-key workloads, whose local-sort tasks pack
- * sub-buckets of about a hundred keys).
+ * tiny threshold from a later sweep of 64..256 on those and on printable keys,
+ * whose local-sort tasks pack sub-buckets of about a hundred keys and gain
+ * from it, while the binary workloads do not change).
  * digit_bits     radix digit width in bits (8: 256 buckets per pass, Algorithm 1).
  * tile_items     keys per thread in a device-wide partition tile (8, 16 or 32;
  *                a tile is 256 * tile_items keys).
