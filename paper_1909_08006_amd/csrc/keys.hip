@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kTB) void k_tie_scatter(const uint32_t *R, const ui
 }
 
 struct Scratch {
-    void *p[8] = {};
+    void *p[7] = {};
     ~Scratch() {
         for (void *q : p)
             if (q) (void)hipFree(q);
@@ -260,10 +260,10 @@ int resolve_ties(uint32_t *A, uint64_t n, uint32_t key_bytes, hipStream_t s, con
         if (m > nc || h[1] > m / 2) return fail(LEYENDA_EHIP, "leyenda_sort_keyed: inconsistent tie count");
         if (!E) {
             cap = m;
-            if ((rc = alloc(&sc.p[6], cap * kRec * 2)) || (rc = alloc(&sc.p[7], cap * 16))) return rc;
-            E = static_cast<uint32_t *>(sc.p[6]);
+            if ((rc = alloc(&sc.p[5], cap * kRec * 2)) || (rc = alloc(&sc.p[6], cap * 16))) return rc;
+            E = static_cast<uint32_t *>(sc.p[5]);
             E2 = E + cap * kRecWords;
-            dest[0] = static_cast<uint64_t *>(sc.p[7]);
+            dest[0] = static_cast<uint64_t *>(sc.p[6]);
             dest[1] = dest[0] + cap;
         }
         k_tie_emit<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(A, P, nc, r ? dest[(r - 1) & 1] : nullptr, p, key_bytes,
