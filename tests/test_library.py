@@ -107,3 +107,18 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_keyed_sort_argument_checks():
+    """leyenda_sort_keyed rejects bad key sizes and buffers before any device work."""
+    import paper_1909_08006_amd as ley
+    lib = ley.load()
+    einval = -1
+    assert lib.leyenda_status_string(einval) != b"ok"
+    for kb in (0, 101, 1000):
+        assert lib.leyenda_sort_keyed(None, 10, kb, None, None) == einval
+        assert b"key_bytes" in lib.leyenda_last_error()
+    assert lib.leyenda_sort_keyed(None, 0, 20, None, None) == 0  # nothing to sort
+    assert lib.leyenda_sort_keyed(None, 10, 20, None, None) == einval  # NULL buffers
+    assert lib.leyenda_sort_keyed(ctypes.c_void_p(4096), 10, 20, ctypes.c_void_p(4098), None) == einval  # misaligned
+    assert lib.leyenda_sort_keyed(ctypes.c_void_p(4096), 10, 20, ctypes.c_void_p(4096 + 500), None) == einval  # overlap
