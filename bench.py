@@ -9,7 +9,11 @@ resident in HBM before the timed region; one step = one full leyenda_sort
 
 Prints one JSON line: GB/s of records sorted, the roofline of the dominant
 kernel (from HIP events recorded around each phase on the sort's stream),
-and the CPU oracle timed on a bounded sample of the same workload.
+and the CPU oracle timed on a bounded sample of the same workload.  Further
+objects on the same line (each can be skipped by a flag): `serving` (batched
+vs per-request serving of 2,000 requests), `copy_ceiling`, `flexible_keys`
+(leyenda_sort_keyed with 4- and 20-byte keys), `ascii_keys` (the 20 GB
+printable-key workload) and `external` (60 GB through a 30 GB device budget).
 """
 from __future__ import annotations
 
