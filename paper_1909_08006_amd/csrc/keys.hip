@@ -193,14 +193,16 @@ __global__ __launch_bounds__(kTB) void k_tie_emit(const uint32_t *A, const uint8
     }
 }
 
-// out[t] = A[position held by sorted entry t], one dword per thread.
-__global__ __launch_bounds__(kTB) void k_tie_gather(const uint32_t *A, const uint32_t *E2, uint64_t m,
+// out[t] = A[position held by sorted entry t], one dword per thread (a
+// position outside the n records, which only a failed entry sort could leave,
+// is skipped rather than read).
+__global__ __launch_bounds__(kTB) void k_tie_gather(const uint32_t *A, uint64_t n, const uint32_t *E2, uint64_t m,
                                                     uint32_t *out) {
     const uint64_t g = (uint64_t)blockIdx.x * kTB + threadIdx.x;
     if (g >= m * kRecWords) return;
     const uint64_t t = g / kRecWords, d = g - t * kRecWords;
     const uint64_t j = (uint64_t)E2[t * kRecWords + 3] | ((uint64_t)E2[t * kRecWords + 4] << 32);
-    out[g] = A[j * kRecWords + d];
+    if (j < n) out[g] = A[j * kRecWords + d];
 }
 
 // A[dest[t]] = R[t], one dword per thread.
@@ -271,7 +273,7 @@ int resolve_ties(uint32_t *A, uint64_t n, uint32_t key_bytes, hipStream_t s, con
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: entries");
         if ((rc = sort_device(E, m, E2, s, t))) return rc;
         const uint64_t blocks = (m * kRecWords + kTB - 1) / kTB;
-        k_tie_gather<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(A, E2, m, E);  // E is free again
+        k_tie_gather<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(A, n, E2, m, E);  // E is free again
         k_tie_scatter<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(E, dest[r & 1], m, A);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: permute");
         nc = m;  // the next round looks only inside these runs
