@@ -81,16 +81,52 @@ def pmc_traffic(n: int, kernel: str):
     return int(float(fields["hbm_bytes_per_launch"]))
 
 
-def cpu_baseline(host_u8, n_sample: int) -> dict:
+def host_cpu() -> dict:
+    """Host CPU facts for the baseline: logical CPUs visible, the CPUs this
+    process may run on, and the model name."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+# The paper's CPU sort-phase times for 10 GB of uniform 100-byte records
+# (Table 1, Section 2.2): its first radix sort and GNU's parallel sorts.  The
+# paper does not name the machine for this table; its contest testbed (Table 2,
+# Section 4.1) is two Xeon E5-2640 v4 (20 cores, 40 hardware threads), 30 GB.
+PAPER_TABLE1_S = {"leyenda_radix_sort": 2.238, "gnu_parallel_sort": 7.443, "gnu_parallel_stable_sort": 17.917,
+                  "hardware": "not stated for Table 1; the paper's testbed (Table 2) is 2x Xeon E5-2640 v4 "
+                              "(20 cores, 40 threads), 30 GB"}
+
+
+def cpu_baseline(host_u8, n: int, n_one: int):
+    """The oracle on the host: the whole workload on every host thread
+    (``oracle_sort_par``: per-thread qsort slices, merged), plus one thread on
+    the first ``n_one`` records.  Returns (cpu_baseline object, oracle output)."""
     import oracle
-    rec = host_u8[: n_sample * 100].numpy().reshape(n_sample, 100)
-    log(f"cpu baseline: oracle sort of {n_sample} records ...")
+    rec = host_u8[: n * 100].numpy().reshape(n, 100)
+    threads = oracle.host_threads()
+    log(f"cpu baseline: oracle sort of {n:,} records on {threads} threads ...")
     t0 = time.perf_counter()
-    oracle.sort(rec)
+    want = oracle.sort(rec, threads=0)
     dt = time.perf_counter() - t0
-    return {"value": round(n_sample * 100 / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_sample:,} records ({n_sample * 100 / 1e9:.1f} GB) of the same workload; "
-                      f"qsort of (key, index) by memcmp then record gather, one thread, {dt:.1f} s"}
+    log(f"cpu baseline: oracle sort of {n_one:,} records on one thread ...")
+    t0 = time.perf_counter()
+    oracle.sort(rec[:n_one])
+    dt1 = time.perf_counter() - t0
+    res = {"value": round(n * 100 / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": f"the whole workload ({n:,} records, {n * 100 / 1e9:.1f} GB): (key, index) pairs sorted by "
+                     f"memcmp then index in {threads} qsort slices merged on {threads} threads, then the record "
+                     f"gather; {dt:.2f} s",
+           "seconds": round(dt, 3), "host": host_cpu(),
+           "one_thread": {"records": n_one, "seconds": round(dt1, 3), "gbs": round(n_one * 100 / dt1 / 1e9, 4)},
+           "paper_table1_sort_s_10gb": PAPER_TABLE1_S}
+    return res, want
 
 
 def serving(ley, count: int, warm: int, budget: int) -> dict:
@@ -207,10 +243,13 @@ def flexible_keys(ley, torch, datagen, dev, steps: int) -> dict:
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps
 
+    def guard():  # key sizes above 10 report a fired guard as an error; these read the prefix sort's
+        return ley.stats(torch.cuda.current_stream())["guard"]
+
     for kb in (4, 20):
         ms = timed(dev, out, kb)
         res[f"uniform_1e8_k{kb}"] = {"ms_per_sort": round(ms, 3), "gbs": round(n * 100 / (ms / 1e3) / 1e9, 2),
-                                      "ordered": prefix_ordered(torch, out, n, kb)}
+                                      "ordered": prefix_ordered(torch, out, n, kb), "guard": guard()}
     del out
     torch.cuda.empty_cache()
     m = 200_000_000
@@ -224,7 +263,8 @@ def flexible_keys(ley, torch, datagen, dev, steps: int) -> dict:
     ms10 = timed(sk, out, 10)
     ms = timed(sk, out, 20)
     res["skewed_2e8_k20"] = {"ms_per_sort": round(ms, 3), "gbs": round(m * 100 / (ms / 1e3) / 1e9, 2),
-                             "ms_per_sort_k10": round(ms10, 3), "ordered": prefix_ordered(torch, out, m, 20)}
+                             "ms_per_sort_k10": round(ms10, 3), "ordered": prefix_ordered(torch, out, m, 20),
+                             "guard": guard()}
     del sk, out
     torch.cuda.empty_cache()
     res["steps"] = steps
@@ -252,6 +292,7 @@ def ascii_keys(ley, torch, datagen, steps: int) -> dict:
         ley.sort(dev, out, stream)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    guard = st["guard"] | ley.stats(stream)["guard"]
     ok = keys_ordered(torch, out, n)
     del dev, out
     torch.cuda.empty_cache()
@@ -259,19 +300,20 @@ def ascii_keys(ley, torch, datagen, steps: int) -> dict:
                         "uniform over 0x20..0x7E", "steps": steps, "ms_per_step": round(ms, 3),
             "gbs": round(n * 100 / (ms / 1e3) / 1e9, 2),
             "partition_passes": round(sum(st["moved"]) / n, 4), "levels": st["levels"],
-            "output_keys_ordered": ok}
+            "output_keys_ordered": ok, "guard": guard}
 
 
-def external(ley, torch, datagen) -> dict:
+def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9) -> dict:
     """The 60 GB limited-memory workload: 600,000,000 records in pinned host
     memory, 30 GB device budget, sorted runs written over the input, then the
     k-way merge into pageable host memory (the pinned limit of the host holds
     the input only).  Bound: PCIe, 200 B/record each way, the two directions
     overlapped at their measured single-direction rates.  The merge runs twice
     into the same output: first into fresh memory (its first-touch page faults
-    included), then into the now resident buffer (a reused output)."""
+    included), then into the now resident buffer (a reused output).  Then the
+    keys-only variant on the regenerated input.  (n and budget: smaller
+    instances of the same workload, e.g. under a profiler.)"""
     import numpy as np
-    n, budget = 600_000_000, 30 * 10**9
     # PCIe rates with a pinned 2 GB buffer (HIP events, best of 3): each way
     # alone, and both ways at once on two streams
     part = ley.pinned_empty(2_000_000_000)
@@ -322,13 +364,25 @@ def external(ley, torch, datagen) -> dict:
     step = 1_000_000  # sampled order check (every millionth neighbour pair)
     keys = out[::step, :10]
     ok = bool(all(bytes(keys[i]) <= bytes(keys[i + 1]) for i in range(len(keys) - 1)))
-    del keys, out, runs
+    del keys, runs
+    # keys-only variant on the same (regenerated) input, into the same output buffer
+    log("external: keys-only variant ...")
+    datagen.fill_uniform(a.data_ptr(), n, datagen.SEED_EXTERNAL)
+    t0 = time.perf_counter()
+    ley.sort_external_keys(a, budget, host_out=torch.from_numpy(out).view(-1))
+    t_keys = time.perf_counter() - t0
+    keys = out[::step, :10]
+    ok_keys = bool(all(bytes(keys[i]) <= bytes(keys[i + 1]) for i in range(len(keys) - 1)))
+    del keys, out
     ley.pinned_free(a)
     # 200 B/record each way (runs: up + down; merge: up + down); the two directions
     # at their own single-direction rates, fully overlapped, is a lower bound on
     # any box (the rate of two concurrent copies issued from torch has varied
     # from box to box, 57-97 GB/s, while the runs moved 89 GB/s both ways)
     both_bound = max(n * 200 / (rates["h2d"] * 1e9), n * 200 / (rates["d2h"] * 1e9))
+    # keys-only: 200 B/record up (the input read once in order, then every
+    # record again by the gather) and 100 B/record down
+    keys_bound = max(n * 200 / (rates["h2d"] * 1e9), n * 100 / (rates["d2h"] * 1e9))
     return {"workload": "600,000,000 x 100-byte records (60 GB) in pinned host memory, 30 GB device budget, "
                         "uniform keys; runs over the input, merge into pageable host memory",
             "runs": len(bounds) - 1, "t_runs_s": round(t_runs, 3),
@@ -338,7 +392,11 @@ def external(ley, torch, datagen) -> dict:
             "pcie_measured_gbs": rates,
             "pcie_bound": {"bytes_per_record_each_way": 200, "bound_s_each_way_rates_overlapped": round(both_bound, 3),
                            "frac": round(both_bound / (t_runs + t_merge[1]), 3)},
-            "sampled_order_ok": ok}
+            "sampled_order_ok": ok,
+            "keys_only": {"t_s": round(t_keys, 3), "gbs_records_end_to_end": round(n * 100 / t_keys / 1e9, 2),
+                          "pcie_bound": {"bytes_per_record_up": 200, "bytes_per_record_down": 100,
+                                         "bound_s": round(keys_bound, 3), "frac": round(keys_bound / t_keys, 3)},
+                          "sampled_order_ok": ok_keys}}
 
 
 def main() -> int:
@@ -347,11 +405,17 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=100_000_000, help="records (default: the 10 GB workload)")
-    ap.add_argument("--cpu-sample", type=int, default=50_000_000, help="records the oracle sorts for cpu_baseline")
+    ap.add_argument("--cpu-sample", type=int, default=10_000_000,
+                    help="records the one-thread oracle run of cpu_baseline sorts")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (batched vs per-request) comparison")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-external", action="store_true", help="skip the 60 GB runs + merge workload")
+    ap.add_argument("--external-n", type=int, default=600_000_000, help="records of the external workload")
+    ap.add_argument("--external-budget", type=int, default=30 * 10**9, help="device budget of the external workload")
+    ap.add_argument("--workload", choices=["uniform", "skewed", "ascii"], default="uniform",
+                    help="keys of the timed internal sort: uniform (the 10 GB workload), skewed (Zipf prefixes, "
+                         "5%% duplicates) or printable ASCII; --n sets the size")
     ap.add_argument("--no-ascii", action="store_true", help="skip the 20 GB printable-key workload")
     ap.add_argument("--no-keys", action="store_true", help="skip the flexible key size (leyenda_sort_keyed) runs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -364,15 +428,22 @@ def main() -> int:
               "(run with --gpus 1)", file=sys.stderr)
         return 2
 
+    import numpy as np
     import torch
     import datagen
     import paper_1909_08006_amd as ley
 
     ley.load()
     n = args.n
-    log(f"generating {n:,} records ({n * 100 / 1e9:.1f} GB, seed {datagen.SEED_INTERNAL}) ...")
+    fill, seed, keys = {
+        "uniform": (datagen.fill_uniform, datagen.SEED_INTERNAL, "uniform 10-byte keys"),
+        "skewed": (datagen.fill_skewed, datagen.SEED_SKEWED,
+                   "skewed keys (Zipf(1.2) 4-byte prefixes over 65,536 values, 5% exact duplicates)"),
+        "ascii": (datagen.fill_ascii, datagen.SEED_ASCII, "keys of 10 printable ASCII bytes"),
+    }[args.workload]
+    log(f"generating {n:,} records ({n * 100 / 1e9:.1f} GB, {args.workload}, seed {seed}) ...")
     host = torch.empty(n * 100, dtype=torch.uint8, pin_memory=True)
-    datagen.fill_uniform(host.data_ptr(), n, datagen.SEED_INTERNAL)
+    fill(host.data_ptr(), n, seed)
     dev = host.to("cuda:0", non_blocking=True)
     out = torch.empty_like(dev)
     torch.cuda.synchronize()
@@ -405,8 +476,12 @@ def main() -> int:
     ms = (t1 - t0) * 1e3 / args.steps
     gbs = n * 100 / (ms / 1e3) / 1e9
     avg = {k: v / max(calls, 1) for k, v in phases.items()}
+    # device-side guards of the warm-up sort and of the last timed sort
+    guards = {"warmup": st["guard"], "timed": ley.stats(stream)["guard"]}
+    ok = guards["warmup"] == 0 and guards["timed"] == 0
 
     ordered = keys_ordered(torch, out, n)
+    ok = ok and ordered
 
     moved = sum(st["moved"])
     passes = moved / n
@@ -425,8 +500,8 @@ def main() -> int:
         "metric": METRIC, "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "internal sort, 100,000,000 x 100-byte records (10 GB) in HBM, uniform 10-byte keys",
-                   "n_records": n, "record_bytes": 100, "key_bytes": 10, "seed": datagen.SEED_INTERNAL,
+        "config": {"workload": f"internal sort, {n:,} x 100-byte records ({n * 100 / 1e9:g} GB) in HBM, {keys}",
+                   "n_records": n, "record_bytes": 100, "key_bytes": 10, "seed": seed,
                    "params": ley.get_params()},
         "roofline": {"bound": "hbm", "kernel": KERNEL_OF[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -441,6 +516,7 @@ def main() -> int:
         "sort_roofline_frac": round(b_alg * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "floor_frac_210B": round(210 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "output_keys_ordered": ordered,
+        "device_guards": guards,
     }
     pf = pmc_fields(n)
     if pf and "sort_hbm_bytes_per_record" in pf:
@@ -448,32 +524,37 @@ def main() -> int:
         bpr = float(pf["sort_hbm_bytes_per_record"])
         res["sort_hbm_traffic"] = {"bytes_per_record": bpr, "gbs": round(bpr * n / (ms / 1e3) / 1e9, 1),
                                    "source": os.path.relpath(PMC_FILE, ROOT)}
+    if not args.no_cpu_baseline:
+        # the oracle on the host cores, and the timed sort's output against it record by record
+        res["cpu_baseline"], want = cpu_baseline(host, n, min(args.cpu_sample, n))
+        got = out.cpu().numpy().reshape(n, 100)
+        res["output_matches_oracle"] = bool(np.array_equal(got, want))
+        ok = ok and res["output_matches_oracle"]
+        del got, want
+    del out
+    torch.cuda.empty_cache()
     if not args.no_serve:
-        del out
-        torch.cuda.empty_cache()
         res["serving"] = serving(ley, args.serve_requests, 50, 32 * 10**9)
     res["copy_ceiling"] = copy_ceiling(torch)
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(host, min(args.cpu_sample, n))
     del host
     if hasattr(torch._C, "_host_emptyCache"):  # return the cached pinned block (host pinned limit)
         torch._C._host_emptyCache()
     if not args.no_keys:
         res["flexible_keys"] = flexible_keys(ley, torch, datagen, dev, min(args.steps, 5))
-        ordered = ordered and all(v["ordered"] for k, v in res["flexible_keys"].items() if k != "steps")
+        ok = ok and all(v["ordered"] and v["guard"] == 0 for k, v in res["flexible_keys"].items() if k != "steps")
     if not args.no_ascii:
         res["ascii_keys"] = ascii_keys(ley, torch, datagen, args.steps)
-        ordered = ordered and res["ascii_keys"]["output_keys_ordered"]
+        ok = ok and res["ascii_keys"]["output_keys_ordered"] and res["ascii_keys"]["guard"] == 0
     if not args.no_external:
         torch.cuda.empty_cache()
         if hasattr(torch._C, "_host_emptyCache"):  # return the cached pinned block (host pinned limit)
             torch._C._host_emptyCache()
         try:
-            res["external"] = external(ley, torch, datagen)
+            res["external"] = external(ley, torch, datagen, args.external_n, args.external_budget)
         except ley.LeyendaError as exc:  # e.g. the host cannot pin 60 GB: report, keep the line
             res["external"] = {"skipped": str(exc)}
     print(json.dumps(res), flush=True)
-    return 0 if ordered else 1
+    return 0 if ok else 1
 
 
 if __name__ == "__main__":

@@ -135,6 +135,30 @@ int leyenda_sort_runs(const void *host_records, uint64_t n, uint64_t device_budg
 int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, uint64_t k, void *host_out,
                   uint64_t device_budget_bytes, void *stream);
 
+/* Keys-only external sort (Section 3.2: key-pointer tuples extracted while
+ * the input is read, sorted, then the records scattered by the sorted
+ * tuples).  The input streams host -> device in chunks and every record's
+ * 16-byte (key, index) tuple is kept on the device; all n tuples are then
+ * sorted in one device-resident pass (Algorithm 1), and the records are
+ * gathered in sorted order by device loads straight from the pinned input
+ * (PCIe reads of 100-byte records) and streamed to host_out.  No runs, no
+ * merge: it needs the tuples and sort tables of all n records on the device
+ * (leyenda_workspace_bytes(n) + 256 bytes, about 43 bytes per record), and
+ * returns LEYENDA_EBUDGET, touching nothing, when device_budget_bytes is
+ * below that (leyenda_sort_runs + leyenda_merge then fit).
+ *   host_records: n records in pinned host memory (read only; the gather
+ *                 reads it through its device mapping).
+ *   host_out:     n records of host memory, pinned (written by the copy
+ *                 engine) or pageable (through pinned bounce buffers and host
+ *                 copies); must not overlap host_records.
+ * Output: the stable sort of the records by their 10-byte key, the same bytes
+ * as leyenda_sort.  Synchronous: returns when host_out is complete.
+ * LEYENDA_EINVAL (NULL, misaligned, overlapping, unpinned input),
+ * LEYENDA_ETOOBIG (n > LEYENDA_MAX_RECORDS), LEYENDA_ENOMEM, LEYENDA_EHIP,
+ * LEYENDA_EINTERNAL (a device-side guard of the sort fired). */
+int leyenda_sort_external_keys(const void *host_records, uint64_t n, uint64_t device_budget_bytes,
+                               void *host_out, void *stream);
+
 /* Pinned host memory for the external path (hipHostMalloc; exactly `bytes`,
  * no rounding).  leyenda_host_free(NULL) is a no-op. */
 int leyenda_host_alloc(uint64_t bytes, void **out);
@@ -223,7 +247,10 @@ int leyenda_serve_replay(const leyenda_server_config *cfg, uint64_t count, const
  * tiny threshold from a later sweep of 64..256 on those and on printable keys,
  * whose local-sort tasks pack sub-buckets of about a hundred keys and gain
  * from it, while the binary workloads do not change).
- * digit_bits     radix digit width in bits (8: 256 buckets per pass, Algorithm 1).
+ * digit_bits     radix digit width in bits, 4..8 (8: 256 buckets per pass, the
+ *                byte digit of Algorithm 1; a narrower digit splits each big
+ *                bucket 2^digit_bits ways and needs up to ceil(80 / digit_bits)
+ *                partition levels).
  * tile_items     keys per thread in a device-wide partition tile (8, 16 or 32;
  *                a tile is 256 * tile_items keys).
  * big_threshold  buckets with more keys than this get another device-wide
@@ -256,10 +283,11 @@ int leyenda_load_params(const char *json_path);
 /* ---------------------------------------------------------------------------
  * Diagnostics.
  * ------------------------------------------------------------------------- */
+#define LEYENDA_MAX_LEVELS 20 /* partition levels of the narrowest digit (4 bits over 80 key bits) */
 typedef struct {
     uint32_t levels;          /* device-wide partition levels that moved data */
-    uint32_t segments[12];    /* big buckets planned at each level */
-    uint64_t moved[12];       /* keys moved by the device-wide partition at each level */
+    uint32_t segments[LEYENDA_MAX_LEVELS]; /* big buckets planned at each level */
+    uint64_t moved[LEYENDA_MAX_LEVELS];    /* keys moved by the device-wide partition at each level */
     uint64_t tasks;           /* local-sort tasks */
     uint32_t guard;           /* nonzero if a device-side capacity guard fired */
 } leyenda_stats;
@@ -288,16 +316,28 @@ const char *leyenda_last_error(void);
 int leyenda_release_workspaces(void);
 
 /* ---------------------------------------------------------------------------
- * Step-level entry points used by the parity tests (same kernels as the sort).
+ * Step-level entry points used by the parity tests.
  *
- * leyenda_debug_extract: for each record i, hi[i] = big-endian key bytes 0..7,
- *   lo[i] = (big-endian key bytes 8..9) << 32 | i, and hist[b] = number of
- *   records whose key byte 0 is b (256 counters).  All device pointers.
- * leyenda_debug_gather: out[j] = records[idx[j]] for j < n (device pointers;
- *   idx holds n indices below n_records).
+ * leyenda_debug_extract: the first stage of leyenda_sort alone -- the request
+ *   table, the level-0 bucket and the sort's own extraction kernel, launched
+ *   exactly as the sort launches it (same tiles, key masks and histogram
+ *   replicas) on the workspace of `stream` -- for the key-pointer tuples of
+ *   Section 3.2 and the first-digit histogram of Algorithm 1.  For record i:
+ *   hi[i] = big-endian key bytes 0..7 and lo[i] = (big-endian key bytes 8..9)
+ *   << 32 | i, with the bytes at and past key_bytes (1..10) cleared (the
+ *   masked prefix of leyenda_sort_keyed); hist[d] = number of records whose
+ *   leading digit_bits (leyenda_params) key bits equal d, 256 counters (those
+ *   at and above 2^digit_bits stay zero).  All device pointers: records 4-byte
+ *   aligned, hi and lo 8-byte aligned (n entries each), hist 256 u32.
+ *   Asynchronous on `stream`.  LEYENDA_EINVAL for NULL or misaligned buffers
+ *   or key_bytes outside 1..10, LEYENDA_ETOOBIG for n > LEYENDA_MAX_RECORDS,
+ *   LEYENDA_ENOMEM if the workspace cannot be allocated.
+ * leyenda_debug_gather: out[j] = records[idx[j]] for j < n with the sort's
+ *   record gather kernel (device pointers; idx holds n indices below
+ *   n_records).
  * ------------------------------------------------------------------------- */
-int leyenda_debug_extract(const void *records_dev, uint64_t n, uint64_t *hi_dev, uint64_t *lo_dev,
-                          uint32_t *hist_dev, void *stream);
+int leyenda_debug_extract(const void *records_dev, uint64_t n, uint32_t key_bytes, uint64_t *hi_dev,
+                          uint64_t *lo_dev, uint32_t *hist_dev, void *stream);
 int leyenda_debug_gather(const void *records_dev, uint64_t n_records, const uint32_t *idx_dev,
                          uint64_t n, void *out_dev, void *stream);
 

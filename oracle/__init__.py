@@ -50,6 +50,10 @@ def _load():
     vp, u64 = ctypes.c_void_p, ctypes.c_uint64
     lib.oracle_sort.argtypes = [vp, u64, vp, vp]
     lib.oracle_sort.restype = ctypes.c_int
+    lib.oracle_sort_par.argtypes = [vp, u64, vp, vp, ctypes.c_int]
+    lib.oracle_sort_par.restype = ctypes.c_int
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = ctypes.c_int
     lib.oracle_sort_key.argtypes = [vp, u64, ctypes.c_uint32, vp, vp]
     lib.oracle_sort_key.restype = ctypes.c_int
     lib.oracle_output_rank.argtypes = [vp, u64, vp, u64, vp]
@@ -76,9 +80,13 @@ def _ptr(a: np.ndarray) -> ctypes.c_void_p:
     return ctypes.c_void_p(a.ctypes.data)
 
 
-def sort(records, return_perm: bool = False, key_bytes: int = KEY):
+def sort(records, return_perm: bool = False, key_bytes: int = KEY, threads: int = 1):
     """Stable sort of records by their key (memcmp order): the 10-byte key, or
-    the first ``key_bytes`` bytes (1..100, the flexible key sizes of Section 5)."""
+    the first ``key_bytes`` bytes (1..100, the flexible key sizes of Section 5).
+
+    ``threads`` != 1 (0: every host thread) sorts the 10-byte key with
+    ``oracle_sort_par``: slices sorted by the same comparison, then merged --
+    the same result, pinned against the one-thread sort."""
     rec = _as_records(records)
     n = rec.shape[0]
     if not 1 <= key_bytes <= REC:
@@ -86,13 +94,20 @@ def sort(records, return_perm: bool = False, key_bytes: int = KEY):
     out = np.empty_like(rec)
     perm = np.empty(n, dtype=np.uint32)
     if n:
-        if key_bytes == KEY:
+        if key_bytes == KEY and threads != 1:
+            rc = 0 if _load().oracle_sort_par(_ptr(rec), n, _ptr(out), _ptr(perm), int(threads)) > 0 else -1
+        elif key_bytes == KEY:
             rc = _load().oracle_sort(_ptr(rec), n, _ptr(out), _ptr(perm))
         else:
             rc = _load().oracle_sort_key(_ptr(rec), n, key_bytes, _ptr(out), _ptr(perm))
         if rc != 0:
             raise MemoryError("oracle sort failed")
     return (out, perm) if return_perm else out
+
+
+def host_threads() -> int:
+    """Threads the parallel oracle runs on when asked for all of them."""
+    return int(_load().oracle_threads())
 
 
 def output_rank(records, samples) -> np.ndarray:

@@ -27,6 +27,8 @@
  *   oracle_ties_in_order  equal-key runs of an output hold their records in
  *                         input order (with the two checks above, this
  *                         pins a large output without a full oracle sort)
+ *   oracle_sort_par       oracle_sort on several host threads (slices sorted
+ *                         by the same comparison, then merged); the same result
  *   oracle_sort_key       the same stable sort with a key of the first K
  *                         bytes, 1 <= K <= 100: the flexible key sizes that
  *                         Section 5 names as the method's next step (same
@@ -34,6 +36,7 @@
  *                         keys in input order)
  */
 #define _GNU_SOURCE
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -77,6 +80,88 @@ int oracle_sort(const uint8_t *rec, uint64_t n, uint8_t *out, uint32_t *perm) {
     }
     free(t);
     return 0;
+}
+
+/* ---- oracle_sort_par ---------------------------------------------------------- */
+
+/* Host threads the parallel oracle uses when asked for 0 (all of them). */
+int oracle_threads(void) { return omp_get_max_threads(); }
+
+/* Number of elements the first r outputs of merging the sorted arrays a (na
+ * elements) and b (nb) take from a.  The (key, index) order is total -- no
+ * two pairs compare equal -- so the split is unique: the largest i with
+ * a[i-1] < b[r-i], found by binary search. */
+static uint64_t merge_split(const key_idx *a, uint64_t na, const key_idx *b, uint64_t nb, uint64_t r) {
+    uint64_t lo = r > nb ? r - nb : 0, hi = r < na ? r : na;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (cmp_key_idx(&a[mid], &b[r - mid - 1]) < 0) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+/* The same stable sort as oracle_sort, on `threads` host threads (0: all).
+ * The (key, index) pairs are cut into one slice per thread; each slice is
+ * sorted by qsort under the comparison oracle_sort uses; neighbouring sorted
+ * slices are then merged pairwise until one remains, each merge cut into
+ * per-thread pieces at exact output ranks (merge_split), and the records are
+ * gathered.  Since no two pairs compare equal, the merged order is the one
+ * qsort gives over the whole array.  Returns the thread count used, or -1 if
+ * memory could not be allocated. */
+int oracle_sort_par(const uint8_t *rec, uint64_t n, uint8_t *out, uint32_t *perm, int threads) {
+    if (threads <= 0) threads = omp_get_max_threads();
+    if (n == 0) return threads;
+    if (n >= 0xFFFFFFFFull) return -1;
+    key_idx *a = (key_idx *)malloc(sizeof(key_idx) * n);
+    key_idx *b = (key_idx *)malloc(sizeof(key_idx) * n);
+    uint64_t *bnd = (uint64_t *)malloc(sizeof(uint64_t) * ((uint64_t)threads + 1));
+    if (!a || !b || !bnd) { free(a); free(b); free(bnd); return -1; }
+#pragma omp parallel for num_threads(threads) schedule(static)
+    for (int64_t i = 0; i < (int64_t)n; i++) {
+        memcpy(a[i].key, rec + (uint64_t)i * REC, KEY);
+        a[i].pad[0] = a[i].pad[1] = 0;
+        a[i].idx = (uint32_t)i;
+    }
+    uint64_t ns = (uint64_t)threads;  /* slices: bnd[k] .. bnd[k + 1] */
+    for (uint64_t k = 0; k <= ns; k++) bnd[k] = n * k / ns;
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 1)
+    for (int64_t k = 0; k < (int64_t)ns; k++)
+        qsort(a + bnd[k], bnd[k + 1] - bnd[k], sizeof(key_idx), cmp_key_idx);
+    while (ns > 1) {
+        /* merge slices (2m, 2m + 1) into b; an odd last slice is copied */
+        const uint64_t pairs = (ns + 1) / 2;
+        const uint64_t pieces = (uint64_t)threads;
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 1) collapse(2)
+        for (int64_t m = 0; m < (int64_t)pairs; m++) {
+            for (int64_t p = 0; p < (int64_t)pieces; p++) {
+                const uint64_t lo = bnd[2 * m], mid = 2 * m + 1 <= ns ? bnd[2 * m + 1] : bnd[ns];
+                const uint64_t hi = 2 * m + 2 <= ns ? bnd[2 * m + 2] : bnd[ns];
+                const uint64_t na = mid - lo, nb = hi - mid, tot = hi - lo;
+                const uint64_t r0 = tot * (uint64_t)p / pieces, r1 = tot * (uint64_t)(p + 1) / pieces;
+                uint64_t i = merge_split(a + lo, na, a + mid, nb, r0);
+                uint64_t j = r0 - i;
+                const uint64_t i1 = merge_split(a + lo, na, a + mid, nb, r1), j1 = r1 - i1;
+                for (uint64_t o = lo + r0; o < lo + r1; o++) {
+                    if (j >= j1 || (i < i1 && cmp_key_idx(&a[lo + i], &a[mid + j]) < 0)) b[o] = a[lo + i++];
+                    else b[o] = a[mid + j++];
+                }
+            }
+        }
+        for (uint64_t m = 0; m < pairs; m++) bnd[m] = bnd[2 * m];
+        bnd[pairs] = n;
+        ns = pairs;
+        key_idx *t = a; a = b; b = t;
+    }
+#pragma omp parallel for num_threads(threads) schedule(static)
+    for (int64_t j = 0; j < (int64_t)n; j++) {
+        memcpy(out + (uint64_t)j * REC, rec + (uint64_t)a[j].idx * REC, REC);
+        if (perm) perm[j] = a[j].idx;
+    }
+    free(a);
+    free(b);
+    free(bnd);
+    return threads;
 }
 
 /* ---- oracle_sort_key ---------------------------------------------------------- */

@@ -10,6 +10,7 @@ tensors are ``torch.uint8`` of shape ``(n, 100)`` (or flat, ``n * 100``).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from typing import Iterable, Sequence
@@ -18,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libleyenda.so")
 RECORD_BYTES = 100
 KEY_BYTES = 10
+MAX_LEVELS = 20  # LEYENDA_MAX_LEVELS: partition levels of the narrowest (4-bit) digit
 
 _lib = None
 
@@ -42,8 +44,8 @@ class Params(ctypes.Structure):
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [("levels", ctypes.c_uint32), ("segments", ctypes.c_uint32 * 12),
-                ("moved", ctypes.c_uint64 * 12), ("tasks", ctypes.c_uint64), ("guard", ctypes.c_uint32)]
+    _fields_ = [("levels", ctypes.c_uint32), ("segments", ctypes.c_uint32 * MAX_LEVELS),
+                ("moved", ctypes.c_uint64 * MAX_LEVELS), ("tasks", ctypes.c_uint64), ("guard", ctypes.c_uint32)]
 
 
 class Segment(ctypes.Structure):
@@ -78,6 +80,7 @@ def load():
         "leyenda_sort_parts": ([u64], ctypes.c_uint32),
         "leyenda_sort_runs": ([vp, u64, u64, vp, P64, u64, P64, vp], i32),
         "leyenda_merge": ([vp, P64, u64, vp, u64, vp], i32),
+        "leyenda_sort_external_keys": ([vp, u64, u64, vp, vp], i32),
         "leyenda_plan_runs": ([u64, u64, P64, P64], i32),
         "leyenda_sort_batch": ([ctypes.POINTER(Segment), u64, vp], i32),
         "leyenda_get_params": ([ctypes.POINTER(Params)], i32),
@@ -87,7 +90,7 @@ def load():
         "leyenda_status_string": ([i32], ctypes.c_char_p),
         "leyenda_last_error": ([], ctypes.c_char_p),
         "leyenda_release_workspaces": ([], i32),
-        "leyenda_debug_extract": ([vp, u64, vp, vp, vp, vp], i32),
+        "leyenda_debug_extract": ([vp, u64, ctypes.c_uint32, vp, vp, vp, vp], i32),
         "leyenda_debug_gather": ([vp, u64, vp, u64, vp, vp], i32),
         "leyenda_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)], i32),
         "leyenda_server_submit": ([vp, vp, u64, u64], i32),
@@ -107,7 +110,20 @@ def load():
         fn.argtypes = args
         fn.restype = res
     _lib = lib
+    # registered after torch's own exit handlers, so it runs before them
+    atexit.register(_release_at_exit)
     return lib
+
+
+def _release_at_exit() -> None:
+    """Frees the library's pooled workspaces, side streams and captured graphs
+    while the HIP runtime is still up, instead of leaving them to process
+    teardown (a no-op when nothing is held)."""
+    if _lib is not None:
+        try:
+            _lib.leyenda_release_workspaces()
+        except Exception:
+            pass
 
 
 def _check(rc: int, where: str) -> None:
@@ -233,6 +249,23 @@ def merge(host_runs, run_bounds: Sequence[int], budget_bytes: int, host_out=None
         raise ValueError("run_bounds must end at the record count")
     _check(load().leyenda_merge(host_runs.data_ptr(), b, k, host_out.data_ptr(), budget_bytes, _stream_ptr(stream)),
            "leyenda_merge")
+    return host_out
+
+
+def sort_external_keys(host_records, budget_bytes: int, host_out=None, stream=None):
+    """Keys-only external sort of pinned host records: every (key, index)
+    tuple sorted on the device at once, then the records gathered from the
+    pinned input in sorted order into ``host_out`` (pinned or pageable; a new
+    pageable tensor by default).  Needs ``workspace_bytes(n) + 256`` of device
+    budget."""
+    import torch
+    n = _nrec(host_records)
+    if host_out is None:
+        host_out = torch.empty_like(host_records, pin_memory=False)
+    elif _nrec(host_out) != n:
+        raise ValueError("host_out must hold as many records as host_records")
+    _check(load().leyenda_sort_external_keys(host_records.data_ptr(), n, budget_bytes, host_out.data_ptr(),
+                                             _stream_ptr(stream)), "leyenda_sort_external_keys")
     return host_out
 
 
@@ -383,16 +416,18 @@ def release_workspaces() -> None:
     _check(load().leyenda_release_workspaces(), "leyenda_release_workspaces")
 
 
-def debug_extract(records, stream=None):
-    """(hi, lo, hist) tuples of the extraction step, as int64 tensors + int32 histogram."""
+def debug_extract(records, key_bytes: int = KEY_BYTES, stream=None):
+    """(hi, lo, hist) of the sort's own extraction kernel: int64 tuple words and
+    the int32 histogram of the leading ``digit_bits`` key bits (256 counters);
+    key bytes at and past ``key_bytes`` (1..10) are cleared."""
     import torch
     n = _nrec(records)
     dev = records.device
     hi = torch.empty(n, dtype=torch.int64, device=dev)
     lo = torch.empty(n, dtype=torch.int64, device=dev)
     hist = torch.empty(256, dtype=torch.int32, device=dev)
-    _check(load().leyenda_debug_extract(records.data_ptr(), n, hi.data_ptr(), lo.data_ptr(), hist.data_ptr(),
-                                        _stream_ptr(stream)), "leyenda_debug_extract")
+    _check(load().leyenda_debug_extract(records.data_ptr(), n, key_bytes, hi.data_ptr(), lo.data_ptr(),
+                                        hist.data_ptr(), _stream_ptr(stream)), "leyenda_debug_extract")
     return hi, lo, hist
 
 

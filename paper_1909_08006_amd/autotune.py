@@ -1,6 +1,7 @@
 """Autotuner for the sort's tuning parameters.
 
-Sweeps the digit width, the partition tile (keys per thread), the big-bucket
+Sweeps the partition digit width (4..8 bits: 2^digit_bits buckets per level
+of Algorithm 1), the partition tile (keys per thread), the big-bucket
 threshold (Algorithm 1's bigBucketThreshold: buckets above it get another
 device-wide pass) and the radix-vs-comparison cutoff inside the local sort
 (tinyBucketThreshold), times each candidate on the GPU with HIP events on a
@@ -24,7 +25,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 DEFAULT_SPACE = {
-    "digit_bits": [8],
+    "digit_bits": [4, 6, 8],
     "tile_items": [16, 32],
     "big_threshold": [1024, 2048],
     "tiny_threshold": [32, 64, 128, 192],

@@ -73,7 +73,7 @@ std::mutex g_batch_mu;
 std::map<std::pair<int, hipStream_t>, BatchEngine> g_batch;
 
 bool same_tune(const Tune &a, const Tune &b) {
-    return a.tile_items == b.tile_items && a.tile == b.tile && a.big == b.big && a.tiny == b.tiny &&
+    return a.digit == b.digit && a.tile_items == b.tile_items && a.tile == b.tile && a.big == b.big && a.tiny == b.tiny &&
            a.scatter_wg == b.scatter_wg && a.local_wg == b.local_wg;
 }
 
@@ -265,6 +265,11 @@ void batch_forget(hipStream_t s) {
         it->second.release();
         g_batch.erase(it);
     }
+}
+
+bool batch_holds_any() {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    return !g_batch.empty();
 }
 
 void batch_release_all() {

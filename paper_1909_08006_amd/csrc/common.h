@@ -8,13 +8,16 @@ namespace ley {
 constexpr int kRec = 100;          // record bytes (Section 4.1)
 constexpr int kKeyBits = 80;       // 10-byte key
 constexpr uint32_t kKeyBytes = 10;
-constexpr int kRB = 8;             // digit width: 256-way buckets per pass (Algorithm 1)
-constexpr int kRadix = 1 << kRB;
+constexpr int kRB = 8;             // widest digit: 256-way buckets per pass (Algorithm 1's byte digit)
+constexpr int kRadix = 1 << kRB;   // counters per histogram (a narrower digit leaves the top ones at zero)
+constexpr int kMinRB = 4;          // narrowest digit width the partition levels take
 constexpr int kWG = 256;           // threads per workgroup, all kernels (4 wave64)
 constexpr int kWaves = kWG / 64;
 constexpr int kMaxRep = 64;        // histogram replicas per bucket (spreads the tiles' atomics)
 constexpr int kRepWords = kRadix + 8;  // replica: 256 counts + OR / OR-of-complement masks (4 x u64)
-constexpr int kMaxLev = (kKeyBits + kRB - 1) / kRB;  // device-wide partition levels at most
+constexpr int kMaxLev = (kKeyBits + kMinRB - 1) / kMinRB;  // device-wide partition levels at most (narrowest digit)
+// Partition levels a digit width of `bits` needs to cover the key.
+__host__ __device__ constexpr int levels_for(int bits) { return (kKeyBits + bits - 1) / bits; }
 constexpr int kLocalCap = 2048;    // keys per local (LDS) sort task
 constexpr uint16_t kNoScatter = 0xFFFF;
 
@@ -90,6 +93,7 @@ struct Hdr {
 
 // Runtime tuning values the kernels read.
 struct Tune {
+    uint32_t digit;        // partition digit width in bits (kMinRB..kRB)
     uint32_t tile_items;   // 8, 16 or 32
     uint32_t tile;         // kWG * tile_items
     uint32_t big;          // big-bucket threshold
@@ -145,6 +149,8 @@ Work bind_layout(const Layout &L, void *base);
 struct Stage {
     int lev_begin = 0, lev_end = kMaxLev;  // partition levels launched
     bool head = true;                      // k_init + k_extract first
+    bool tuples_in = false;                // head: the tuples are already in buffer 0 (level-0
+                                           // histogram pass instead of the extraction)
     bool tail = true;                      // the local sorts after
     int gate = kMaxLev;                    // the tail exits if level `gate` has big buckets
     uint32_t *flag = nullptr;              // host-visible word: 1 if level `gate` has big buckets
@@ -159,7 +165,5 @@ hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32
 // The batch gather (sizes from the device header); exits like the tail of a
 // Stage when level `gate` has big buckets.
 hipError_t launch_gather_batch(const Work &w, hipStream_t s, int gate = kMaxLev);
-hipError_t launch_debug_extract(const uint8_t *rec, uint64_t n, uint64_t *hi, uint64_t *lo,
-                                uint32_t *hist, hipStream_t s);
 
 }  // namespace ley

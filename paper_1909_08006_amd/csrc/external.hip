@@ -24,6 +24,7 @@
 #include <thread>
 #include <vector>
 
+#include "host_copy.h"
 #include "runtime.h"
 
 namespace ley {
@@ -152,6 +153,17 @@ __global__ __launch_bounds__(kWG) void k_merge_extract(const uint8_t *stage, uin
     L[q] = ((uint64_t)k.l << 32) | (uint32_t)q;
 }
 
+// Key-pointer tuples of m staged records whose input indices start at base
+// (Section 3.2: the tuples are extracted while the input is read).
+__global__ __launch_bounds__(kWG) void k_extract_chunk(const uint8_t *stage, uint64_t m, uint64_t base, uint64_t *H,
+                                                       uint64_t *L) {
+    const uint64_t q = (uint64_t)blockIdx.x * kWG + threadIdx.x;
+    if (q >= m) return;
+    const Key80 k = load_key(stage + q * kRec);
+    H[base + q] = k.h;
+    L[base + q] = ((uint64_t)k.l << 32) | (uint32_t)(base + q);
+}
+
 struct MergePair {
     uint32_t a_off, a_len, b_len, first_tile;  // sequence B starts at a_off + a_len; output covers the same range
 };
@@ -213,11 +225,17 @@ __global__ __launch_bounds__(kWG) void k_merge_pairs(const MergePair *pairs, uin
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_gather_lo(const uint8_t *stage, const uint64_t *L, uint8_t *out, uint64_t n) {
+// out[j] = stage[index in L[j]]; an index outside the chunk (only a broken
+// merge could leave one) is not read: it sets *err and leaves zeros.
+__global__ __launch_bounds__(kWG) void k_gather_lo(const uint8_t *stage, const uint64_t *L, uint8_t *out, uint64_t n,
+                                                   uint32_t *err) {
     __shared__ uint32_t sidx[kWG];
     const uint64_t g0 = (uint64_t)blockIdx.x * kWG;
     const uint32_t nr = (uint32_t)min<uint64_t>(kWG, n - g0);
-    if (threadIdx.x < nr) sidx[threadIdx.x] = (uint32_t)L[g0 + threadIdx.x];
+    if (threadIdx.x < nr) {
+        sidx[threadIdx.x] = (uint32_t)L[g0 + threadIdx.x];
+        if (sidx[threadIdx.x] >= n) atomicOr(err, 2u);
+    }
     __syncthreads();
     const uint32_t *src = reinterpret_cast<const uint32_t *>(stage);
     uint32_t *dst = reinterpret_cast<uint32_t *>(out) + g0 * 25;
@@ -312,59 +330,56 @@ struct Pipe {
 
 size_t a256(size_t v) { return (v + 255) / 256 * 256; }
 
-// Host copy split over threads (pageable destination of the merge output).
-void par_copy(uint8_t *dst, const uint8_t *src, size_t bytes) {
-    const unsigned nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
-    if (bytes < (8u << 20) || nt == 1) { std::memcpy(dst, src, bytes); return; }
-    std::vector<std::thread> th;
-    const size_t per = (bytes + nt - 1) / nt;
-    for (unsigned t = 0; t < nt; t++) {
-        const size_t a = t * per, b = std::min(bytes, a + per);
-        if (a < b) th.emplace_back([=] { std::memcpy(dst + a, src + a, b - a); });
-    }
-    for (auto &x : th) x.join();
-}
-
-// Device -> pageable host through two pinned bounce buffers: the copy engine
-// fills one while host threads empty the other.
+// Device -> pageable host through pinned bounce buffers: the copy engine
+// fills them in turn while the host team empties the oldest one.
 struct Bounce {
-    static constexpr size_t kPiece = 256u << 20;
-    uint8_t *buf[2] = {nullptr, nullptr};
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    static constexpr int kBufs = 4;
+    static constexpr size_t kPiece = 128u << 20;
+    uint8_t *buf[kBufs] = {};
+    hipEvent_t ev[kBufs] = {};
+    CopyTeam team;
     int init() {
-        for (int i = 0; i < 2; i++) {
+        for (int i = 0; i < kBufs; i++) {
             hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&buf[i]), kPiece, hipHostMallocDefault);
             if (e != hipSuccess) { (void)hipGetLastError(); buf[i] = nullptr; return fail(LEYENDA_ENOMEM, "bounce buffer"); }
             if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
         }
         return LEYENDA_OK;
     }
+    // Copies `bytes` of device memory at src_dev to dst once `ready` has
+    // fired on the device; returns when dst is complete.
     int drain(const uint8_t *src_dev, uint8_t *dst, uint64_t bytes, hipEvent_t ready, hipStream_t s) {
         hipError_t e = hipStreamWaitEvent(s, ready, 0);
         if (e != hipSuccess) return hip_fail(e, "bounce wait");
-        uint8_t *pend_dst[2] = {nullptr, nullptr};
-        size_t pend_len[2] = {0, 0};
-        uint64_t off = 0;
-        for (int p = 0; off < bytes || pend_len[0] || pend_len[1]; p ^= 1) {
+        uint8_t *pend_dst[kBufs] = {};
+        size_t pend_len[kBufs] = {};
+        uint64_t issued = 0;
+        // keep every buffer's download in flight; empty them oldest first
+        for (uint64_t piece = 0;; piece++) {
+            const int p = (int)(piece % kBufs);
             if (pend_len[p]) {
                 if ((e = hipEventSynchronize(ev[p])) != hipSuccess) return hip_fail(e, "bounce copy");
-                par_copy(pend_dst[p], buf[p], pend_len[p]);
+                team.copy(pend_dst[p], buf[p], pend_len[p]);
                 pend_len[p] = 0;
             }
-            if (off < bytes) {
-                const size_t len = (size_t)std::min<uint64_t>(kPiece, bytes - off);
-                e = hipMemcpyAsync(buf[p], src_dev + off, len, hipMemcpyDeviceToHost, s);
+            if (issued < bytes) {
+                const size_t len = (size_t)std::min<uint64_t>(kPiece, bytes - issued);
+                e = hipMemcpyAsync(buf[p], src_dev + issued, len, hipMemcpyDeviceToHost, s);
                 if (e == hipSuccess) e = hipEventRecord(ev[p], s);
                 if (e != hipSuccess) return hip_fail(e, "bounce copy");
-                pend_dst[p] = dst + off;
+                pend_dst[p] = dst + issued;
                 pend_len[p] = len;
-                off += len;
+                issued += len;
+            } else {
+                bool any = false;
+                for (int q = 0; q < kBufs; q++) any = any || pend_len[q];
+                if (!any) break;
             }
         }
         return LEYENDA_OK;
     }
     ~Bounce() {
-        for (int i = 0; i < 2; i++) {
+        for (int i = 0; i < kBufs; i++) {
             if (ev[i]) { (void)hipEventSynchronize(ev[i]); (void)hipEventDestroy(ev[i]); }
             if (buf[i]) (void)hipHostFree(buf[i]);
         }
@@ -442,14 +457,16 @@ extern "C" int leyenda_sort_runs(const void *host_records, uint64_t n, uint64_t 
     if ((rc = P.init(static_cast<hipStream_t>(stream)))) return rc;
     const size_t rb = a256(R * kRec);
     const size_t ws_bytes = plan_layout(R, 1, t).total;
-    if ((rc = P.alloc(4 * rb + ws_bytes))) return rc;
+    if ((rc = P.alloc(4 * rb + ws_bytes + 256))) return rc;
     char *base = static_cast<char *>(P.arena);
     uint8_t *in[2] = {reinterpret_cast<uint8_t *>(base), reinterpret_cast<uint8_t *>(base + rb)};
     uint8_t *out[2] = {reinterpret_cast<uint8_t *>(base + 2 * rb), reinterpret_cast<uint8_t *>(base + 3 * rb)};
     void *ws = base + 4 * rb;
+    uint32_t *guard = reinterpret_cast<uint32_t *>(base + 4 * rb + a256(ws_bytes));  // OR of the runs' guard words
     const uint8_t *src = static_cast<const uint8_t *>(host_records);
     uint8_t *dst = static_cast<uint8_t *>(host_runs);
-    hipError_t e = hipSuccess;
+    hipError_t e = hipMemsetAsync(guard, 0, 4, P.cs);
+    if (e != hipSuccess) return hip_fail(e, "leyenda_sort_runs: guard word");
     for (uint64_t r = 0; r < K; r++) {
         const int b = (int)(r & 1);
         const uint64_t off = r * R, len = std::min<uint64_t>(R, n - off);
@@ -463,7 +480,8 @@ extern "C" int leyenda_sort_runs(const void *host_records, uint64_t n, uint64_t 
         if (e == hipSuccess && r >= 2) e = hipStreamWaitEvent(P.cs, P.ev[2][b], 0);
         if (e != hipSuccess) return hip_fail(e, "leyenda_sort_runs: enqueue");
         if ((rc = sort_device_ws(in[b], len, out[b], P.cs, t, ws))) return rc;
-        e = hipEventRecord(P.ev[1][b], P.cs);
+        e = launch_guard_or(ws, len, t, guard, P.cs);
+        if (e == hipSuccess) e = hipEventRecord(P.ev[1][b], P.cs);
         // download the sorted run over its own input range
         if (e == hipSuccess) e = hipStreamWaitEvent(P.d2h, P.ev[1][b], 0);
         if (e == hipSuccess) e = hipMemcpyAsync(dst + off * kRec, out[b], len * kRec, hipMemcpyDeviceToHost, P.d2h);
@@ -472,6 +490,10 @@ extern "C" int leyenda_sort_runs(const void *host_records, uint64_t n, uint64_t 
     }
     run_bounds[K] = n;
     if ((rc = P.finish())) return rc;
+    uint32_t g = 0;
+    e = hipMemcpy(&g, guard, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "leyenda_sort_runs: guard word");
+    if (g) return fail(LEYENDA_EINTERNAL, "leyenda_sort_runs: a device-side guard fired in a run's sort (0x%x)", g);
     *k_out = K;
     return LEYENDA_OK;
 }
@@ -548,13 +570,13 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
     // 1. exact chunk boundaries (co-rank of ranks C, 2C, ...)
     std::vector<uint64_t> split((nch + 1) * k, 0);
     for (uint64_t i = 0; i < k; i++) split[nch * k + i] = run_bounds[i + 1] - run_bounds[i];
-    hipError_t e = hipSuccess;
+    hipError_t e = hipMemsetAsync(d_err, 0, 4, P.cs);  // error word of the co-rank and gather kernels
+    if (e != hipSuccess) return hip_fail(e, "leyenda_merge: error word");
     if (nch > 1) {
         std::vector<uint64_t> tgt(nch - 1);
         for (uint64_t c = 1; c < nch; c++) tgt[c - 1] = c * C;
         e = hipMemcpyAsync(d_off, run_bounds, (k + 1) * 8, hipMemcpyHostToDevice, P.cs);
         if (e == hipSuccess) e = hipMemcpyAsync(d_tgt, tgt.data(), (nch - 1) * 8, hipMemcpyHostToDevice, P.cs);
-        if (e == hipSuccess) e = hipMemsetAsync(d_err, 0, 4, P.cs);
         if (e != hipSuccess) return hip_fail(e, "leyenda_merge: tables");
         k_corank<<<dim3((uint32_t)(nch - 1)), dim3(kWG), 0, P.cs>>>(runs_dev, d_off, (uint32_t)k, d_tgt, d_split,
                                                                    d_err);
@@ -656,7 +678,7 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
                                                             TL[rd.in_buf ^ 1]);
         }
         k_gather_lo<<<dim3((uint32_t)((clen + kWG - 1) / kWG)), dim3(kWG), 0, P.cs>>>(stage[b], TL[final_buf[c]],
-                                                                                   outb[b], clen);
+                                                                                   outb[b], clen, d_err);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "merge kernels");
         e = hipEventRecord(P.ev[1][b], P.cs);
         if (e != hipSuccess) return hip_fail(e, "leyenda_merge: enqueue");
@@ -678,5 +700,121 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
     if (!direct_out && (rc = bounce.drain(outb[(nch - 1) & 1], out_h + prev_first * kRec, prev_len * kRec,
                                           P.ev[1][(nch - 1) & 1], P.d2h)))
         return rc;
-    return P.finish();
+    if ((rc = P.finish())) return rc;
+    uint32_t err = 0;
+    e = hipMemcpy(&err, d_err, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "leyenda_merge: error word");
+    if (err) return fail(LEYENDA_EINTERNAL, "leyenda_merge: a merged index fell outside its chunk (0x%x)", err);
+    return LEYENDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Keys-only external sort: every record's (key, index) tuple is extracted as
+// the input streams in, all tuples are sorted on the device at once, and the
+// records are then gathered in sorted order straight from the pinned input
+// (device loads of host memory) and streamed out.  Section 3.2 sorts
+// key-pointer tuples extracted while reading and then scatters the records by
+// them; here the tuples of the whole input fit the device budget, so there are
+// no runs to merge.
+
+extern "C" int leyenda_sort_external_keys(const void *host_records, uint64_t n, uint64_t device_budget_bytes,
+                                          void *host_out, void *stream) {
+    if (n == 0) return LEYENDA_OK;
+    if (n > LEYENDA_MAX_RECORDS)
+        return fail(LEYENDA_ETOOBIG, "leyenda_sort_external_keys: %llu records exceed the per-sort limit",
+                    (unsigned long long)n);
+    if (!host_records || !host_out) return fail(LEYENDA_EINVAL, "leyenda_sort_external_keys: NULL buffer");
+    if ((reinterpret_cast<uintptr_t>(host_records) | reinterpret_cast<uintptr_t>(host_out)) & 3u)
+        return fail(LEYENDA_EINVAL, "leyenda_sort_external_keys: buffers must be 4-byte aligned");
+    if (overlaps(host_records, n * kRec, host_out, n * kRec))
+        return fail(LEYENDA_EINVAL, "leyenda_sort_external_keys: host_out overlaps host_records");
+    const uint8_t *rec_dev = static_cast<const uint8_t *>(pinned_device_ptr(host_records));
+    if (!rec_dev)
+        return fail(LEYENDA_EINVAL, "leyenda_sort_external_keys: host_records must be pinned (hipHostMalloc / pin_memory)");
+    const bool direct_out = pinned_device_ptr(host_out) != nullptr;
+    const Tune t = tune_of(current_params());
+    const Layout L = plan_layout(n, 1, t);
+    const uint64_t need = L.total + 256;
+    if (need > device_budget_bytes)
+        return fail(LEYENDA_EBUDGET,
+                    "leyenda_sort_external_keys: the tuples and sort tables of %llu records need %llu device bytes, "
+                    "above the budget of %llu (runs + merge fit smaller budgets)",
+                    (unsigned long long)n, (unsigned long long)need, (unsigned long long)device_budget_bytes);
+    Pipe P;
+    int rc = P.init(static_cast<hipStream_t>(stream));
+    if (rc) return rc;
+    if ((rc = P.alloc(need))) return rc;
+    char *base = static_cast<char *>(P.arena);
+    uint64_t *H0 = reinterpret_cast<uint64_t *>(base + L.off_H0);
+    uint64_t *L0 = reinterpret_cast<uint64_t *>(base + L.off_L0);
+    const uint32_t *idx = reinterpret_cast<const uint32_t *>(base + L.off_idx);
+    uint32_t *guard = reinterpret_cast<uint32_t *>(base + L.total);
+    hipError_t e = hipMemsetAsync(guard, 0, 4, P.cs);
+    if (e != hipSuccess) return hip_fail(e, "leyenda_sort_external_keys: guard word");
+
+    // 1. read: the input streams through two staging areas that are the
+    //    second tuple buffers (H1, L1; the sort first writes them in its
+    //    first partition pass), each chunk's tuples extracted on arrival
+    uint8_t *stage_in[2] = {reinterpret_cast<uint8_t *>(base + L.off_H1), reinterpret_cast<uint8_t *>(base + L.off_L1)};
+    const uint64_t cap_in = std::min<uint64_t>(L.off_L0 - L.off_H1, L.off_idx - L.off_L1) / kRec;
+    const uint64_t C1 = std::max<uint64_t>(1, std::min<uint64_t>(cap_in, 16ull << 20));
+    const uint8_t *src = static_cast<const uint8_t *>(host_records);
+    for (uint64_t c0 = 0, c = 0; c0 < n; c0 += C1, c++) {
+        const int b = (int)(c & 1);
+        const uint64_t len = std::min<uint64_t>(C1, n - c0);
+        if (c >= 2) e = hipStreamWaitEvent(P.h2d, P.ev[1][b], 0);  // extraction of chunk c - 2 done
+        if (e == hipSuccess) e = hipMemcpyAsync(stage_in[b], src + c0 * kRec, len * kRec, hipMemcpyHostToDevice, P.h2d);
+        if (e == hipSuccess) e = hipEventRecord(P.ev[0][b], P.h2d);
+        if (e == hipSuccess) e = hipStreamWaitEvent(P.cs, P.ev[0][b], 0);
+        if (e != hipSuccess) return hip_fail(e, "leyenda_sort_external_keys: read");
+        k_extract_chunk<<<dim3((uint32_t)((len + kWG - 1) / kWG)), dim3(kWG), 0, P.cs>>>(stage_in[b], len, c0, H0, L0);
+        if ((e = hipGetLastError()) == hipSuccess) e = hipEventRecord(P.ev[1][b], P.cs);
+        if (e != hipSuccess) return hip_fail(e, "leyenda_sort_external_keys: extraction");
+    }
+
+    // 2. sort all tuples (Algorithm 1 on the device, one pass)
+    if ((rc = sort_tuples_ws(n, P.cs, t, base))) return rc;
+    if ((e = launch_guard_or(base, n, t, guard, P.cs)) != hipSuccess) return hip_fail(e, "guard kernel");
+
+    // 3. scatter: records gathered in sorted order from the pinned input into
+    //    two output staging areas (the tuple buffers, free after the sort:
+    //    H0 + H1 and L0 + L1), each downloaded while the next one fills
+    uint8_t *stage_out[2] = {reinterpret_cast<uint8_t *>(base + L.off_H0), reinterpret_cast<uint8_t *>(base + L.off_L0)};
+    const uint64_t cap_out = std::min<uint64_t>(L.off_L0 - L.off_H0, L.off_idx - L.off_L0) / kRec;
+    const uint64_t C3 = std::max<uint64_t>(1, std::min<uint64_t>(cap_out, 32ull << 20));
+    uint8_t *out_h = static_cast<uint8_t *>(host_out);
+    Bounce bounce;
+    if (!direct_out && (rc = bounce.init())) return rc;
+    uint64_t prev_first = 0, prev_len = 0;
+    uint64_t c = 0;
+    for (uint64_t c0 = 0; c0 < n; c0 += C3, c++) {
+        const int b = (int)(c & 1);
+        const uint64_t len = std::min<uint64_t>(C3, n - c0);
+        if (c >= 2 && direct_out) e = hipStreamWaitEvent(P.cs, P.ev[2][b], 0);  // download of chunk c - 2 done
+        if (e == hipSuccess) e = launch_gather_single(rec_dev, n, idx + c0, stage_out[b], len, P.cs);
+        if (e == hipSuccess) e = hipEventRecord(P.ev[1][b], P.cs);
+        if (e != hipSuccess) return hip_fail(e, "leyenda_sort_external_keys: gather");
+        if (direct_out) {
+            e = hipStreamWaitEvent(P.d2h, P.ev[1][b], 0);
+            if (e == hipSuccess) e = hipMemcpyAsync(out_h + c0 * kRec, stage_out[b], len * kRec, hipMemcpyDeviceToHost, P.d2h);
+            if (e == hipSuccess) e = hipEventRecord(P.ev[2][b], P.d2h);
+            if (e != hipSuccess) return hip_fail(e, "leyenda_sort_external_keys: write");
+        } else {
+            // chunk c - 1 drains while chunk c is gathered
+            if (c >= 1 && (rc = bounce.drain(stage_out[b ^ 1], out_h + prev_first * kRec, prev_len * kRec,
+                                             P.ev[1][b ^ 1], P.d2h)))
+                return rc;
+            prev_first = c0;
+            prev_len = len;
+        }
+    }
+    if (!direct_out && (rc = bounce.drain(stage_out[(c - 1) & 1], out_h + prev_first * kRec, prev_len * kRec,
+                                          P.ev[1][(c - 1) & 1], P.d2h)))
+        return rc;
+    if ((rc = P.finish())) return rc;
+    uint32_t g = 0;
+    e = hipMemcpy(&g, guard, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "leyenda_sort_external_keys: guard word");
+    if (g) return fail(LEYENDA_EINTERNAL, "leyenda_sort_external_keys: a device-side guard fired in the sort (0x%x)", g);
+    return LEYENDA_OK;
 }

@@ -193,16 +193,17 @@ __global__ __launch_bounds__(kTB) void k_tie_emit(const uint32_t *A, const uint8
     }
 }
 
-// out[t] = A[position held by sorted entry t], one dword per thread (a
+// out[t] = A[position held by sorted entry t], one dword per thread.  A
 // position outside the n records, which only a failed entry sort could leave,
-// is skipped rather than read).
+// is not read: it sets *err, and the call reports LEYENDA_EINTERNAL.
 __global__ __launch_bounds__(kTB) void k_tie_gather(const uint32_t *A, uint64_t n, const uint32_t *E2, uint64_t m,
-                                                    uint32_t *out) {
+                                                    uint32_t *out, uint32_t *err) {
     const uint64_t g = (uint64_t)blockIdx.x * kTB + threadIdx.x;
     if (g >= m * kRecWords) return;
     const uint64_t t = g / kRecWords, d = g - t * kRecWords;
     const uint64_t j = (uint64_t)E2[t * kRecWords + 3] | ((uint64_t)E2[t * kRecWords + 4] << 32);
     if (j < n) out[g] = A[j * kRecWords + d];
+    else atomicOr(err, 1u << 16);
 }
 
 // A[dest[t]] = R[t], one dword per thread.
@@ -214,36 +215,50 @@ __global__ __launch_bounds__(kTB) void k_tie_scatter(const uint32_t *R, const ui
     A[dest[t] * kRecWords + d] = R[g];
 }
 
-struct Scratch {
-    void *p[7] = {};
-    ~Scratch() {
-        for (void *q : p)
-            if (q) (void)hipFree(q);
-    }
+size_t a256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Scratch of the tie rounds, from the stream's pooled slot 0 (kept between
+// calls): the tie marks (n bytes), the per-block counts and offsets of the
+// run numbering, and the totals + error word.
+struct RoundTables {
+    uint8_t *P;
+    uint32_t *cnt_in, *cnt_start;
+    uint64_t *off_in, *off_start, *totals;
 };
 
-int alloc(void **p, size_t bytes) {
-    const hipError_t e = hipMalloc(p, bytes ? bytes : 1);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        *p = nullptr;
-        return fail(LEYENDA_ENOMEM, "leyenda_sort_keyed: hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-    }
-    return LEYENDA_OK;
+size_t tables_bytes(uint64_t n) {
+    const uint64_t nb = (n + kTSpan - 1) / kTSpan;
+    return a256(n) + 2 * a256(nb * 4) + 2 * a256(nb * 8) + 256;
 }
 
-// Rounds over the tie runs of the prefix-sorted records in A (n records); P
-// (n bytes) holds the first round's tie marks and is reused by later rounds.
-int resolve_ties(uint32_t *A, uint64_t n, uint32_t key_bytes, hipStream_t s, const Tune &t, uint8_t *P) {
-    const uint64_t nb_max = (n + kTSpan - 1) / kTSpan;
-    Scratch sc;  // freed after the stream drains (hipFree waits for the device)
+RoundTables bind_tables(void *base, uint64_t n) {
+    const uint64_t nb = (n + kTSpan - 1) / kTSpan;
+    char *b = static_cast<char *>(base);
+    RoundTables r;
+    r.P = reinterpret_cast<uint8_t *>(b); b += a256(n);
+    r.cnt_in = reinterpret_cast<uint32_t *>(b); b += a256(nb * 4);
+    r.cnt_start = reinterpret_cast<uint32_t *>(b); b += a256(nb * 4);
+    r.off_in = reinterpret_cast<uint64_t *>(b); b += a256(nb * 8);
+    r.off_start = reinterpret_cast<uint64_t *>(b); b += a256(nb * 8);
+    r.totals = reinterpret_cast<uint64_t *>(b);  // tie count, run count, error word
+    return r;
+}
+
+// Rounds over the tie runs of the prefix-sorted records in A (n records);
+// tb.P (n bytes) holds the first round's tie marks and is reused by later
+// rounds.  The entries live in the stream's pooled slot 1.
+int resolve_ties(uint32_t *A, uint64_t n, uint32_t key_bytes, hipStream_t s, const Tune &t, const RoundTables &tb) {
     int rc;
-    if ((rc = alloc(&sc.p[0], nb_max * 4)) || (rc = alloc(&sc.p[1], nb_max * 4)) ||
-        (rc = alloc(&sc.p[2], nb_max * 8)) || (rc = alloc(&sc.p[3], nb_max * 8)) || (rc = alloc(&sc.p[4], 16)))
-        return rc;
-    uint32_t *cnt_in = static_cast<uint32_t *>(sc.p[0]), *cnt_start = static_cast<uint32_t *>(sc.p[1]);
-    uint64_t *off_in = static_cast<uint64_t *>(sc.p[2]), *off_start = static_cast<uint64_t *>(sc.p[3]);
-    uint64_t *totals = static_cast<uint64_t *>(sc.p[4]);
+    uint8_t *P = tb.P;
+    uint32_t *cnt_in = tb.cnt_in, *cnt_start = tb.cnt_start;
+    uint64_t *off_in = tb.off_in, *off_start = tb.off_start;
+    uint64_t *totals = tb.totals;
+    // error word next to the totals: the sorts' device-side guard words
+    // (capacity guards, bounded waits) and the entry gather's bound check
+    uint32_t *err = reinterpret_cast<uint32_t *>(totals + 2);
+    hipError_t e0 = hipMemsetAsync(err, 0, 4, s);
+    if (e0 != hipSuccess) return hip_fail(e0, "leyenda_sort_keyed: error word");
+    if ((rc = guard_or_pooled(s, err))) return rc;  // the prefix sort
     uint32_t *E = nullptr, *E2 = nullptr;  // entries, then sorted entries (room for the first round's count)
     uint64_t *dest[2] = {nullptr, nullptr};  // positions of the entries, by round parity
     uint64_t cap = 0, nc = n;
@@ -253,33 +268,39 @@ int resolve_ties(uint32_t *A, uint64_t n, uint32_t key_bytes, hipStream_t s, con
         if (r) k_tie_eq<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(E2, nc, P);
         k_tie_count<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(P, nc, cnt_in, cnt_start);
         k_tie_scan<<<dim3(1), dim3(kSB), 0, s>>>(cnt_in, cnt_start, nb, off_in, off_start, totals);
-        uint64_t h[2] = {0, 0};
+        uint64_t h[3] = {0, 0, 0};  // tie count, run count, error word
         hipError_t e = hipMemcpyAsync(h, totals, sizeof(h), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: tie count");
+        if ((uint32_t)h[2]) return fail(LEYENDA_EINTERNAL, "leyenda_sort_keyed: device-side guard 0x%x", (uint32_t)h[2]);
         const uint64_t m = h[0];
         if (m == 0) break;
         if (m > nc || h[1] > m / 2) return fail(LEYENDA_EHIP, "leyenda_sort_keyed: inconsistent tie count");
-        if (!E) {
+        if (!E) {  // the first round has the most entries: later rounds reuse its room
             cap = m;
-            if ((rc = alloc(&sc.p[5], cap * kRec * 2)) || (rc = alloc(&sc.p[6], cap * 16))) return rc;
-            E = static_cast<uint32_t *>(sc.p[5]);
+            void *ent = nullptr;
+            if ((rc = get_aux(s, 1, cap * kRec * 2 + cap * 16, &ent))) return rc;
+            E = static_cast<uint32_t *>(ent);
             E2 = E + cap * kRecWords;
-            dest[0] = static_cast<uint64_t *>(sc.p[6]);
+            dest[0] = reinterpret_cast<uint64_t *>(E2 + cap * kRecWords);
             dest[1] = dest[0] + cap;
         }
         k_tie_emit<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(A, P, nc, r ? dest[(r - 1) & 1] : nullptr, p, key_bytes,
                                                              off_in, off_start, E, dest[r & 1]);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: entries");
         if ((rc = sort_device(E, m, E2, s, t))) return rc;
+        if ((rc = guard_or_pooled(s, err))) return rc;  // the entry sort
         const uint64_t blocks = (m * kRecWords + kTB - 1) / kTB;
-        k_tie_gather<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(A, n, E2, m, E);  // E is free again
+        k_tie_gather<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(A, n, E2, m, E, err);  // E is free again
         k_tie_scatter<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(E, dest[r & 1], m, A);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: permute");
         nc = m;  // the next round looks only inside these runs
     }
-    const hipError_t e = hipStreamSynchronize(s);
+    uint32_t eh = 0;
+    hipError_t e = hipMemcpyAsync(&eh, err, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "leyenda_sort_keyed");
+    if (eh) return fail(LEYENDA_EINTERNAL, "leyenda_sort_keyed: device-side guard 0x%x", eh);
     return LEYENDA_OK;
 }
 
@@ -299,9 +320,9 @@ extern "C" int leyenda_sort_keyed(const void *records_dev, uint64_t n, uint32_t 
     const Tune t = tune_of(current_params());
     if (key_bytes <= kKeyBytes || n < 2)
         return sort_device(records_dev, n, out_dev, s, t, key_bytes < kKeyBytes ? key_bytes : kKeyBytes);
-    Scratch sc;  // the prefix sort's tie marks (one byte per output record)
-    if ((rc = alloc(&sc.p[0], n))) return rc;
-    uint8_t *P = static_cast<uint8_t *>(sc.p[0]);
-    if ((rc = sort_device(records_dev, n, out_dev, s, t, kKeyBytes, P))) return rc;
-    return resolve_ties(static_cast<uint32_t *>(out_dev), n, key_bytes, s, t, P);
+    void *tab = nullptr;  // tie marks of the prefix sort's gather, then the rounds' tables
+    if ((rc = get_aux(s, 0, tables_bytes(n), &tab))) return rc;
+    const RoundTables tb = bind_tables(tab, n);
+    if ((rc = sort_device(records_dev, n, out_dev, s, t, kKeyBytes, tb.P))) return rc;
+    return resolve_ties(static_cast<uint32_t *>(out_dev), n, key_bytes, s, t, tb);
 }

@@ -49,6 +49,7 @@ leyenda_params current_params() {
 
 Tune tune_of(const leyenda_params &p) {
     Tune t;
+    t.digit = p.digit_bits;
     t.tile_items = p.tile_items;
     t.tile = kWG * p.tile_items;
     t.big = p.big_threshold;
@@ -59,8 +60,8 @@ Tune tune_of(const leyenda_params &p) {
 }
 
 static bool params_ok(const leyenda_params &p) {
-    return p.digit_bits == 8 && (p.tile_items == 8 || p.tile_items == 16 || p.tile_items == 32) &&
-           p.local_capacity == kLocalCap &&
+    return p.digit_bits >= (uint32_t)kMinRB && p.digit_bits <= (uint32_t)kRB &&
+           (p.tile_items == 8 || p.tile_items == 16 || p.tile_items == 32) && p.local_capacity == kLocalCap &&
            p.big_threshold >= 1 && p.big_threshold <= p.local_capacity && p.tiny_threshold >= 1 &&
            p.tiny_threshold <= 256 && (p.scatter_threads == 256 || p.scatter_threads == 512 || p.scatter_threads == 1024) &&
            (p.local_threads == 256 || p.local_threads == 512);
@@ -91,7 +92,7 @@ Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t) {
     L.n = n;
     const uint64_t segs = std::max<uint64_t>(reqs, n / ((uint64_t)t.big + 1)) + 1;
     const uint64_t tiles = (n + t.tile - 1) / t.tile + segs + reqs;
-    const uint64_t tasks = 3 * (n / kLocalCap) + 4ull * (kMaxLev + 1) * segs + reqs + 64;
+    const uint64_t tasks = 3 * (n / kLocalCap) + 4ull * (levels_for((int)t.digit) + 1) * segs + reqs + 64;
     L.max_seg = (uint32_t)std::min<uint64_t>(segs, 0xFFFFFFFFull);
     L.max_tiles = (uint32_t)std::min<uint64_t>(tiles, 0xFFFFFFFFull);
     L.max_tasks = (uint32_t)std::min<uint64_t>(tasks, 0xFFFFFFFFull);
@@ -168,7 +169,17 @@ struct PoolEntry {
     size_t bytes = 0;
     Layout layout{};
     Side side;
+    void *aux[2] = {nullptr, nullptr};  // scratch of the keyed sort's tie rounds
+    size_t aux_bytes[2] = {0, 0};
 };
+
+static void aux_free(PoolEntry &pe) {
+    for (int k = 0; k < 2; k++) {
+        if (pe.aux[k]) (void)hipFree(pe.aux[k]);
+        pe.aux[k] = nullptr;
+        pe.aux_bytes[k] = 0;
+    }
+}
 
 static void side_destroy(Side &sd) {
     for (hipEvent_t &e : sd.ready)
@@ -205,6 +216,37 @@ int get_workspace(hipStream_t stream, size_t bytes, void **out) {
     }
     pe.ptr = p;
     pe.bytes = bytes;
+    *out = p;
+    return LEYENDA_OK;
+}
+
+int get_aux(hipStream_t stream, int which, size_t bytes, void **out) {
+    if (which < 0 || which > 1) return fail(LEYENDA_EINVAL, "get_aux: slot %d", which);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    PoolEntry &pe = g_pool[{dev, stream}];
+    if (pe.aux[which] && pe.aux_bytes[which] >= bytes) { *out = pe.aux[which]; return LEYENDA_OK; }
+    if (pe.aux[which]) {
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        e = hipFree(pe.aux[which]);
+        pe.aux[which] = nullptr;
+        pe.aux_bytes[which] = 0;
+        if (e != hipSuccess) return hip_fail(e, "hipFree");
+    }
+    // grow by a quarter beyond the request, so slowly growing calls do not
+    // reallocate every time
+    const size_t want = bytes + bytes / 4 + 256;
+    void *p = nullptr;
+    e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LEYENDA_ENOMEM, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+    }
+    pe.aux[which] = p;
+    pe.aux_bytes[which] = want;
     *out = p;
     return LEYENDA_OK;
 }
@@ -258,17 +300,27 @@ void pool_forget(hipStream_t stream) {
     (void)hipStreamSynchronize(stream);
     if (it->second.side.s) (void)hipStreamSynchronize(it->second.side.s);
     if (it->second.ptr) (void)hipFree(it->second.ptr);
+    aux_free(it->second);
     side_destroy(it->second.side);
     g_pool.erase(it);
 }
 
 int release_all() {
+    // nothing held: leave the HIP runtime alone (this also runs at interpreter
+    // exit, where the process may never have used a GPU)
+    bool any = batch_holds_any();
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        any = any || !g_pool.empty();
+    }
+    if (!any) return LEYENDA_OK;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     batch_release_all();
     std::lock_guard<std::mutex> lk(g_pool_mu);
     for (auto &kv : g_pool) {
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+        aux_free(kv.second);
         side_destroy(kv.second.side);
     }
     g_pool.clear();
@@ -393,14 +445,53 @@ int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t 
     return sort_device_ws(records_dev, n, out_dev, stream, t, ws, key_bytes, ties);
 }
 
-int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t, void *ws,
-                   uint32_t key_bytes, uint8_t *ties) {
-    const Layout L = plan_layout(n, 1, t);
-    Work w = bind_layout(L, ws);
+void apply_key_mask(Work &w, uint32_t key_bytes) {
     if (key_bytes < kKeyBytes) {  // bytes key_bytes..9 of the prefix do not take part
         w.kmask_h = key_bytes >= 8 ? ~0ull : ~0ull << (64 - 8 * key_bytes);
         w.kmask_l = key_bytes == 9 ? 0xFF00u : 0u;
     }
+}
+
+// Device-side guards: a capacity guard or a bounded wait that gave up leaves
+// a bit in the sort's control block instead of touching memory out of bounds.
+__global__ void k_guard_or(const Ctl *ctl, uint32_t *acc) {
+    const uint32_t g = ctl->guard;
+    if (g) atomicOr(acc, g);
+}
+
+hipError_t launch_guard_or(const void *ws, uint64_t n, const Tune &t, uint32_t *acc, hipStream_t s) {
+    const Layout L = plan_layout(n, 1, t);
+    k_guard_or<<<1, 1, 0, s>>>(reinterpret_cast<const Ctl *>(static_cast<const char *>(ws) + L.off_ctl), acc);
+    return hipGetLastError();
+}
+
+int guard_or_pooled(hipStream_t stream, uint32_t *acc) {
+    void *ws = nullptr;
+    Layout L{};
+    if (find_workspace(stream, &ws, &L) != LEYENDA_OK) return LEYENDA_OK;  // no sort ran on this stream
+    k_guard_or<<<1, 1, 0, stream>>>(reinterpret_cast<const Ctl *>(static_cast<const char *>(ws) + L.off_ctl), acc);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? LEYENDA_OK : hip_fail(e, "guard kernel");
+}
+
+int sort_tuples_ws(uint64_t n, hipStream_t s, const Tune &t, void *ws) {
+    if (n == 0) return LEYENDA_OK;
+    const Layout L = plan_layout(n, 1, t);
+    const Work w = bind_layout(L, ws);
+    const uint32_t tiles0 = (uint32_t)((n + t.tile - 1) / t.tile);
+    k_setup_single<<<1, 1, 0, s>>>(w.reqs, w.hdr, nullptr, nullptr, n, tiles0);
+    Stage st;
+    st.tuples_in = true;
+    if (n <= t.big) st.lev_end = 1;  // one bucket, one local-sort task
+    const hipError_t e = launch_sort_core(w, t, 1, tiles0, s, device_cus(), nullptr, st);
+    return e == hipSuccess ? LEYENDA_OK : hip_fail(e, "tuple sort kernels");
+}
+
+int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t, void *ws,
+                   uint32_t key_bytes, uint8_t *ties) {
+    const Layout L = plan_layout(n, 1, t);
+    Work w = bind_layout(L, ws);
+    apply_key_mask(w, key_bytes);
     const uint32_t tiles0 = (uint32_t)((n + t.tile - 1) / t.tile);
     const uint32_t K = parts_for(n);
     Side *sd = nullptr;  // K output parts: the gathers run on the side stream
@@ -540,7 +631,7 @@ extern "C" int leyenda_sort_stats(void *stream, leyenda_stats *out) {
     e = hipMemcpy(&c, static_cast<char *>(ws) + L.off_ctl, sizeof(Ctl), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
     memset(out, 0, sizeof(*out));
-    for (int l = 0; l < kMaxLev && l < 12; l++) {
+    for (int l = 0; l < kMaxLev && l < LEYENDA_MAX_LEVELS; l++) {
         out->segments[l] = c.nseg[l];
         out->moved[l] = c.moved[l];
         if (c.moved[l]) out->levels = l + 1;
@@ -588,15 +679,47 @@ extern "C" int leyenda_profile_read(double *phase_ms, uint64_t *calls) {
     return LEYENDA_OK;
 }
 
-extern "C" int leyenda_debug_extract(const void *records_dev, uint64_t n, uint64_t *hi_dev, uint64_t *lo_dev,
-                                     uint32_t *hist_dev, void *stream) {
+// Sum of a bucket's histogram replicas (one thread per digit).
+__global__ void k_rep_sum(const uint32_t *rep, uint32_t nrep, uint32_t *hist) {
+    const uint32_t d = threadIdx.x;
+    uint32_t v = 0;
+    for (uint32_t r = 0; r < nrep; r++) v += rep[(size_t)r * kRepWords + d];
+    hist[d] = v;
+}
+
+extern "C" int leyenda_debug_extract(const void *records_dev, uint64_t n, uint32_t key_bytes, uint64_t *hi_dev,
+                                     uint64_t *lo_dev, uint32_t *hist_dev, void *stream) {
     if (n == 0) return LEYENDA_OK;
     if (n > LEYENDA_MAX_RECORDS) return fail(LEYENDA_ETOOBIG, "leyenda_debug_extract: too many records");
+    if (key_bytes < 1 || key_bytes > kKeyBytes)
+        return fail(LEYENDA_EINVAL, "leyenda_debug_extract: key_bytes %u outside 1..10", key_bytes);
     if (!records_dev || !hi_dev || !lo_dev || !hist_dev) return fail(LEYENDA_EINVAL, "leyenda_debug_extract: NULL");
+    if ((reinterpret_cast<uintptr_t>(records_dev) & 3u) || (reinterpret_cast<uintptr_t>(hi_dev) & 7u) ||
+        (reinterpret_cast<uintptr_t>(lo_dev) & 7u) || (reinterpret_cast<uintptr_t>(hist_dev) & 3u))
+        return fail(LEYENDA_EINVAL, "leyenda_debug_extract: misaligned buffer");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemsetAsync(hist_dev, 0, kRadix * 4, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
-    e = launch_debug_extract(static_cast<const uint8_t *>(records_dev), n, hi_dev, lo_dev, hist_dev, s);
+    // the sort's own first stage: request table, level-0 bucket, then the
+    // extraction kernel the sort launches (same masks, tiles and replicas)
+    const Tune t = tune_of(current_params());
+    const Layout L = plan_layout(n, 1, t);
+    void *ws = nullptr;
+    int rc = get_workspace(s, L.total, &ws);
+    if (rc) return rc;
+    remember_layout(s, L);
+    Work w = bind_layout(L, ws);
+    apply_key_mask(w, key_bytes);
+    const uint32_t tiles0 = (uint32_t)((n + t.tile - 1) / t.tile);
+    k_setup_single<<<1, 1, 0, s>>>(w.reqs, w.hdr, static_cast<const uint8_t *>(records_dev), nullptr, n, tiles0);
+    Stage st;
+    st.lev_end = 0;  // extraction only
+    st.tail = false;
+    hipError_t e = launch_sort_core(w, t, 1, tiles0, s, device_cus(), nullptr, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hi_dev, w.H[0], n * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(lo_dev, w.L[0], n * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) {
+        k_rep_sum<<<1, kRadix, 0, s>>>(w.rep[0], tiles0 < (uint32_t)kMaxRep ? tiles0 : (uint32_t)kMaxRep, hist_dev);
+        e = hipGetLastError();
+    }
     return e == hipSuccess ? LEYENDA_OK : hip_fail(e, "extract kernel");
 }
 

@@ -36,15 +36,15 @@ namespace ley {
 // ---------------------------------------------------------------------------
 // small helpers
 
-// Bits [pos, pos + kRB) of the 80-bit key (most significant bit first); bits
-// past the key read as zero.  pos < 80.
-__device__ __forceinline__ uint32_t digit_at(uint64_t h, uint64_t l, uint32_t pos) {
+// Bits [pos, pos + bits) of the 80-bit key (most significant bit first); bits
+// past the key read as zero.  pos < 80, kMinRB <= bits <= kRB.
+__device__ __forceinline__ uint32_t digit_at(uint64_t h, uint64_t l, uint32_t pos, uint32_t bits) {
     const uint64_t k2 = (l >> 32) << 48;
     uint64_t w;
     if (pos == 0) w = h;
     else if (pos < 64) w = (h << pos) | (k2 >> (64 - pos));
     else w = k2 << (pos - 64);
-    return (uint32_t)(w >> (64 - kRB));
+    return (uint32_t)(w >> (64 - bits));
 }
 
 __device__ __forceinline__ unsigned long long ld_agent(const unsigned long long *p) {
@@ -335,7 +335,7 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
             sp->spos = kNoScatter;
             const uint32_t f = first_varying(p_mask[0], p_mask[1], p_mask[2], p_mask[3]);
             if (f >= kKeyBits) emit_sorted(w, sg.start, sg.count, sg.buf, sg.req);
-            else new_segment(w, tu, lev + 1, sg.start, sg.count, max(f, (uint32_t)sg.pos + kRB), sg.buf, sg.req);
+            else new_segment(w, tu, lev + 1, sg.start, sg.count, max(f, (uint32_t)sg.pos + tu.digit), sg.buf, sg.req);
         }
         return;
     }
@@ -349,7 +349,7 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
         atomicAdd(&w.ctl->moved[lev], (unsigned long long)sg.count);
     }
     const uint8_t cbuf = sg.buf ^ 1;
-    const uint32_t cpos = p + kRB;
+    const uint32_t cpos = p + tu.digit;
     if (cnt > tu.big && cpos >= kKeyBits) emit_sorted(w, sg.start + base, cnt, cbuf, sg.req);  // equal keys
     new_segments_block(w, tu, lev + 1, cnt > tu.big && cpos < kKeyBits, sg.start + base, cnt, cpos, cbuf, sg.req);
     __syncthreads();
@@ -553,15 +553,16 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
 #pragma unroll
             for (int u = 0; u < RI; u++) {
                 const uint32_t q = (r0 + u) * kWG + threadIdx.x;
-                a[u] = b[u] = c[u] = 0;
-                if (q < nvalid) {
-                    // the caller's records are device memory: global (not flat)
-                    // loads, marked non-temporal (each line is read once here)
-                    const gu32 *p = (const gu32 *)(rq.in + (local0 + q) * kRec);
-                    a[u] = __builtin_nontemporal_load(p);
-                    b[u] = __builtin_nontemporal_load(p + 1);
-                    c[u] = __builtin_nontemporal_load(p + 2);
-                }
+                // lanes past the tile's last record load that record again: no
+                // branch around the loads, so all RI of them are in flight
+                // together (a load inside a branch is waited for at its end)
+                const uint32_t qc = q < nvalid ? q : nvalid - 1;
+                // the caller's records are device memory: global (not flat)
+                // loads, marked non-temporal (each line is read once here)
+                const gu32 *p = (const gu32 *)(rq.in + (local0 + qc) * kRec);
+                a[u] = __builtin_nontemporal_load(p);
+                b[u] = __builtin_nontemporal_load(p + 1);
+                c[u] = __builtin_nontemporal_load(p + 2);
             }
 #pragma unroll
             for (int u = 0; u < RI; u++) {
@@ -575,7 +576,7 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
                     __builtin_nontemporal_store((k16 << 32) | (uint32_t)(local0 + q), L + q);
                     oh |= h; onh |= ~h; ol |= k16; onl |= (~k16) & 0xFFFFu;
                 }
-                hist_add(sh, (uint32_t)(h >> 56), valid);
+                hist_add(sh, (uint32_t)(h >> (64 - tu.digit)), valid);
             }
         }
         block_masks(oh, onh, ol, onl, smask);
@@ -616,7 +617,7 @@ __global__ __launch_bounds__(kWG) void k_hist(Work w, Tune tu, int lev) {
         // key bytes 8..9 are read only when the digit reaches them; otherwise
         // their mask reads "varying", so a bucket constant through byte 7
         // moves on to bit 64 and the next level reads them
-        const bool needL = sg.pos + kRB > 64;
+        const bool needL = sg.pos + tu.digit > 64;
         __syncthreads();
         uint64_t oh = 0, onh = 0, ol = needL ? 0 : 0xFFFFu, onl = needL ? 0 : 0xFFFFu;
 #pragma unroll 1
@@ -635,7 +636,7 @@ __global__ __launch_bounds__(kWG) void k_hist(Work w, Tune tu, int lev) {
 #pragma unroll
             for (int u = 0; u < RI; u++) {
                 const uint32_t q = (r0 + u) * kWG + threadIdx.x;
-                hist_add(sh, digit_at(h[u], l[u], sg.pos), q < nvalid);
+                hist_add(sh, digit_at(h[u], l[u], sg.pos, tu.digit), q < nvalid);
                 if (q < nvalid) {
                     oh |= h[u]; onh |= ~h[u];
                     if (needL) {
@@ -838,7 +839,7 @@ __global__ __launch_bounds__(WG, (scatter_waves<ITEMS, WG>())) void k_scatter(Wo
             for (int u = c0; u < c0 + RCH; u++) {
                 const uint32_t q = wv * (ITEMS * 64) + u * 64 + lane;
                 const bool valid = q < nvalid;
-                rank_issue(valid ? digit_at(h[u], l[u], sg.spos) : 0u, valid, cnt[wv], old[u - c0], pk[u]);
+                rank_issue(valid ? digit_at(h[u], l[u], sg.spos, tu.digit) : 0u, valid, cnt[wv], old[u - c0], pk[u]);
             }
 #pragma unroll
             for (int u = c0; u < c0 + RCH; u++) pk[u] = (pk[u] & 0xFFu) | (rank_finish(old[u - c0], pk[u]) << 8);
@@ -877,7 +878,7 @@ __global__ __launch_bounds__(WG, (scatter_waves<ITEMS, WG>())) void k_scatter(Wo
             const uint32_t q = u * WG + tid;
             if (q < nvalid) {
                 const uint64_t hh = sH[q], ll = sL[q];
-                const uint64_t dst = gbase[digit_at(hh, ll, sg.spos)] + q;
+                const uint64_t dst = gbase[digit_at(hh, ll, sg.spos, tu.digit)] + q;
                 if (dst >= sg.start && dst < seg_end) {
                     Hd[dst] = hh;
                     Ld[dst] = ll;
@@ -1349,25 +1350,6 @@ __global__ __launch_bounds__(kWG) void k_gather_ties(const uint8_t *rec, uint64_
     gather_body<true>(rec, n_rec, idx, out, n, ties, has_prev);
 }
 
-// Extraction alone (tuples + byte-0 histogram) for the step-level test entry point.
-__global__ __launch_bounds__(kWG) void k_extract_plain(const uint8_t *rec, uint64_t n, uint64_t *H, uint64_t *L,
-                                                       uint32_t *hist) {
-    __shared__ uint32_t sh[kRadix];
-    sh[threadIdx.x] = 0;
-    __syncthreads();
-    const uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x;
-    if (i < n) {
-        const uint32_t *p = reinterpret_cast<const uint32_t *>(rec + i * kRec);
-        const uint64_t h = __builtin_bswap64(((uint64_t)p[1] << 32) | p[0]);
-        const uint64_t k16 = __builtin_bswap16((uint16_t)(p[2] & 0xFFFFu));
-        H[i] = h;
-        L[i] = (k16 << 32) | (uint32_t)i;
-        atomicAdd(&sh[h >> 56], 1u);
-    }
-    __syncthreads();
-    if (sh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], sh[threadIdx.x]);
-}
-
 // ---------------------------------------------------------------------------
 // launch wrappers
 
@@ -1387,13 +1369,6 @@ __global__ void k_flag(Work w, int gate, uint32_t *flag) {
 template <int ITEMS, int SWG, int LWG>
 static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
                                 hipStream_t s, int cus, hipEvent_t *ev, const Stage &st) {
-    if (st.head) {
-        // nreq / tiles0 == 0: sizes known only on the device (captured sequences)
-        k_init<<<dim3(nreq ? max(1u, min(nreq, 1024u)) : 1024u), dim3(kWG), 0, s>>>(w);
-        const int g_ext = tiles0 ? (int)max(1u, min(tiles0, (uint32_t)(cus * 16))) : cus * 16;
-        k_extract<ITEMS><<<dim3(g_ext), dim3(kWG), 0, s>>>(w, t);
-    }
-    if (ev) (void)hipEventRecord(ev[0], s);
     constexpr int SITEMS = ITEMS * kWG / SWG;  // same tile, SWG threads
     static int g_sc = 0, g_hist = 0, g_loc = 0;
     if (!g_sc) {
@@ -1401,8 +1376,20 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
         g_hist = occupancy(reinterpret_cast<const void *>(&k_hist<ITEMS>), cus);
         g_loc = occupancy(reinterpret_cast<const void *>(&k_local<LWG, LWG == 512 ? 2 : 3>), cus, LWG);
     }
+    if (st.head) {
+        // nreq / tiles0 == 0: sizes known only on the device (captured sequences)
+        k_init<<<dim3(nreq ? max(1u, min(nreq, 1024u)) : 1024u), dim3(kWG), 0, s>>>(w);
+        if (st.tuples_in) {  // tuples already in buffer 0: level 0 starts with its histogram pass
+            k_hist<ITEMS><<<dim3(g_hist), dim3(kWG), 0, s>>>(w, t, 0);
+        } else {
+            const int g_ext = tiles0 ? (int)max(1u, min(tiles0, (uint32_t)(cus * 16))) : cus * 16;
+            k_extract<ITEMS><<<dim3(g_ext), dim3(kWG), 0, s>>>(w, t);
+        }
+    }
+    if (ev) (void)hipEventRecord(ev[0], s);
     const int g_plan = cus * 4;
-    for (int lev = st.lev_begin; lev < st.lev_end; lev++) {
+    const int lev_end = min(st.lev_end, levels_for((int)t.digit));
+    for (int lev = st.lev_begin; lev < lev_end; lev++) {
         if (lev > 0) k_hist<ITEMS><<<dim3(g_hist), dim3(kWG), 0, s>>>(w, t, lev);
         k_plan<<<dim3(g_plan), dim3(kWG), 0, s>>>(w, t, lev);
         k_scatter<SITEMS, SWG><<<dim3(g_sc), dim3(SWG), 0, s>>>(w, t, lev);
@@ -1470,14 +1457,6 @@ hipError_t launch_gather_single(const uint8_t *rec, uint64_t n_rec, const uint32
         k_gather_ties<<<dim3((uint32_t)blocks), dim3(kWG), 0, s>>>(rec, n_rec, idx, out, n, ties, has_prev ? 1 : 0);
     else
         k_gather_plain<<<dim3((uint32_t)blocks), dim3(kWG), 0, s>>>(rec, n_rec, idx, out, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_debug_extract(const uint8_t *rec, uint64_t n, uint64_t *hi, uint64_t *lo, uint32_t *hist,
-                                hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    const uint64_t blocks = (n + kWG - 1) / kWG;
-    k_extract_plain<<<dim3((uint32_t)blocks), dim3(kWG), 0, s>>>(rec, n, hi, lo, hist);
     return hipGetLastError();
 }
 

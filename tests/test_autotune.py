@@ -43,7 +43,7 @@ def test_small_sweep_on_gpu(gpu, tmp_path):
     import datagen
     import oracle
     out = tmp_path / "params.json"
-    space = {"digit_bits": [8], "tile_items": [8, 16], "big_threshold": [256, 2048], "tiny_threshold": [4, 32],
+    space = {"digit_bits": [5, 8], "tile_items": [8, 16], "big_threshold": [256, 2048], "tiny_threshold": [4, 32],
              "local_threads": [256, 512]}
     old = gpu.get_params()
     try:

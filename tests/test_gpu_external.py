@@ -109,3 +109,48 @@ def test_external_errors(gpu):
         gpu.sort_runs(pinned(rec), budget_for_runs(gpu, 1000, 9), k_max=3)
     assert ei.value.status == -3
     assert lib is not None
+
+
+# ---- keys-only variant: all tuples sorted on the device, records gathered from the pinned input ----
+
+@pytest.mark.parametrize("kind,pinned_out", [("uniform", True), ("uniform", False), ("ties", True),
+                                             ("ties", False), ("few", True)])
+def test_keys_only_matches_oracle(gpu, kind, pinned_out):
+    """The input streams in about twelve chunks and the output leaves in about
+    seven, so equal keys straddle chunk boundaries on both sides."""
+    import torch
+    n = 250_007
+    if kind == "uniform":
+        rec = datagen.uniform(n, 81)
+    elif kind == "ties":
+        rec = datagen.skewed(n, 82, nvals=40, dup_frac=0.3)
+    else:  # eight distinct keys: every bucket is far above the local capacity
+        rec = datagen.uniform(n, 83)
+        rec[:, :10] = datagen.uniform(8, 84)[np.arange(n) % 8, :10]
+    host = pinned(rec)
+    out = torch.empty(n * 100, dtype=torch.uint8, pin_memory=pinned_out)
+    gpu.sort_external_keys(host, gpu.workspace_bytes(n) + 256, host_out=out)
+    np.testing.assert_array_equal(out.numpy().reshape(n, 100), oracle.sort(rec))
+    np.testing.assert_array_equal(host.numpy().reshape(n, 100), rec)  # the input is left as it was
+
+
+def test_keys_only_tiny(gpu):
+    for n in (1, 2, 3, 12, 13, 101, 2049):
+        rec = datagen.skewed(n, 85, nvals=4, dup_frac=0.5) if n > 3 else datagen.uniform(n, 85)
+        out = gpu.sort_external_keys(pinned(rec), 64 << 20)
+        np.testing.assert_array_equal(out.numpy().reshape(n, 100), oracle.sort(rec))
+
+
+def test_keys_only_budget_and_errors(gpu):
+    import torch
+    n = 5_000
+    rec = datagen.uniform(n, 86)
+    need = gpu.workspace_bytes(n) + 256
+    with pytest.raises(gpu.LeyendaError) as ei:
+        gpu.sort_external_keys(pinned(rec), need - 1)
+    assert ei.value.status == -3
+    out = gpu.sort_external_keys(pinned(rec), need)
+    np.testing.assert_array_equal(out.numpy().reshape(n, 100), oracle.sort(rec))
+    with pytest.raises(gpu.LeyendaError) as ei:  # pageable input: the gather reads it from the device
+        gpu.sort_external_keys(torch.from_numpy(rec.reshape(-1).copy()), need)
+    assert ei.value.status == -1

@@ -28,19 +28,43 @@ def assert_same(got: np.ndarray, want: np.ndarray, what: str = ""):
 
 # ---- step-level parity ------------------------------------------------------------
 
-def test_extract_step(gpu):
-    import torch
-    rec = datagen.uniform(10007, 31)
-    hi, lo, hist = gpu.debug_extract(torch.from_numpy(rec).cuda())
-    torch.cuda.synchronize()
-    want_hi = np.zeros(rec.shape[0], dtype=np.uint64)
+def _want_tuples(rec: np.ndarray, key_bytes: int):
+    """Expected key-pointer tuple words written out from the definition: key
+    bytes 0..7 big-endian, key bytes 8..9 big-endian above the record index,
+    bytes at and past key_bytes cleared."""
+    key = rec[:, :10].astype(np.uint64).copy()
+    key[:, key_bytes:] = 0
+    hi = np.zeros(rec.shape[0], dtype=np.uint64)
     for b in range(8):
-        want_hi = (want_hi << np.uint64(8)) | rec[:, b].astype(np.uint64)
-    k16 = (rec[:, 8].astype(np.uint64) << np.uint64(8)) | rec[:, 9].astype(np.uint64)
-    want_lo = (k16 << np.uint64(32)) | np.arange(rec.shape[0], dtype=np.uint64)
+        hi = (hi << np.uint64(8)) | key[:, b]
+    k16 = (key[:, 8] << np.uint64(8)) | key[:, 9]
+    lo = (k16 << np.uint64(32)) | np.arange(rec.shape[0], dtype=np.uint64)
+    return hi, lo
+
+
+# 3 * 8192 + 77 records: three full extraction tiles of the default shape and
+# a ragged fourth; 2,048-key tiles (tile_items 8) make it thirteen
+@pytest.mark.parametrize("key_bytes,digit_bits,tile_items", [
+    (10, 8, 32), (9, 8, 32), (4, 8, 32), (10, 5, 32), (1, 4, 8), (10, 8, 8), (8, 7, 16)])
+def test_extract_step(gpu, key_bytes, digit_bits, tile_items):
+    """The sort's own extraction kernel (first stage of leyenda_sort): tuples
+    and the histogram of the leading digit, with the key masks of shorter keys."""
+    import torch
+    n = 3 * 8192 + 77
+    rec = datagen.uniform(n, 31)
+    rec[: n // 3, :3] = rec[0, :3]  # a third of the keys share a 3-byte prefix
+    old = gpu.get_params()
+    try:
+        gpu.set_params(digit_bits=digit_bits, tile_items=tile_items)
+        hi, lo, hist = gpu.debug_extract(torch.from_numpy(rec).cuda(), key_bytes)
+        torch.cuda.synchronize()
+    finally:
+        gpu.set_params(**old)
+    want_hi, want_lo = _want_tuples(rec, key_bytes)
     np.testing.assert_array_equal(hi.cpu().numpy().view(np.uint64), want_hi)
     np.testing.assert_array_equal(lo.cpu().numpy().view(np.uint64), want_lo)
-    np.testing.assert_array_equal(hist.cpu().numpy(), np.bincount(rec[:, 0], minlength=256))
+    lead = (want_hi >> np.uint64(64 - digit_bits)).astype(np.int64)
+    np.testing.assert_array_equal(hist.cpu().numpy(), np.bincount(lead, minlength=256))
 
 
 def test_extract_worked_example_histogram(gpu):
@@ -144,6 +168,9 @@ def test_sort_worked_example(gpu):
     dict(tile_items=16, scatter_threads=512), dict(tile_items=32, scatter_threads=512),
     dict(tile_items=16, scatter_threads=1024, big_threshold=100), dict(tiny_threshold=256),
     dict(tiny_threshold=160, big_threshold=300),
+    dict(digit_bits=4), dict(digit_bits=5), dict(digit_bits=6, big_threshold=64),
+    dict(digit_bits=7, tile_items=8), dict(digit_bits=4, big_threshold=1, tiny_threshold=5),
+    dict(digit_bits=6, tile_items=16, scatter_threads=512, local_threads=256),
 ])
 def test_params_do_not_change_output(gpu, params):
     rec = pattern("skewed_narrow", 150_000)
@@ -154,6 +181,28 @@ def test_params_do_not_change_output(gpu, params):
         assert_same(run_sort(gpu, rec), want, str(params))
     finally:
         gpu.set_params(**old)
+
+
+@pytest.mark.parametrize("digit_bits", [4, 5, 6, 7])
+@pytest.mark.parametrize("name", ["uniform", "bytes_7_8_only", "shared_prefix", "one_big_bucket", "ascii"])
+def test_digit_widths(gpu, digit_bits, name):
+    """Narrower partition digits (Algorithm 1 with 2^digit_bits buckets per
+    level): digits straddle the byte boundaries and the two tuple words, and
+    the level count grows to ceil(80 / digit_bits)."""
+    import torch
+    n = 1_000_003
+    rec = datagen.uniform(n, 95) if name == "uniform" else pattern(name, n)
+    want = oracle.sort(rec)
+    old = gpu.get_params()
+    try:
+        gpu.set_params(digit_bits=digit_bits)
+        assert_same(run_sort(gpu, rec), want, f"{name} digit_bits={digit_bits}")
+        st = gpu.stats(torch.cuda.current_stream())
+    finally:
+        gpu.set_params(**old)
+    assert st["guard"] == 0
+    if name == "uniform":
+        assert st["moved"][0] == n and st["levels"] >= 2
 
 
 def test_deterministic_repeats(gpu):

@@ -47,7 +47,8 @@ def test_status_strings_and_param_checks():
     assert p["digit_bits"] == 8 and p["local_capacity"] == 2048 and p["scatter_threads"] == 1024
     assert p["local_threads"] == 512 and p["tile_items"] == 32 and p["tiny_threshold"] == 128
     for bad in [dict(tile_items=3), dict(big_threshold=0), dict(big_threshold=4096), dict(tiny_threshold=0),
-                dict(tiny_threshold=257), dict(digit_bits=4), dict(scatter_threads=384),
+                dict(tiny_threshold=257), dict(digit_bits=3), dict(digit_bits=9), dict(digit_bits=16),
+                dict(scatter_threads=384),
                 dict(local_threads=128)]:
         with pytest.raises(ley.LeyendaError):
             ley.set_params(**bad)

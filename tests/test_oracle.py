@@ -115,6 +115,42 @@ def test_empty_and_single():
     np.testing.assert_array_equal(oracle.sort(r), r)
 
 
+# ---- the multithreaded oracle -----------------------------------------------------
+
+@pytest.mark.parametrize("threads", [2, 3, 5, 8, 16])
+@pytest.mark.parametrize("n", [2, 3, 7, 9, 31, 1000, 65537])
+def test_parallel_sort_matches_one_thread(n, threads):
+    # more threads than records, odd slice counts, and many equal keys (ties
+    # across slice boundaries must still come out in input order)
+    rec = datagen.skewed(n, 40 + n % 7, nvals=16, dup_frac=0.4) if n > 8 else datagen.uniform(n, 41)
+    rec[: n // 2, :10] = rec[0, :10]
+    a, pa = oracle.sort(rec, return_perm=True)
+    b, pb = oracle.sort(rec, return_perm=True, threads=threads)
+    np.testing.assert_array_equal(pb, pa)
+    np.testing.assert_array_equal(b, a)
+
+
+def test_parallel_sort_matches_numpy_lexsort():
+    rec = datagen.skewed(200_000, 43, nvals=256, dup_frac=0.2)
+    _, perm = oracle.sort(rec, return_perm=True, threads=0)
+    np.testing.assert_array_equal(perm.astype(np.int64), _lexsort_perm(rec))
+
+
+@pytest.mark.parametrize("n", [3, 5, 7])
+def test_parallel_sort_brute_force_tiny(n):
+    rng = np.random.default_rng(200 + n)
+    for trial in range(10):
+        keys = []
+        for _ in range(n):
+            k = bytearray(10)
+            for pos in (0, 8, 9):
+                k[pos] = ALPHABET[rng.integers(3)]
+            keys.append(bytes(k))
+        rec = records_from_keys(keys, seed=2000 + trial)
+        _, perm = oracle.sort(rec, return_perm=True, threads=4)
+        assert list(perm) == oracle.brute_force_order(keys)
+
+
 # ---- one-by-one ranks ------------------------------------------------------------
 
 def test_output_rank_matches_full_sort():
