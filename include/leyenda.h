@@ -69,6 +69,23 @@ typedef enum {
  * ------------------------------------------------------------------------- */
 int leyenda_sort(const void *records_dev, uint64_t n, void *out_dev, void *stream);
 
+/* The same sort for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no hipMalloc, hipFree or other allocating call.  Its scratch is a fixed
+ * 64 MiB device array inside the library, one copy per GPU, held until the
+ * process ends; its address is looked up once per device on the first call.
+ * Arguments, layout, ownership and output are those of leyenda_sort; the
+ * caller still allocates records_dev and out_dev.  n is limited by the array:
+ * leyenda_noalloc_max_records() gives the largest n for the current
+ * parameters (about 1.67 million records with the defaults); a larger n
+ * returns LEYENDA_EBUDGET and touches nothing.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on the device (different streams, or
+ * host threads) race and must be serialized by the caller.  Phase timing
+ * (leyenda_profile_*) and leyenda_sort_stats do not cover these calls.
+ * Asynchronous on `stream`. */
+int leyenda_sort_noalloc(const void *records_dev, uint64_t n, void *out_dev, void *stream);
+uint64_t leyenda_noalloc_max_records(void);
+
 /* Flexible key sizes (Section 5 names keys of any size as the method's next
  * step: a prefix sort combined with comparisons of the full keys where the
  * prefixes tie).  Stable sort of n device-resident records by a key of their

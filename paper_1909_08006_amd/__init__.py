@@ -75,6 +75,8 @@ def load():
     P64 = ctypes.POINTER(ctypes.c_uint64)
     sig = {
         "leyenda_sort": ([vp, u64, vp, vp], i32),
+        "leyenda_sort_noalloc": ([vp, u64, vp, vp], i32),
+        "leyenda_noalloc_max_records": ([], u64),
         "leyenda_sort_keyed": ([vp, u64, ctypes.c_uint32, vp, vp], i32),
         "leyenda_workspace_bytes": ([u64], u64),
         "leyenda_sort_parts": ([u64], ctypes.c_uint32),

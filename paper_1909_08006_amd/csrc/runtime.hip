@@ -488,19 +488,20 @@ int sort_tuples_ws(uint64_t n, hipStream_t s, const Tune &t, void *ws) {
 }
 
 int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t, void *ws,
-                   uint32_t key_bytes, uint8_t *ties) {
+                   uint32_t key_bytes, uint8_t *ties, bool bare) {
     const Layout L = plan_layout(n, 1, t);
     Work w = bind_layout(L, ws);
     apply_key_mask(w, key_bytes);
     const uint32_t tiles0 = (uint32_t)((n + t.tile - 1) / t.tile);
     const uint32_t K = parts_for(n);
+    if (bare && K > 1) return fail(LEYENDA_EINTERNAL, "a bare sort runs one output part only");
     Side *sd = nullptr;  // K output parts: the gathers run on the side stream
     if (K > 1) {
         const int rc = get_side(stream, &sd);
         if (rc) return rc;
     }
     ProfCall pc;
-    const bool prof = prof_start(&pc, stream);
+    const bool prof = !bare && prof_start(&pc, stream);
     k_setup_single<<<1, 1, 0, stream>>>(w.reqs, w.hdr, static_cast<const uint8_t *>(records_dev),
                                         static_cast<uint8_t *>(out_dev), n, tiles0);
     if (K == 1) {
@@ -567,6 +568,73 @@ extern "C" int leyenda_sort(const void *records_dev, uint64_t n, void *out_dev, 
     int rc = check_records(records_dev, out_dev, n, "leyenda_sort");
     if (rc) return rc;
     return sort_device(records_dev, n, out_dev, static_cast<hipStream_t>(stream), tune_of(current_params()));
+}
+
+// ---------------------------------------------------------------------------
+// leyenda_sort_noalloc: the same sort with its scratch in a fixed device array
+
+namespace ley {
+
+// The no-alloc sort's workspace: one copy per GPU, held until the process
+// ends.  In host code the array's name is not a device address; the address
+// comes from hipGetSymbolAddress once per device.
+constexpr size_t kNoAllocBytes = 64ull << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64] = {};
+
+// Device address of the current device's copy of `scratch` (looked up on the
+// first call on that device, with the device current).
+static int scratch_ptr(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(LEYENDA_EINVAL, "leyenda_sort_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LEYENDA_OK;
+}
+
+// Largest record count whose workspace fits the array with parameters t
+// (plan_layout grows with n, so a binary search finds it).
+static uint64_t noalloc_max_records(const Tune &t) {
+    uint64_t lo = 0, hi = kNoAllocBytes / 32;  // the tuples alone take 32 B per record
+    while (lo < hi) {
+        const uint64_t m = lo + (hi - lo + 1) / 2;
+        if (plan_layout(m, 1, t).total <= kNoAllocBytes) lo = m; else hi = m - 1;
+    }
+    return lo;
+}
+
+}  // namespace ley
+
+extern "C" uint64_t leyenda_noalloc_max_records(void) { return noalloc_max_records(tune_of(current_params())); }
+
+extern "C" int leyenda_sort_noalloc(const void *records_dev, uint64_t n, void *out_dev, void *stream) {
+    if (n == 0) return LEYENDA_OK;
+    int rc = check_records(records_dev, out_dev, n, "leyenda_sort_noalloc");
+    if (rc) return rc;
+    const Tune t = tune_of(current_params());
+    const Layout L = plan_layout(n, 1, t);
+    if (L.total > kNoAllocBytes)
+        return fail(LEYENDA_EBUDGET,
+                    "leyenda_sort_noalloc: %llu records need %zu bytes of scratch, above the fixed %zu "
+                    "(at most %llu records with the current parameters)",
+                    (unsigned long long)n, L.total, kNoAllocBytes,
+                    (unsigned long long)noalloc_max_records(t));
+    void *ws = nullptr;
+    if ((rc = scratch_ptr(&ws))) return rc;
+    // the kernels clear what they read before writing it (control block,
+    // replicas, look-back words), so the array's old contents do not matter
+    return sort_device_ws(records_dev, n, out_dev, static_cast<hipStream_t>(stream), t, ws, kKeyBytes, nullptr,
+                          true);
 }
 
 extern "C" uint32_t leyenda_sort_parts(uint64_t n) { return parts_for(n); }
