@@ -280,6 +280,22 @@ int leyenda_serve_replay(const leyenda_server_config *cfg, uint64_t count, const
  * scatter_threads threads per device-wide partition workgroup (256, 512 or
  *                1024; the tile stays 256 * tile_items keys).
  * local_threads  threads per local-sort workgroup (256 or 512).
+ * first_pass     how a single sort of at least 8 Mi records makes its
+ *                first-digit buckets (Algorithm 1's first partition round on
+ *                the key-pointer tuples of Section 3.2):
+ *                0  an extraction pass writes the tuples in input order with
+ *                   the first-digit histogram, then a partition pass moves
+ *                   them into their buckets;
+ *                1  one pass extracts the tuples and writes them straight
+ *                   into their buckets, each bucket a chain of fixed-size
+ *                   chunks (its size is unknown while the pass runs; a tile's
+ *                   offset inside a bucket comes from a look-back over the
+ *                   tiles before it);
+ *                2  as 1, and the pass also copies every record into its
+ *                   bucket's chunks, so the final gather reads one bucket's
+ *                   region at a time (Section 3.1, cache-aware scattering)
+ *                   instead of the whole input.
+ *                Smaller sorts, batches and the external calls always use 0.
  * ------------------------------------------------------------------------- */
 typedef struct {
     uint32_t digit_bits;
@@ -289,6 +305,7 @@ typedef struct {
     uint32_t local_capacity;
     uint32_t scatter_threads;
     uint32_t local_threads;
+    uint32_t first_pass;
 } leyenda_params;
 
 int leyenda_get_params(leyenda_params *out);

@@ -37,7 +37,7 @@ class Params(ctypes.Structure):
     _fields_ = [("digit_bits", ctypes.c_uint32), ("tile_items", ctypes.c_uint32),
                 ("big_threshold", ctypes.c_uint32), ("tiny_threshold", ctypes.c_uint32),
                 ("local_capacity", ctypes.c_uint32), ("scatter_threads", ctypes.c_uint32),
-                ("local_threads", ctypes.c_uint32)]
+                ("local_threads", ctypes.c_uint32), ("first_pass", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

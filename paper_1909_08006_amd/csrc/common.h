@@ -69,6 +69,8 @@ struct Ctl {
     uint32_t guard;
     uint32_t pad;
     unsigned long long moved[kMaxLev + 2];
+    uint32_t ftile_ctr;         // next tile of the fused first pass
+    uint32_t pool_ctr;          // next free chunk of the first-pass tuple pool
 };
 
 // Batch request (level-0 segment) descriptor.
@@ -100,12 +102,32 @@ struct Tune {
     uint32_t tiny;         // comparison-sort threshold inside the local sort
     uint32_t scatter_wg;   // threads per partition workgroup (256, 512 or 1024; same tile)
     uint32_t local_wg;     // threads per local-sort workgroup (256 or 512)
+    uint32_t first_pass;   // kFirstSplit, kFirstFused or kFirstRecords (large single sorts)
 };
+
+// How a large single sort makes its level-0 buckets.
+//   kFirstSplit    extraction pass (tuples in input order + first-digit
+//                  histogram), then a partition pass over the tuples
+//   kFirstFused    one pass: tuples extracted and written straight into their
+//                  first-digit buckets, held as chains of chunks (the bucket
+//                  sizes are not known while the pass runs); a tile's offset
+//                  inside each bucket comes from a look-back over the tiles
+//                  before it
+//   kFirstRecords  the same pass also copies each record into its bucket's
+//                  chunks, so the final gather reads records from a region of
+//                  one bucket at a time instead of from the whole input
+constexpr uint32_t kFirstSplit = 0, kFirstFused = 1, kFirstRecords = 2;
+// Fused first pass: 1,024 threads a tile, 8 keys each (4 with the record
+// copy, whose staging needs LDS too).  A tile must not exceed the partition
+// tile (the chunk), so a tile's run of one digit spans at most two chunks.
+constexpr int kFuseWG = 1024;
+__host__ __device__ constexpr int fuse_items(uint32_t first_pass) { return first_pass == kFirstRecords ? 4 : 8; }
+__host__ __device__ constexpr uint32_t fuse_tile(uint32_t first_pass) { return kFuseWG * fuse_items(first_pass); }
 
 // Device workspace views for one sort.
 struct Work {
-    uint64_t *H[2];      // big-endian key bytes 0..7
-    uint64_t *L[2];      // (key bytes 8..9) << 32 | record index
+    uint64_t *H[3];      // big-endian key bytes 0..7 (buffers 0 and 1; 2: the first-pass chunk pool)
+    uint64_t *L[3];      // (key bytes 8..9) << 32 | record index
     uint32_t *idx;       // sorted record index per output position
     Ctl *ctl;
     Seg *segs[2];        // by level parity
@@ -126,7 +148,19 @@ struct Work {
     // the bytes past it, so records equal on it tie and keep index order)
     uint64_t kmask_h;
     uint32_t kmask_l;
+    // fused first pass (null/zero otherwise): bucket d's chunk j is pool chunk
+    // ctab[d * ctab_stride + j] - 1 (0: not yet allocated); a chunk holds
+    // `tile` keys, so level-1 tile k of a bucket is its chunk k, and
+    // tsrc[tile] names that chunk for the level-1 tile map
+    uint32_t *ctab;
+    uint32_t ctab_stride;
+    uint32_t max_chunks;
+    uint32_t *tsrc;
+    uint8_t *rpool;      // kFirstRecords: records in pool order (max_chunks * tile records)
 };
+
+// Buffer a partition pass writes the children of a bucket held in buffer b to.
+__host__ __device__ constexpr uint8_t next_buf(uint8_t b) { return b == 2 ? 1 : b ^ 1; }
 
 // Workspace sizing for a tuple space of n keys and up to `reqs` requests.
 struct Layout {
@@ -134,8 +168,13 @@ struct Layout {
     uint32_t max_seg, max_tiles, max_tasks, max_reqs, max_reps;
     size_t off_H0, off_H1, off_L0, off_L1, off_idx, off_ctl, off_seg0, off_seg1, off_rep0,
         off_rep1, off_ts0, off_ts1, off_status, off_cstat, off_tasks, off_reqs, off_hdr, total;
+    // fused first pass (first_pass != kFirstSplit; all zero otherwise)
+    uint32_t first_pass, max_chunks, ctab_stride;
+    size_t off_PH, off_PL, off_ctab, off_tsrc, off_rpool;
 };
-Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t);
+// first_pass: the first pass the layout has room for (kFirstSplit: none of
+// the pool regions).
+Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t, uint32_t first_pass = kFirstSplit);
 Work bind_layout(const Layout &L, void *base);
 
 // Launch wrappers (sort_kernels.hip).  All return hipError_t of the launches.
@@ -151,6 +190,8 @@ struct Stage {
     bool head = true;                      // k_init + k_extract first
     bool tuples_in = false;                // head: the tuples are already in buffer 0 (level-0
                                            // histogram pass instead of the extraction)
+    uint32_t first = kFirstSplit;          // head: how level 0 is made (kFirstFused/kFirstRecords:
+                                           // one fused pass, the levels start at 1)
     bool tail = true;                      // the local sorts after
     int gate = kMaxLev;                    // the tail exits if level `gate` has big buckets
     uint32_t *flag = nullptr;              // host-visible word: 1 if level `gate` has big buckets

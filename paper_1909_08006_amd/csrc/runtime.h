@@ -40,8 +40,12 @@ int guard_or_pooled(hipStream_t stream, uint32_t *acc);
 int sort_tuples_ws(uint64_t n, hipStream_t s, const Tune &t, void *ws);
 // Same sort with a caller-provided workspace of plan_layout(n, 1, t).total bytes.
 // bare: no phase-timing events and no side stream (one output part only).
+// first_pass: kFirstSplit, or the first pass the workspace was laid out for
+// (first_pass_for's choice for this n).
 int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t, void *ws,
-                   uint32_t key_bytes = kKeyBytes, uint8_t *ties = nullptr, bool bare = false);
+                   uint32_t key_bytes = kKeyBytes, uint8_t *ties = nullptr, bool bare = false,
+                   uint32_t first_pass = kFirstSplit);
+uint32_t first_pass_for(uint64_t n, const Tune &t, bool ties);
 
 // batch.hip
 int batch_sort(const leyenda_segment *segs, uint64_t count, hipStream_t s);

@@ -40,7 +40,7 @@ int hip_fail(hipError_t e, const char *what) {
 // parameters
 
 static std::mutex g_param_mu;
-static leyenda_params g_params = {8, 32, 2048, 128, 2048, 1024, 512};
+static leyenda_params g_params = {8, 32, 2048, 128, 2048, 1024, 512, kFirstSplit};
 
 leyenda_params current_params() {
     std::lock_guard<std::mutex> lk(g_param_mu);
@@ -56,6 +56,7 @@ Tune tune_of(const leyenda_params &p) {
     t.tiny = p.tiny_threshold;
     t.scatter_wg = p.scatter_threads;
     t.local_wg = p.local_threads;
+    t.first_pass = p.first_pass;
     return t;
 }
 
@@ -64,7 +65,7 @@ static bool params_ok(const leyenda_params &p) {
            (p.tile_items == 8 || p.tile_items == 16 || p.tile_items == 32) && p.local_capacity == kLocalCap &&
            p.big_threshold >= 1 && p.big_threshold <= p.local_capacity && p.tiny_threshold >= 1 &&
            p.tiny_threshold <= 256 && (p.scatter_threads == 256 || p.scatter_threads == 512 || p.scatter_threads == 1024) &&
-           (p.local_threads == 256 || p.local_threads == 512);
+           (p.local_threads == 256 || p.local_threads == 512) && p.first_pass <= kFirstRecords;
 }
 
 // ---------------------------------------------------------------------------
@@ -87,7 +88,7 @@ int device_cus() {
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t) {
+Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t, uint32_t first_pass) {
     Layout L{};
     L.n = n;
     const uint64_t segs = std::max<uint64_t>(reqs, n / ((uint64_t)t.big + 1)) + 1;
@@ -118,6 +119,19 @@ Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t) {
     L.off_tasks = take((size_t)kParts * L.max_tasks * sizeof(Task));
     L.off_reqs = take((size_t)L.max_reqs * sizeof(Req));
     L.off_hdr = take(sizeof(Hdr));
+    if (first_pass != kFirstSplit) {
+        // chunk pool of the fused first pass: every bucket's last chunk may be
+        // partly empty, so 256 chunks beyond the keys' own
+        const uint64_t C = t.tile;
+        L.first_pass = first_pass;
+        L.max_chunks = (uint32_t)(n / C + kRadix + 1);
+        L.ctab_stride = (uint32_t)(n / C + 2);
+        L.off_PH = take((size_t)L.max_chunks * C * 8);
+        L.off_PL = take((size_t)L.max_chunks * C * 8);
+        L.off_ctab = take((size_t)kRadix * L.ctab_stride * 4);
+        L.off_tsrc = take((size_t)L.max_tiles * 4);
+        if (first_pass == kFirstRecords) L.off_rpool = take((size_t)L.max_chunks * C * kRec);
+    }
     L.total = o;
     return L;
 }
@@ -152,6 +166,15 @@ Work bind_layout(const Layout &L, void *base) {
     w.max_reps = L.max_reps;
     w.kmask_h = ~0ull;
     w.kmask_l = 0xFFFFu;
+    if (L.first_pass != kFirstSplit) {
+        w.H[2] = reinterpret_cast<uint64_t *>(b + L.off_PH);
+        w.L[2] = reinterpret_cast<uint64_t *>(b + L.off_PL);
+        w.ctab = reinterpret_cast<uint32_t *>(b + L.off_ctab);
+        w.ctab_stride = L.ctab_stride;
+        w.max_chunks = L.max_chunks;
+        w.tsrc = reinterpret_cast<uint32_t *>(b + L.off_tsrc);
+        if (L.first_pass == kFirstRecords) w.rpool = reinterpret_cast<uint8_t *>(b + L.off_rpool);
+    }
     return w;
 }
 
@@ -435,14 +458,31 @@ static void part_bounds(uint64_t n, uint32_t K, uint64_t *end) {
     for (uint32_t k = 0; k < K; k++) end[k] = k + 1 == K ? n : n * kEnd16[k] / 16;
 }
 
+// The first pass a single sort of n records takes with parameters t: the
+// fused ones only for sorts split into output parts (at least 8 Mi records),
+// with a partition tile that holds a fused tile, and look-back words for every
+// fused tile; the record copy not when the gather also marks ties, nor when a
+// pool slot would not fit the 32-bit index.
+uint32_t first_pass_for(uint64_t n, const Tune &t, bool ties) {
+    uint32_t fp = t.first_pass;
+    if (fp == kFirstSplit || parts_for(n) < 2) return kFirstSplit;
+    if (fp == kFirstRecords && ties) fp = kFirstFused;
+    if (fuse_tile(fp) > t.tile) return kFirstSplit;
+    const Layout L = plan_layout(n, 1, t, fp);
+    if ((n + fuse_tile(fp) - 1) / fuse_tile(fp) > L.max_tiles) return kFirstSplit;
+    if (fp == kFirstRecords && (uint64_t)L.max_chunks * t.tile >= 0xFFFFFFFFull) fp = kFirstFused;
+    return fp;
+}
+
 int sort_device(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t,
                 uint32_t key_bytes, uint8_t *ties) {
-    const Layout L = plan_layout(n, 1, t);
+    const uint32_t fp = first_pass_for(n, t, ties != nullptr);
+    const Layout L = plan_layout(n, 1, t, fp);
     void *ws = nullptr;
     int rc = get_workspace(stream, L.total, &ws);
     if (rc) return rc;
     remember_layout(stream, L);
-    return sort_device_ws(records_dev, n, out_dev, stream, t, ws, key_bytes, ties);
+    return sort_device_ws(records_dev, n, out_dev, stream, t, ws, key_bytes, ties, false, fp);
 }
 
 void apply_key_mask(Work &w, uint32_t key_bytes) {
@@ -488,13 +528,14 @@ int sort_tuples_ws(uint64_t n, hipStream_t s, const Tune &t, void *ws) {
 }
 
 int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream_t stream, const Tune &t, void *ws,
-                   uint32_t key_bytes, uint8_t *ties, bool bare) {
-    const Layout L = plan_layout(n, 1, t);
+                   uint32_t key_bytes, uint8_t *ties, bool bare, uint32_t first_pass) {
+    const Layout L = plan_layout(n, 1, t, first_pass);
     Work w = bind_layout(L, ws);
     apply_key_mask(w, key_bytes);
     const uint32_t tiles0 = (uint32_t)((n + t.tile - 1) / t.tile);
     const uint32_t K = parts_for(n);
     if (bare && K > 1) return fail(LEYENDA_EINTERNAL, "a bare sort runs one output part only");
+    if (first_pass != kFirstSplit && K < 2) return fail(LEYENDA_EINTERNAL, "a fused first pass needs output parts");
     Side *sd = nullptr;  // K output parts: the gathers run on the side stream
     if (K > 1) {
         const int rc = get_side(stream, &sd);
@@ -534,8 +575,15 @@ int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream
     }
     Stage st;
     st.tail = false;
+    st.first = first_pass;
     hipError_t e = launch_sort_core(wp, t, 1, tiles0, stream, device_cus(), prof ? pc.e + 1 : nullptr, st);
+    // the gather reads the caller's records, or the record pool of the first pass
     const uint8_t *rec = static_cast<const uint8_t *>(records_dev);
+    uint64_t n_rec = n;
+    if (first_pass == kFirstRecords) {
+        rec = w.rpool;
+        n_rec = (uint64_t)L.max_chunks * t.tile;
+    }
     uint8_t *out = static_cast<uint8_t *>(out_dev);
     for (uint32_t k = 0; k < K && e == hipSuccess; k++) {
         const uint64_t c0 = k ? wp.part_end[k - 1] : 0, c1 = wp.part_end[k];
@@ -544,8 +592,8 @@ int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream
         if (e == hipSuccess) e = hipStreamWaitEvent(sd->s, sd->ready[k], 0);
         if (e == hipSuccess && pg) e = hipEventRecord(pc.g[2 * k], sd->s);
         if (e == hipSuccess && c1 > c0)
-            e = launch_gather_single(rec, n, w.idx + c0, out + c0 * kRec, c1 - c0, sd->s, ties ? ties + c0 : nullptr,
-                                     c0 > 0);
+            e = launch_gather_single(rec, n_rec, w.idx + c0, out + c0 * kRec, c1 - c0, sd->s,
+                                     ties ? ties + c0 : nullptr, c0 > 0);
         if (e == hipSuccess && pg) e = hipEventRecord(pc.g[2 * k + 1], sd->s);
     }
     if (e == hipSuccess && prof) e = hipEventRecord(pc.e[3], stream);
@@ -640,7 +688,8 @@ extern "C" int leyenda_sort_noalloc(const void *records_dev, uint64_t n, void *o
 extern "C" uint32_t leyenda_sort_parts(uint64_t n) { return parts_for(n); }
 
 extern "C" uint64_t leyenda_workspace_bytes(uint64_t n) {
-    return plan_layout(n, 1, tune_of(current_params())).total;
+    const Tune t = tune_of(current_params());
+    return plan_layout(n, 1, t, first_pass_for(n, t, false)).total;
 }
 
 extern "C" int leyenda_get_params(leyenda_params *out) {
@@ -683,6 +732,7 @@ extern "C" int leyenda_load_params(const char *json_path) {
     json_field(s, "local_capacity", &p.local_capacity);
     json_field(s, "scatter_threads", &p.scatter_threads);
     json_field(s, "local_threads", &p.local_threads);
+    json_field(s, "first_pass", &p.first_pass);
     return leyenda_set_params(&p);
 }
 

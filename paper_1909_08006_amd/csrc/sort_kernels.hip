@@ -150,8 +150,20 @@ constexpr uint32_t kSpinLimit = 1u << 24;
 // the tile that points at it (defence against a fired capacity guard).
 __device__ __forceinline__ bool seg_ok(const Work &w, const Seg &sg, uint32_t tile) {
     return sg.count > 0 && sg.start + sg.count <= w.n && tile >= sg.first_tile &&
-           tile - sg.first_tile < sg.ntiles && sg.buf <= 1 && sg.nrep >= 1 && sg.nrep <= kMaxRep &&
+           tile - sg.first_tile < sg.ntiles && sg.buf <= 2 && sg.nrep >= 1 && sg.nrep <= kMaxRep &&
            (uint64_t)sg.rep_first + sg.nrep <= w.max_reps;
+}
+
+// First tuple of tile `tile` of bucket sg (tile k of the bucket starts at key
+// k * tile): in buffer 0 or 1 the bucket is contiguous; in the first-pass pool
+// (buffer 2) tile k is the bucket's chunk k, named by the tile map tsrc.
+// ok false (nothing may be read) if the chunk lies outside the pool.
+__device__ __forceinline__ uint64_t tile_src(const Work &w, const Seg &sg, uint32_t tile, uint32_t tsize, bool &ok) {
+    ok = true;
+    if (sg.buf != 2) return sg.start + (uint64_t)(tile - sg.first_tile) * tsize;
+    const uint32_t c = w.tsrc[tile];
+    ok = w.tsrc != nullptr && c < w.max_chunks;
+    return (uint64_t)c * tsize;
 }
 
 // ---------------------------------------------------------------------------
@@ -318,7 +330,10 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
     Seg *sp = &w.segs[lev & 1][s];
     const Seg sg = *sp;
     if (sg.count == 0 || sg.nrep == 0) return;  // placeholder left by a fired guard
-    if (sg.count <= tu.big) {  // small bucket: one local-sort task as it is
+    // a bucket held as chunks of the first-pass pool always gets its partition
+    // pass, which also makes it contiguous (tasks read contiguous ranges)
+    const bool chunked = sg.buf == 2;
+    if (sg.count <= tu.big && !chunked) {  // small bucket: one local-sort task as it is
         if (d == 0) {
             sp->spos = kNoScatter;
             emit_task(w, sg.start, sg.count, sg.buf, 0, sg.req);
@@ -330,7 +345,7 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
     const uint32_t cnt = reduce_replicas(rp, sg.nrep, d, &m);
     if (d < 4) p_mask[d] = m;
     const int isconst = __syncthreads_or(cnt == sg.count);
-    if (isconst) {  // digit at pos is constant over the bucket: skip ahead without moving data
+    if (isconst && !chunked) {  // digit at pos is constant over the bucket: skip ahead without moving data
         if (d == 0) {
             sp->spos = kNoScatter;
             const uint32_t f = first_varying(p_mask[0], p_mask[1], p_mask[2], p_mask[3]);
@@ -348,7 +363,7 @@ __device__ void plan_segment(const Work &w, const Tune &tu, int lev, uint32_t s)
         sp->spos = (uint16_t)p;
         atomicAdd(&w.ctl->moved[lev], (unsigned long long)sg.count);
     }
-    const uint8_t cbuf = sg.buf ^ 1;
+    const uint8_t cbuf = next_buf(sg.buf);
     const uint32_t cpos = p + tu.digit;
     if (cnt > tu.big && cpos >= kKeyBits) emit_sorted(w, sg.start + base, cnt, cbuf, sg.req);  // equal keys
     new_segments_block(w, tu, lev + 1, cnt > tu.big && cpos < kKeyBits, sg.start + base, cnt, cpos, cbuf, sg.req);
@@ -588,6 +603,348 @@ __global__ __launch_bounds__(kWG) void k_extract(Work w, Tune tu) {
 }
 
 // ---------------------------------------------------------------------------
+// Fused first pass (one request): extraction and the level-0 partition in one
+// pass over the records.
+//
+// A bucket's size is known only once every tile has been read, so the pass
+// cannot place a bucket at its final offset.  Each bucket is instead a chain
+// of chunks of `tile` keys taken from a pool as the bucket grows: a tile's run
+// of digit d occupies positions [v, v + c) of bucket d's own position space,
+// v being the count of digit d in the tiles before it (a decoupled look-back
+// over per-tile status words, tiles taken in order from a counter), and
+// position p of bucket d lives in slot p % tile of chunk ctab[d][p / tile].
+// The tile whose run covers a chunk's first position takes that chunk from
+// the pool counter and publishes it; a tile whose run starts inside a chunk
+// waits for it (the owner is an earlier tile that has finished its
+// look-back, so the wait ends).  Runs are at most one tile long, so a run
+// touches at most two chunks.  Positions follow input order within a bucket
+// (tiles in order, keys ranked stably inside a tile), so the buckets hold
+// their keys in stable order, as the separate passes would.
+//
+// RECORDS: the pass also copies each record to pool slot (chunk * tile +
+// slot) of a record pool, and a tuple carries its position inside its bucket
+// instead of the record index (positions order the bucket's keys like the
+// input does, so ties still break by input order); the local sorts turn
+// positions into pool slots for the gather.
+
+// Clears the first pass's look-back words and chunk table.
+__global__ __launch_bounds__(kWG) void k_fzero(unsigned long long *status, uint64_t nstatus, uint32_t *ctab,
+                                               uint64_t nctab) {
+    const uint64_t stride = (uint64_t)gridDim.x * kWG;
+    for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < nstatus; i += stride) status[i] = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kWG + threadIdx.x; i < nctab; i += stride) ctab[i] = 0;
+}
+
+// A free chunk of the pool (0xFFFFFFFF and a guard bit if none is left).
+__device__ __forceinline__ uint32_t fuse_chunk_take(const Work &w) {
+    const uint32_t c = atomicAdd(&w.ctl->pool_ctr, 1u);
+    if (c >= w.max_chunks) { atomicOr(&w.ctl->guard, 512u); return 0xFFFFFFFFu; }
+    return c;
+}
+
+template <int FWG, int FI, bool RECORDS>
+__global__ __launch_bounds__(FWG, 1) void k_fuse0(Work w, Tune tu) {
+    constexpr int FT = FWG * FI;
+    constexpr int NW = FWG / 64;
+    __shared__ uint64_t sH[FT];
+    __shared__ uint64_t sL[FT];
+    __shared__ uint32_t cnt[NW][kRadix];
+    __shared__ uint32_t lbase[kRadix];
+    __shared__ uint32_t vbase[kRadix];      // first position of the tile's run in its bucket
+    __shared__ uint32_t cph[2][kRadix];     // pool chunks of the run's first and second part
+    __shared__ uint32_t tmp[NW];
+    __shared__ uint32_t s_tile;
+    __shared__ uint16_t sQ[RECORDS ? FT : 1];  // staged slot -> key within the tile
+    __shared__ uint32_t sP[RECORDS ? FT : 1];  // staged slot -> pool slot (~0: none)
+
+    const Req rq = w.reqs[0];
+    const uint64_t n = rq.n;
+    const uint32_t nft = (uint32_t)((n + FT - 1) / FT);
+    const uint32_t C = tu.tile;
+    const uint32_t cshift = 31u - (uint32_t)__builtin_clz(C);
+    const uint32_t ndig = 1u << tu.digit;
+    const uint32_t shift = 64u - tu.digit;
+    const uint64_t pool_keys = (uint64_t)w.max_chunks * C;
+    for (;;) {
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const uint32_t wv = tid >> 6, lane = tid & 63;
+        __syncthreads();
+        if (tid == 0) s_tile = atomicAdd(&w.ctl->ftile_ctr, 1u);
+        for (uint32_t i = tid; i < NW * kRadix; i += FWG) (&cnt[0][0])[i] = 0;
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        if (tile >= nft) break;
+        const uint64_t local0 = (uint64_t)tile * FT;
+        const uint32_t nvalid = (uint32_t)min<uint64_t>(FT, n - local0);
+        // keys of the tile: wave wv holds keys [wv * FI * 64, (wv + 1) * FI * 64)
+        // of the tile, item u of lane l being key wv * FI * 64 + u * 64 + l
+        uint64_t h[FI], l[FI];
+        {
+            uint32_t a[FI], b[FI], c[FI];
+#pragma unroll
+            for (int u = 0; u < FI; u++) {
+                const uint32_t q = wv * (FI * 64) + u * 64 + lane;
+                const uint32_t qc = q < nvalid ? q : nvalid - 1;  // loads stay branch-free
+                const gu32 *p = (const gu32 *)(rq.in + (local0 + qc) * kRec);
+                if (RECORDS) {  // the record is copied below: keep its lines in the caches
+                    a[u] = p[0]; b[u] = p[1]; c[u] = p[2];
+                } else {
+                    a[u] = __builtin_nontemporal_load(p);
+                    b[u] = __builtin_nontemporal_load(p + 1);
+                    c[u] = __builtin_nontemporal_load(p + 2);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < FI; u++) {
+                const uint32_t q = wv * (FI * 64) + u * 64 + lane;
+                h[u] = __builtin_bswap64(((uint64_t)b[u] << 32) | a[u]) & w.kmask_h;
+                const uint64_t k16 = __builtin_bswap16((uint16_t)(c[u] & 0xFFFFu)) & w.kmask_l;
+                l[u] = (k16 << 32) | (uint32_t)(local0 + q);
+            }
+        }
+        // stable ranks by the leading digit (eight items at a time)
+        uint32_t pk[FI];
+        constexpr int RCH = FI < 8 ? FI : 8;
+#pragma unroll
+        for (int c0 = 0; c0 < FI; c0 += RCH) {
+            uint32_t old[RCH];
+#pragma unroll
+            for (int u = c0; u < c0 + RCH; u++) {
+                const uint32_t q = wv * (FI * 64) + u * 64 + lane;
+                const bool valid = q < nvalid;
+                rank_issue(valid ? (uint32_t)(h[u] >> shift) : 0u, valid, cnt[wv], old[u - c0], pk[u]);
+            }
+#pragma unroll
+            for (int u = c0; u < c0 + RCH; u++) pk[u] = (pk[u] & 0xFFu) | (rank_finish(old[u - c0], pk[u]) << 8);
+        }
+        __syncthreads();
+        const bool dl = tid < ndig;  // digit lanes
+        uint32_t tot = 0;
+        if (dl) {
+#pragma unroll
+            for (int j = 0; j < NW; j++) {
+                const uint32_t cj = cnt[j][tid];
+                cnt[j][tid] = tot;
+                tot += cj;
+            }
+        }
+        const uint32_t lb = block_excl_scan<NW>(tot, tmp);
+        unsigned long long *const st = w.status + (size_t)tile * kRadix + tid;
+        if (dl) {
+            lbase[tid] = lb;
+            // the tile's count, published before the staging so later tiles
+            // can sum past this one while it stages
+            st_agent(st, (tile == 0 ? kFlagInc : kFlagAgg) | tot);
+        }
+        __syncthreads();
+        // keys to their slots in the tile (digit-major)
+#pragma unroll
+        for (int u = 0; u < FI; u++) {
+            const uint32_t q = wv * (FI * 64) + u * 64 + lane;
+            if (q < nvalid) {
+                const uint32_t d = pk[u] & 0xFFu;
+                const uint32_t pos = lbase[d] + cnt[wv][d] + (pk[u] >> 8);
+                sH[pos] = h[u];
+                sL[pos] = l[u];
+                if (RECORDS) sQ[pos] = (uint16_t)q;
+            }
+        }
+        if (dl) {
+            // look back over the tiles before this one for the counts of digit tid
+            uint64_t excl = 0;
+            if (tile > 0) {
+                constexpr int LW = 8;
+                uint32_t spins = 0;
+                bool done = false;
+                for (uint32_t t0 = tile - 1; !done; t0 -= LW) {
+                    unsigned long long v[LW];
+#pragma unroll
+                    for (int k = 0; k < LW; k++)
+                        v[k] = t0 >= (uint32_t)k ? ld_agent(w.status + (size_t)(t0 - k) * kRadix + tid) : 0ull;
+#pragma unroll
+                    for (int k = 0; k < LW; k++) {
+                        if (done) break;
+                        const uint32_t tt = t0 - k;
+                        while ((v[k] >> 62) == 0 && spins < kSpinLimit) {
+                            __builtin_amdgcn_s_sleep(1);
+                            spins++;
+                            v[k] = ld_agent(w.status + (size_t)tt * kRadix + tid);
+                        }
+                        if (spins >= kSpinLimit) { atomicOr(&w.ctl->guard, 16u); done = true; break; }
+                        excl += v[k] & kCountMask;
+                        if ((v[k] & kFlagInc) || tt == 0) done = true;
+                    }
+                }
+                st_agent(st, kFlagInc | (excl + tot));
+            }
+            vbase[tid] = (uint32_t)excl;
+            // the run's chunks: take those whose first position lies in the
+            // run, then wait for the one it starts inside (if any)
+            uint32_t c0 = 0xFFFFFFFFu, c1 = 0xFFFFFFFFu;
+            if (tot) {
+                uint32_t *ct = w.ctab + (size_t)tid * w.ctab_stride;
+                const uint64_t j0 = excl >> cshift, j1 = (excl + tot - 1) >> cshift;
+                const bool own0 = (excl & (C - 1)) == 0;
+                if (j1 >= w.ctab_stride) {
+                    atomicOr(&w.ctl->guard, 512u);
+                } else {
+                    if (own0) {
+                        c0 = fuse_chunk_take(w);
+                        __hip_atomic_store(ct + j0, c0 + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    if (j1 != j0) {
+                        c1 = fuse_chunk_take(w);
+                        __hip_atomic_store(ct + j1, c1 + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    if (!own0) {
+                        uint32_t x = ld_agent32(ct + j0);
+                        uint32_t spins = 0;
+                        while (x == 0 && spins < kSpinLimit) {
+                            __builtin_amdgcn_s_sleep(1);
+                            spins++;
+                            x = ld_agent32(ct + j0);
+                        }
+                        if (x == 0) atomicOr(&w.ctl->guard, 16u);
+                        c0 = x - 1u;  // 0xFFFFFFFF if never published
+                    }
+                }
+            }
+            cph[0][tid] = c0;
+            cph[1][tid] = c1;
+        }
+        __syncthreads();
+        // runs to their chunks
+        uint64_t *PH = w.H[2], *PL = w.L[2];
+#pragma unroll
+        for (int u = 0; u < FI; u++) {
+            const uint32_t q = u * FWG + tid;
+            if (q < nvalid) {
+                const uint64_t hh = sH[q];
+                const uint32_t d = (uint32_t)(hh >> shift);
+                const uint32_t v = vbase[d] + (q - lbase[d]);
+                const uint32_t ch = ((v >> cshift) == (vbase[d] >> cshift)) ? cph[0][d] : cph[1][d];
+                const uint64_t slot = (uint64_t)ch * C + (v & (C - 1));
+                uint64_t ll = sL[q];
+                if (RECORDS) ll = (ll & ~0xFFFFFFFFull) | v;
+                if (ch < w.max_chunks && slot < pool_keys) {
+                    PH[slot] = hh;
+                    PL[slot] = ll;
+                    if (RECORDS) sP[q] = (uint32_t)slot;
+                } else {
+                    atomicOr(&w.ctl->guard, 512u);
+                    if (RECORDS) sP[q] = 0xFFFFFFFFu;
+                }
+            }
+        }
+        if (RECORDS) {
+            __syncthreads();
+            // records to their pool slots, 25 dwords each, staged order (the
+            // reads hit lines the key loads brought in; the writes are runs)
+            const gu32 *src = (const gu32 *)(rq.in + local0 * kRec);
+            gu32w *dst = (gu32w *)w.rpool;
+            constexpr int PER = (FT * 25 + FWG - 1) / FWG;
+            constexpr int B = 25;  // loads in flight per thread
+#pragma unroll 1
+            for (int u0 = 0; u0 < PER; u0 += B) {
+                uint32_t val[B], dsl[B];
+#pragma unroll
+                for (int u = 0; u < B; u++) {
+                    const uint32_t g = (uint32_t)(u0 + u) * FWG + tid;
+                    const uint32_t sidx = g / 25u, k = g - 25u * sidx;
+                    dsl[u] = 0xFFFFFFFFu;
+                    val[u] = 0;
+                    if (u0 + u < PER && sidx < nvalid) {
+                        dsl[u] = sP[sidx];
+                        if (dsl[u] != 0xFFFFFFFFu) val[u] = src[(uint32_t)sQ[sidx] * 25u + k];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < B; u++) {
+                    const uint32_t g = (uint32_t)(u0 + u) * FWG + tid;
+                    const uint32_t k = g - 25u * (g / 25u);
+                    if (dsl[u] != 0xFFFFFFFFu) __builtin_nontemporal_store(val[u], dst + (uint64_t)dsl[u] * 25u + k);
+                }
+            }
+        }
+    }
+}
+
+// Level-1 buckets of the fused first pass: the bucket counts are the last
+// tile's inclusive look-back words; bucket d (when not empty) becomes level-1
+// bucket number (non-empty digits before d), starting at the sum of the
+// counts before it, with one level-1 tile per chunk.  Every block computes the
+// same scans; block 0 writes the buckets and counters, and all blocks fill the
+// level-1 tile map and chunk names and clear the level-1 replicas.
+__global__ __launch_bounds__(kWG) void k_plan0(Work w, Tune tu, uint32_t ftile) {
+    __shared__ uint32_t tmp[kWaves];
+    __shared__ uint32_t s_ft[kRadix + 1];
+    __shared__ uint32_t s_seg[kRadix];
+    __shared__ uint32_t s_tot[3];
+    const uint32_t d = threadIdx.x;
+    const uint64_t n = w.reqs[0].n;
+    const uint32_t nft = (uint32_t)((n + ftile - 1) / ftile);
+    const uint32_t C = tu.tile;
+    uint32_t c = 0;
+    if (nft > 0 && d < (1u << tu.digit)) {
+        const unsigned long long v = ld_agent(w.status + (size_t)(nft - 1) * kRadix + d);
+        if (!(v & kFlagInc)) { if (blockIdx.x == 0) atomicOr(&w.ctl->guard, 16u); }
+        else c = (uint32_t)(v & kCountMask);
+    }
+    const bool need = c > 0;
+    const uint32_t nt = need ? (c + C - 1) / C : 0u;
+    const uint32_t nr = min(nt, (uint32_t)kMaxRep);
+    const uint32_t es = block_excl_scan(need ? 1u : 0u, tmp);
+    const uint32_t et = block_excl_scan(nt, tmp);
+    const uint32_t er = block_excl_scan(nr, tmp);
+    const uint32_t base = block_excl_scan(c, tmp);
+    s_ft[d] = et;
+    s_seg[d] = es;
+    if (d == kWG - 1) {
+        s_ft[kRadix] = et + nt;
+        s_tot[0] = es + (need ? 1u : 0u);
+        s_tot[1] = et + nt;
+        s_tot[2] = er + nr;
+    }
+    __syncthreads();
+    const bool fits = s_tot[0] <= w.max_seg && s_tot[1] <= w.max_tiles && s_tot[2] <= w.max_reps &&
+                      (uint64_t)base + c <= w.n;
+    const int all_fit = __syncthreads_and(fits);
+    if (!all_fit) {
+        if (blockIdx.x == 0 && d == 0) { atomicOr(&w.ctl->guard, 4u); w.ctl->nseg[1] = 0; w.ctl->ntiles[1] = 0; }
+        return;
+    }
+    if (blockIdx.x == 0) {
+        if (need) {
+            Seg g;
+            g.start = base; g.count = c; g.first_tile = et; g.ntiles = nt; g.rep_first = er; g.nrep = (uint8_t)nr;
+            g.pos = (uint16_t)tu.digit; g.spos = kNoScatter; g.buf = 2; g.req = 0;
+            w.segs[1][es] = g;
+        }
+        if (d == 0) {
+            w.ctl->nseg[1] = s_tot[0];
+            w.ctl->ntiles[1] = s_tot[1];
+            w.ctl->rep_ctr[1] = s_tot[2];
+            w.ctl->moved[0] = n;
+        }
+    }
+    // tile map and chunk names of the level-1 tiles
+    const uint32_t ntl = s_tot[1];
+    for (uint32_t t = blockIdx.x * kWG + d; t < ntl; t += gridDim.x * kWG) {
+        uint32_t lo = 0, hi = kRadix - 1;  // last digit whose first tile is <= t
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (s_ft[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        w.tile_seg[1][t] = s_seg[lo];
+        const uint32_t cv = w.ctab[(size_t)lo * w.ctab_stride + (t - s_ft[lo])];
+        w.tsrc[t] = cv - 1u;  // 0xFFFFFFFF (outside the pool) if never taken
+    }
+    const uint64_t nw = (uint64_t)s_tot[2] * kRepWords;
+    for (uint64_t i = (uint64_t)blockIdx.x * kWG + d; i < nw; i += (uint64_t)gridDim.x * kWG) w.rep[1][i] = 0;
+}
+
+// ---------------------------------------------------------------------------
 // k_hist: digit histogram and key masks of the big buckets of level lev >= 1
 
 template <int ITEMS>
@@ -611,9 +968,12 @@ __global__ __launch_bounds__(kWG) void k_hist(Work w, Tune tu, int lev) {
             continue;
         }
         const uint64_t local0 = (uint64_t)(tile - sg.first_tile) * tu.tile;
+        bool src_ok;
+        const uint64_t src = tile_src(w, sg, tile, tu.tile, src_ok);
+        if (!src_ok) { if (threadIdx.x == 0) atomicOr(&w.ctl->guard, 8u); __syncthreads(); continue; }
         const uint32_t nvalid = (uint32_t)min<uint64_t>(tu.tile, sg.count - local0);
-        const uint64_t *H = w.H[sg.buf] + sg.start + local0;
-        const uint64_t *L = w.L[sg.buf] + sg.start + local0;
+        const uint64_t *H = w.H[sg.buf] + src;
+        const uint64_t *L = w.L[sg.buf] + src;
         // key bytes 8..9 are read only when the digit reaches them; otherwise
         // their mask reads "varying", so a bucket constant through byte 7
         // moves on to bit 64 and the next level reads them
@@ -811,9 +1171,12 @@ __global__ __launch_bounds__(WG, (scatter_waves<ITEMS, WG>())) void k_scatter(Wo
         if (sg.spos == kNoScatter || !seg_ok(w, sg, tile) || sg.spos >= kKeyBits) continue;
         const uint64_t seg_end = sg.start + sg.count;
         const uint64_t local0 = (uint64_t)(tile - sg.first_tile) * TILE;
+        bool src_ok;
+        const uint64_t src = tile_src(w, sg, tile, TILE, src_ok);
+        if (!src_ok) { if (tid == 0) atomicOr(&w.ctl->guard, 8u); continue; }
         const uint32_t nvalid = (uint32_t)min<uint64_t>(TILE, sg.count - local0);
-        const uint64_t *Hs = w.H[sg.buf] + sg.start + local0;
-        const uint64_t *Ls = w.L[sg.buf] + sg.start + local0;
+        const uint64_t *Hs = w.H[sg.buf] + src;
+        const uint64_t *Ls = w.L[sg.buf] + src;
         const bool dl = tid < (uint32_t)kRadix;  // digit lanes
         // digit lane: the digit's bucket offset and this tile's offset among the
         // bucket's tiles (both known before the pass; used after the ranking)
@@ -871,8 +1234,8 @@ __global__ __launch_bounds__(WG, (scatter_waves<ITEMS, WG>())) void k_scatter(Wo
         }
         if (dl) gbase[tid] = sg.start + toff - lb;
         __syncthreads();
-        uint64_t *Hd = w.H[sg.buf ^ 1];
-        uint64_t *Ld = w.L[sg.buf ^ 1];
+        uint64_t *Hd = w.H[next_buf(sg.buf)];
+        uint64_t *Ld = w.L[next_buf(sg.buf)];
 #pragma unroll
         for (int u = 0; u < ITEMS; u++) {
             const uint32_t q = u * WG + tid;
@@ -972,6 +1335,7 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu, int gate, 
     __shared__ uint64_t orh[NW], andh[NW], orl[NW], andl[NW];
     __shared__ int stk_n;
     __shared__ uint32_t s_next;
+    __shared__ uint32_t s_d0;  // record pool: the task's leading digit (one first-pass bucket)
 
     // a first part of a two-part sort stands down when deeper levels remain
     if (gate < kMaxLev && w.ctl->nseg[gate] > 0) return;
@@ -1039,6 +1403,7 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu, int gate, 
 #pragma unroll
         for (int u = 0; u < LI; u++) {
             const uint32_t q = u * LWG + tid;
+            if (q == 0 && m > 0) s_d0 = (uint32_t)(ph[u] >> (64 - tu.digit));
             if (q < m) {
                 if (sorted) {
                     segb[q] = (uint32_t)pl[u];
@@ -1196,10 +1561,28 @@ __global__ __launch_bounds__(LWG, MINB) void k_local(Work w, Tune tu, int gate, 
         {
             // a fixed number of stores per thread; lanes past m are dropped
             const __amdgpu_buffer_rsrc_t ro = rsrc_of(w.idx + cur.start, m * 4u);
+            if (w.rpool) {
+                // record pool: a tuple's index is its position in its
+                // first-pass bucket; the gather wants the pool slot
+                const uint32_t C = tu.tile, cshift = 31u - (uint32_t)__builtin_clz(C);
+                const uint32_t *ct = w.ctab + (size_t)ufirst(s_d0) * w.ctab_stride;
 #pragma unroll
-            for (int u = 0; u < LI; u++) {
-                const uint32_t q = u * LWG + tid;
-                __builtin_amdgcn_raw_buffer_store_b32(segb[q], ro, q * 4u, 0, 0);
+                for (int u = 0; u < LI; u++) {
+                    const uint32_t q = u * LWG + tid;
+                    uint32_t v = 0;
+                    if (q < m) {
+                        const uint32_t p = segb[q], j = p >> cshift;
+                        const uint32_t c = j < w.ctab_stride ? ct[j] : 0u;
+                        v = (c != 0u && c - 1u < w.max_chunks) ? (c - 1u) * C + (p & (C - 1u)) : 0xFFFFFFFFu;
+                    }
+                    __builtin_amdgcn_raw_buffer_store_b32(v, ro, q * 4u, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < LI; u++) {
+                    const uint32_t q = u * LWG + tid;
+                    __builtin_amdgcn_raw_buffer_store_b32(segb[q], ro, q * 4u, 0, 0);
+                }
             }
         }
         __syncthreads();  // segb, s_next and the mask slots are reused by the next task
@@ -1376,7 +1759,20 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
         g_hist = occupancy(reinterpret_cast<const void *>(&k_hist<ITEMS>), cus);
         g_loc = occupancy(reinterpret_cast<const void *>(&k_local<LWG, LWG == 512 ? 2 : 3>), cus, LWG);
     }
-    if (st.head) {
+    const bool fused = st.head && st.first != kFirstSplit;
+    if (fused) {
+        // one request of w.n records; the workspace was laid out for this first pass
+        const uint32_t ft = fuse_tile(st.first);
+        const uint64_t nft = (w.n + ft - 1) / ft;
+        k_init<<<dim3(1), dim3(kWG), 0, s>>>(w);
+        k_fzero<<<dim3(cus * 4), dim3(kWG), 0, s>>>(w.status, nft * kRadix, w.ctab,
+                                                    (uint64_t)kRadix * w.ctab_stride);
+        if (st.first == kFirstRecords)
+            k_fuse0<kFuseWG, fuse_items(kFirstRecords), true><<<dim3(cus), dim3(kFuseWG), 0, s>>>(w, t);
+        else
+            k_fuse0<kFuseWG, fuse_items(kFirstFused), false><<<dim3(cus), dim3(kFuseWG), 0, s>>>(w, t);
+        k_plan0<<<dim3(cus * 2), dim3(kWG), 0, s>>>(w, t, ft);
+    } else if (st.head) {
         // nreq / tiles0 == 0: sizes known only on the device (captured sequences)
         k_init<<<dim3(nreq ? max(1u, min(nreq, 1024u)) : 1024u), dim3(kWG), 0, s>>>(w);
         if (st.tuples_in) {  // tuples already in buffer 0: level 0 starts with its histogram pass
@@ -1389,7 +1785,7 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
     if (ev) (void)hipEventRecord(ev[0], s);
     const int g_plan = cus * 4;
     const int lev_end = min(st.lev_end, levels_for((int)t.digit));
-    for (int lev = st.lev_begin; lev < lev_end; lev++) {
+    for (int lev = fused ? max(st.lev_begin, 1) : st.lev_begin; lev < lev_end; lev++) {
         if (lev > 0) k_hist<ITEMS><<<dim3(g_hist), dim3(kWG), 0, s>>>(w, t, lev);
         k_plan<<<dim3(g_plan), dim3(kWG), 0, s>>>(w, t, lev);
         k_scatter<SITEMS, SWG><<<dim3(g_sc), dim3(SWG), 0, s>>>(w, t, lev);
