@@ -33,14 +33,18 @@ PMC_FILE = os.path.join(ROOT, "profiles", "sort_internal_1e8_pmc.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1909_08006_amd", "csrc", "sort_kernels.hip")
 
 # Algorithmic bytes per record of each phase (element granularity, no line overfetch):
-#   extract   reads the 10 key bytes, writes a 16-byte (key, index) tuple
-#   partition per level: reads + writes 16-byte tuples (32 B) for every moved key,
-#             and levels >= 1 first read 8 key bytes per key for their histograms
+#   extract   reads the 10 key bytes, writes a 16-byte (key, index) tuple (with the
+#             fused first pass the tuple goes straight into its level-0 bucket, so
+#             level 0 moves no tuple a second time)
+#   partition per device-wide partition pass: reads + writes 16-byte tuples (32 B)
+#             for every moved key, and levels >= 1 first read 8 key bytes per key
+#             for their histograms
 #   local     reads 16-byte tuples, writes a 4-byte index
 #   gather    reads the 4-byte index and the 100-byte record, writes 100 bytes
 ALG_BYTES = {"extract": 26, "local": 20, "gather": 204}
 KERNEL_OF = {"extract": "k_extract", "partition": "k_hist+k_plan+k_scatter", "local": "k_local",
              "gather": "k_gather_plain"}
+FIRST_PASS_KERNEL = {0: "k_extract", 1: "k_fuse0", 2: "k_fuse0"}
 
 
 def log(msg: str) -> None:
@@ -127,6 +131,35 @@ def cpu_baseline(host_u8, n: int, n_one: int):
            "one_thread": {"records": n_one, "seconds": round(dt1, 3), "gbs": round(n_one * 100 / dt1 / 1e9, 4)},
            "paper_table1_sort_s_10gb": PAPER_TABLE1_S}
     return res, want
+
+
+def first_pass_ab(ley, torch, dev, ref, n: int, steps: int) -> dict:
+    """The sort timed with each first pass (parameter first_pass 0, 1, 2) on
+    the same input: HIP events around `steps` back-to-back sorts after one
+    warm-up, the output compared with `ref` byte for byte."""
+    old = ley.get_params()
+    res = {}
+    try:
+        for fp in (0, 1, 2):
+            ley.set_params(first_pass=fp)
+            out = torch.empty_like(dev)
+            ley.sort(dev, out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                ley.sort(dev, out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            res[str(fp)] = {"ms_per_sort": round(ms, 4), "gbs": round(n * 100 / (ms / 1e3) / 1e9, 2),
+                            "taken": ley.first_pass(n), "same_output": bool(torch.equal(out, ref)),
+                            "guard": ley.stats()["guard"]}
+            del out
+            torch.cuda.empty_cache()
+    finally:
+        ley.set_params(**old)
+    return res
 
 
 def serving(ley, count: int, warm: int, budget: int) -> dict:
@@ -418,6 +451,10 @@ def main() -> int:
                          "5%% duplicates) or printable ASCII; --n sets the size")
     ap.add_argument("--no-ascii", action="store_true", help="skip the 20 GB printable-key workload")
     ap.add_argument("--no-keys", action="store_true", help="skip the flexible key size (leyenda_sort_keyed) runs")
+    ap.add_argument("--first-pass", type=int, choices=[0, 1, 2], default=None,
+                    help="first pass of the sort (library parameter first_pass; default: the library's)")
+    ap.add_argument("--no-first-pass-ab", action="store_true",
+                    help="skip timing the sort with each of the three first passes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 2 GB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -434,6 +471,8 @@ def main() -> int:
     import paper_1909_08006_amd as ley
 
     ley.load()
+    if args.first_pass is not None:
+        ley.set_params(first_pass=args.first_pass)
     n = args.n
     fill, seed, keys = {
         "uniform": (datagen.fill_uniform, datagen.SEED_INTERNAL, "uniform 10-byte keys"),
@@ -483,7 +522,11 @@ def main() -> int:
     ordered = keys_ordered(torch, out, n)
     ok = ok and ordered
 
-    moved = sum(st["moved"])
+    first_pass = ley.first_pass(n)
+    KERNEL_OF["extract"] = FIRST_PASS_KERNEL[first_pass]
+    # keys moved by device-wide partition passes (a fused first pass writes each
+    # tuple into its level-0 bucket once, as the extraction would: no pass)
+    moved = sum(st["moved"]) - (st["moved"][0] if first_pass else 0)
     passes = moved / n
     b_alg = 250 + 32 * passes
     part_bytes = 32 * moved + 8 * sum(st["moved"][1:])
@@ -511,9 +554,15 @@ def main() -> int:
                      "avg_launch_ms": round(avg[dom] / launches, 4)},
         "phases_ms": {k: round(v, 4) for k, v in avg.items()},
         "phase_alg_gbs": {k: round(alg[k] / (avg[k] / 1e3) / 1e9, 1) for k in avg if avg[k] > 0},
+        "first_pass": first_pass,
         "partition_passes": round(passes, 4),
         "b_alg_bytes_per_record": round(b_alg, 2),
         "sort_roofline_frac": round(b_alg * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        # the same time against the algorithmic bytes of the plan with a separate
+        # extraction pass (250 + 32 * (passes + 1) with the fused first pass),
+        # comparable across first passes
+        "sort_roofline_frac_split_plan": round((b_alg + (32 if first_pass else 0)) * n / (ms / 1e3) / 1e9
+                                               / HBM_PEAK_GBS, 4),
         "floor_frac_210B": round(210 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "output_keys_ordered": ordered,
         "device_guards": guards,
@@ -524,6 +573,10 @@ def main() -> int:
         bpr = float(pf["sort_hbm_bytes_per_record"])
         res["sort_hbm_traffic"] = {"bytes_per_record": bpr, "gbs": round(bpr * n / (ms / 1e3) / 1e9, 1),
                                    "source": os.path.relpath(PMC_FILE, ROOT)}
+    # the three first passes on the same input (each output byte-equal to the timed one)
+    if not args.no_first_pass_ab:
+        res["first_pass_ab"] = first_pass_ab(ley, torch, dev, out, n, min(args.steps, 10))
+        ok = ok and all(v["same_output"] and v["guard"] == 0 for v in res["first_pass_ab"].values())
     if not args.no_cpu_baseline:
         # the oracle on the host cores, and the timed sort's output against it record by record
         res["cpu_baseline"], want = cpu_baseline(host, n, min(args.cpu_sample, n))

@@ -107,6 +107,12 @@ int leyenda_sort_keyed(const void *records_dev, uint64_t n, uint32_t key_bytes, 
  * current parameters (tuple buffers, index array, bucket tables). */
 uint64_t leyenda_workspace_bytes(uint64_t n);
 
+/* First pass (0, 1 or 2: see leyenda_params.first_pass) a leyenda_sort of n
+ * records takes under the current parameters: the parameter's value for
+ * sorts of at least 8 Mi records whose partition tile holds a fused tile
+ * (tile_items 32 for 1, 16 or 32 for 2), else 0. */
+uint32_t leyenda_first_pass(uint64_t n);
+
 /* Output parts a leyenda_sort of n records runs in: 1 below 8 Mi records,
  * else 4 (holding 1/16, 1/16, 1/8 and 3/4 of the records in output order).
  * With several parts the local sorts are launched once per part, in
@@ -263,7 +269,10 @@ int leyenda_serve_replay(const leyenda_server_config *cfg, uint64_t count, const
  * the autotuner's sweep on the 10 GB uniform and 20 GB skewed workloads; the
  * tiny threshold from a later sweep of 64..256 on those and on printable keys,
  * whose local-sort tasks pack sub-buckets of about a hundred keys and gain
- * from it, while the binary workloads do not change).
+ * from it, while the binary workloads do not change), first_pass 1 (the
+ * fused pass: 10.34 against 10.95 ms for the 10 GB sort, 25.8 against 27.0 ms
+ * for the 20 GB skewed one; the record copy of 2 costs more in its pass than
+ * it saves in the gather, 13.4 ms).
  * digit_bits     radix digit width in bits, 4..8 (8: 256 buckets per pass, the
  *                byte digit of Algorithm 1; a narrower digit splits each big
  *                bucket 2^digit_bits ways and needs up to ceil(80 / digit_bits)
@@ -374,6 +383,27 @@ int leyenda_debug_extract(const void *records_dev, uint64_t n, uint32_t key_byte
                           uint64_t *lo_dev, uint32_t *hist_dev, void *stream);
 int leyenda_debug_gather(const void *records_dev, uint64_t n_records, const uint32_t *idx_dev,
                          uint64_t n, void *out_dev, void *stream);
+
+/* leyenda_debug_first_pass: the fused first pass of leyenda_sort alone
+ * (first_pass 1 or 2, see leyenda_params), launched as the sort launches it
+ * (for any n >= 1; the sort itself takes it from 8 Mi records on): one pass
+ * that extracts the key-pointer tuples (Section 3.2) and partitions them by
+ * the leading digit (Algorithm 1's first round) into per-bucket chains of
+ * chunks, then the level-1 bucket table.  The buckets are copied out in
+ * bucket order: bucket d's tuples at hi/lo[base_d + p] for its positions p =
+ * 0..count[d]-1, base_d being the sum of count[d'] over d' < d; position p is
+ * the p-th record of bucket d in input order (hi as leyenda_debug_extract;
+ * lo's low 32 bits are the record index for first_pass 1 and p for 2).  With
+ * first_pass 2 rec_out (n x 100 bytes) receives the copied records in the
+ * same order.  count: 256 u32.  Key bytes past key_bytes (1..10) are cleared.
+ * Runs on the workspace of `stream`, asynchronously.  LEYENDA_EINVAL for
+ * NULL or misaligned buffers, first_pass or key_bytes out of range, or
+ * parameters whose partition tile cannot hold a fused tile; LEYENDA_ETOOBIG
+ * for n > LEYENDA_MAX_RECORDS; LEYENDA_ENOMEM if the workspace cannot be
+ * allocated. */
+int leyenda_debug_first_pass(const void *records_dev, uint64_t n, uint32_t first_pass, uint32_t key_bytes,
+                             uint64_t *hi_dev, uint64_t *lo_dev, uint32_t *count_dev, void *rec_out_dev,
+                             void *stream);
 
 #ifdef __cplusplus
 }

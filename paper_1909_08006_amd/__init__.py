@@ -80,6 +80,7 @@ def load():
         "leyenda_sort_keyed": ([vp, u64, ctypes.c_uint32, vp, vp], i32),
         "leyenda_workspace_bytes": ([u64], u64),
         "leyenda_sort_parts": ([u64], ctypes.c_uint32),
+        "leyenda_first_pass": ([u64], ctypes.c_uint32),
         "leyenda_sort_runs": ([vp, u64, u64, vp, P64, u64, P64, vp], i32),
         "leyenda_merge": ([vp, P64, u64, vp, u64, vp], i32),
         "leyenda_sort_external_keys": ([vp, u64, u64, vp, vp], i32),
@@ -94,6 +95,7 @@ def load():
         "leyenda_release_workspaces": ([], i32),
         "leyenda_debug_extract": ([vp, u64, ctypes.c_uint32, vp, vp, vp, vp], i32),
         "leyenda_debug_gather": ([vp, u64, vp, u64, vp, vp], i32),
+        "leyenda_debug_first_pass": ([vp, u64, ctypes.c_uint32, ctypes.c_uint32, vp, vp, vp, vp, vp], i32),
         "leyenda_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)], i32),
         "leyenda_server_submit": ([vp, vp, u64, u64], i32),
         "leyenda_server_poll": ([vp, ctypes.POINTER(Done), u64, P64, ctypes.c_double], i32),
@@ -191,6 +193,13 @@ def sort_parts(n: int) -> int:
     """Output parts a sort of n records runs in (local sorts and gathers are
     launched once per part; the gathers overlap later parts' local sorts)."""
     return int(load().leyenda_sort_parts(n))
+
+
+def first_pass(n: int) -> int:
+    """First pass a sort of n records takes under the current parameters
+    (0: extraction then partition; 1: one fused pass; 2: fused with the
+    record copy)."""
+    return int(load().leyenda_first_pass(n))
 
 
 def plan_runs(n: int, budget_bytes: int) -> tuple[int, int]:
@@ -431,6 +440,25 @@ def debug_extract(records, key_bytes: int = KEY_BYTES, stream=None):
     _check(load().leyenda_debug_extract(records.data_ptr(), n, key_bytes, hi.data_ptr(), lo.data_ptr(),
                                         hist.data_ptr(), _stream_ptr(stream)), "leyenda_debug_extract")
     return hi, lo, hist
+
+
+def debug_first_pass(records, first_pass: int = 1, key_bytes: int = KEY_BYTES, stream=None):
+    """(hi, lo, count, recs) of the sort's fused first pass: the level-0 buckets
+    copied out in bucket order (int64 tuple words), the 256 bucket counts
+    (int32) and, for first_pass 2, the records of the record pool in the same
+    order (else None)."""
+    import torch
+    n = _nrec(records)
+    dev = records.device
+    hi = torch.empty(n, dtype=torch.int64, device=dev)
+    lo = torch.empty(n, dtype=torch.int64, device=dev)
+    count = torch.empty(256, dtype=torch.int32, device=dev)
+    recs = torch.empty((n, RECORD_BYTES), dtype=torch.uint8, device=dev) if first_pass == 2 else None
+    _check(load().leyenda_debug_first_pass(records.data_ptr(), n, first_pass, key_bytes, hi.data_ptr(),
+                                           lo.data_ptr(), count.data_ptr(),
+                                           recs.data_ptr() if recs is not None else None, _stream_ptr(stream)),
+           "leyenda_debug_first_pass")
+    return hi, lo, count, recs
 
 
 def debug_gather(records, idx, stream=None):

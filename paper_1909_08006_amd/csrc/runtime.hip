@@ -40,7 +40,7 @@ int hip_fail(hipError_t e, const char *what) {
 // parameters
 
 static std::mutex g_param_mu;
-static leyenda_params g_params = {8, 32, 2048, 128, 2048, 1024, 512, kFirstSplit};
+static leyenda_params g_params = {8, 32, 2048, 128, 2048, 1024, 512, kFirstFused};
 
 leyenda_params current_params() {
     std::lock_guard<std::mutex> lk(g_param_mu);
@@ -91,8 +91,12 @@ static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 Layout plan_layout(uint64_t n, uint32_t reqs, const Tune &t, uint32_t first_pass) {
     Layout L{};
     L.n = n;
-    const uint64_t segs = std::max<uint64_t>(reqs, n / ((uint64_t)t.big + 1)) + 1;
-    const uint64_t tiles = (n + t.tile - 1) / t.tile + segs + reqs;
+    // a bucket gets a device-wide pass only above the big threshold, except the
+    // level-1 buckets of a fused first pass, which all do (up to 256, each with
+    // a partly filled last tile)
+    const uint64_t fused_extra = first_pass != kFirstSplit ? (uint64_t)kRadix : 0;
+    const uint64_t segs = std::max<uint64_t>(reqs, n / ((uint64_t)t.big + 1)) + 1 + fused_extra;
+    const uint64_t tiles = (n + t.tile - 1) / t.tile + segs + reqs + fused_extra;
     const uint64_t tasks = 3 * (n / kLocalCap) + 4ull * (levels_for((int)t.digit) + 1) * segs + reqs + 64;
     L.max_seg = (uint32_t)std::min<uint64_t>(segs, 0xFFFFFFFFull);
     L.max_tiles = (uint32_t)std::min<uint64_t>(tiles, 0xFFFFFFFFull);
@@ -687,6 +691,8 @@ extern "C" int leyenda_sort_noalloc(const void *records_dev, uint64_t n, void *o
 
 extern "C" uint32_t leyenda_sort_parts(uint64_t n) { return parts_for(n); }
 
+extern "C" uint32_t leyenda_first_pass(uint64_t n) { return first_pass_for(n, tune_of(current_params()), false); }
+
 extern "C" uint64_t leyenda_workspace_bytes(uint64_t n) {
     const Tune t = tune_of(current_params());
     return plan_layout(n, 1, t, first_pass_for(n, t, false)).total;
@@ -839,6 +845,80 @@ extern "C" int leyenda_debug_extract(const void *records_dev, uint64_t n, uint32
         e = hipGetLastError();
     }
     return e == hipSuccess ? LEYENDA_OK : hip_fail(e, "extract kernel");
+}
+
+namespace ley {
+
+// The level-0 buckets a fused first pass left in its chunk pool, copied out in
+// bucket order (bucket d at the sum of the counts before it, positions in
+// order), with each bucket's count and, for the record copy, its records.
+__global__ __launch_bounds__(kWG) void k_flatten0(Work w, Tune tu, uint64_t *hi, uint64_t *lo, uint32_t *count,
+                                                  uint8_t *rec_out) {
+    const uint32_t ntl = min(w.ctl->ntiles[1], w.max_tiles);
+    const uint32_t nseg = min(w.ctl->nseg[1], w.max_seg);
+    const uint32_t C = tu.tile;
+    for (uint32_t t = blockIdx.x; t < ntl; t += gridDim.x) {
+        const uint32_t s = w.tile_seg[1][t];
+        if (s >= nseg) continue;
+        const Seg sg = w.segs[1][s];
+        const uint32_t k = t - sg.first_tile, c = w.tsrc[t];
+        if (sg.buf != 2 || k >= sg.ntiles || c >= w.max_chunks || sg.start + sg.count > w.n) continue;
+        const uint32_t nvalid = min(C, sg.count - k * C);
+        const uint64_t src = (uint64_t)c * C, dst = sg.start + (uint64_t)k * C;
+        if (k == 0 && threadIdx.x == 0) count[(uint32_t)(w.H[2][src] >> (64 - tu.digit))] = sg.count;
+        for (uint32_t q = threadIdx.x; q < nvalid; q += kWG) {
+            hi[dst + q] = w.H[2][src + q];
+            lo[dst + q] = w.L[2][src + q];
+        }
+        if (rec_out && w.rpool)
+            for (uint64_t b = threadIdx.x; b < (uint64_t)nvalid * kRec; b += kWG)
+                rec_out[dst * kRec + b] = w.rpool[src * kRec + b];
+    }
+}
+
+}  // namespace ley
+
+extern "C" int leyenda_debug_first_pass(const void *records_dev, uint64_t n, uint32_t first_pass, uint32_t key_bytes,
+                                        uint64_t *hi_dev, uint64_t *lo_dev, uint32_t *count_dev, void *rec_out_dev,
+                                        void *stream) {
+    if (n == 0) return LEYENDA_OK;
+    if (n > LEYENDA_MAX_RECORDS) return fail(LEYENDA_ETOOBIG, "leyenda_debug_first_pass: too many records");
+    if (first_pass != kFirstFused && first_pass != kFirstRecords)
+        return fail(LEYENDA_EINVAL, "leyenda_debug_first_pass: first_pass %u is not 1 or 2", first_pass);
+    if (key_bytes < 1 || key_bytes > kKeyBytes)
+        return fail(LEYENDA_EINVAL, "leyenda_debug_first_pass: key_bytes %u outside 1..10", key_bytes);
+    if (!records_dev || !hi_dev || !lo_dev || !count_dev || (first_pass == kFirstRecords && !rec_out_dev))
+        return fail(LEYENDA_EINVAL, "leyenda_debug_first_pass: NULL");
+    if ((reinterpret_cast<uintptr_t>(records_dev) & 3u) || (reinterpret_cast<uintptr_t>(hi_dev) & 7u) ||
+        (reinterpret_cast<uintptr_t>(lo_dev) & 7u) || (reinterpret_cast<uintptr_t>(count_dev) & 3u))
+        return fail(LEYENDA_EINVAL, "leyenda_debug_first_pass: misaligned buffer");
+    const Tune t = tune_of(current_params());
+    const Layout L = plan_layout(n, 1, t, first_pass);
+    if (fuse_tile(first_pass) > t.tile || (n + fuse_tile(first_pass) - 1) / fuse_tile(first_pass) > L.max_tiles ||
+        (first_pass == kFirstRecords && (uint64_t)L.max_chunks * t.tile >= 0xFFFFFFFFull))
+        return fail(LEYENDA_EINVAL, "leyenda_debug_first_pass: the parameters do not allow first pass %u", first_pass);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *ws = nullptr;
+    int rc = get_workspace(s, L.total, &ws);
+    if (rc) return rc;
+    remember_layout(s, L);
+    Work w = bind_layout(L, ws);
+    apply_key_mask(w, key_bytes);
+    const uint32_t tiles0 = (uint32_t)((n + t.tile - 1) / t.tile);
+    k_setup_single<<<1, 1, 0, s>>>(w.reqs, w.hdr, static_cast<const uint8_t *>(records_dev), nullptr, n, tiles0);
+    // the sort's own first pass, launched as the sort launches it, and nothing after
+    Stage st;
+    st.first = first_pass;
+    st.lev_end = 1;
+    st.tail = false;
+    hipError_t e = launch_sort_core(w, t, 1, tiles0, s, device_cus(), nullptr, st);
+    if (e == hipSuccess) e = hipMemsetAsync(count_dev, 0, kRadix * 4, s);
+    if (e == hipSuccess) {
+        k_flatten0<<<dim3(device_cus() * 4), dim3(kWG), 0, s>>>(w, t, hi_dev, lo_dev, count_dev,
+                                                               static_cast<uint8_t *>(rec_out_dev));
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? LEYENDA_OK : hip_fail(e, "first pass kernels");
 }
 
 extern "C" int leyenda_debug_gather(const void *records_dev, uint64_t n_records, const uint32_t *idx_dev,

@@ -642,6 +642,10 @@ __device__ __forceinline__ uint32_t fuse_chunk_take(const Work &w) {
     return c;
 }
 
+// 12 bytes at a 4-byte aligned address (a record's first three dwords in one load)
+typedef uint32_t u32x3a __attribute__((ext_vector_type(3), aligned(4)));
+typedef const __attribute__((address_space(1))) u32x3a gu32x3;
+
 template <int FWG, int FI, bool RECORDS>
 __global__ __launch_bounds__(FWG, 1) void k_fuse0(Work w, Tune tu) {
     constexpr int FT = FWG * FI;
@@ -689,10 +693,9 @@ __global__ __launch_bounds__(FWG, 1) void k_fuse0(Work w, Tune tu) {
                 const gu32 *p = (const gu32 *)(rq.in + (local0 + qc) * kRec);
                 if (RECORDS) {  // the record is copied below: keep its lines in the caches
                     a[u] = p[0]; b[u] = p[1]; c[u] = p[2];
-                } else {
-                    a[u] = __builtin_nontemporal_load(p);
-                    b[u] = __builtin_nontemporal_load(p + 1);
-                    c[u] = __builtin_nontemporal_load(p + 2);
+                } else {  // each line is read once here: non-temporal
+                    const u32x3a v = __builtin_nontemporal_load((gu32x3 *)p);
+                    a[u] = v.x; b[u] = v.y; c[u] = v.z;
                 }
             }
 #pragma unroll
@@ -828,8 +831,9 @@ __global__ __launch_bounds__(FWG, 1) void k_fuse0(Work w, Tune tu) {
                 uint64_t ll = sL[q];
                 if (RECORDS) ll = (ll & ~0xFFFFFFFFull) | v;
                 if (ch < w.max_chunks && slot < pool_keys) {
-                    PH[slot] = hh;
-                    PL[slot] = ll;
+                    // the pool is read by the next level's passes, far beyond the caches
+                    __builtin_nontemporal_store(hh, PH + slot);
+                    __builtin_nontemporal_store(ll, PL + slot);
                     if (RECORDS) sP[q] = (uint32_t)slot;
                 } else {
                     atomicOr(&w.ctl->guard, 512u);
@@ -1767,6 +1771,7 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
         k_init<<<dim3(1), dim3(kWG), 0, s>>>(w);
         k_fzero<<<dim3(cus * 4), dim3(kWG), 0, s>>>(w.status, nft * kRadix, w.ctab,
                                                     (uint64_t)kRadix * w.ctab_stride);
+        // one workgroup per CU (the staging takes most of the LDS); tiles from a counter
         if (st.first == kFirstRecords)
             k_fuse0<kFuseWG, fuse_items(kFirstRecords), true><<<dim3(cus), dim3(kFuseWG), 0, s>>>(w, t);
         else

@@ -11,7 +11,7 @@ import pytest
 
 import datagen
 import oracle
-from tests.test_gpu_sort import assert_same, pattern, run_sort
+from tests.test_gpu_sort import _want_tuples, assert_same, pattern, run_sort
 
 pytestmark = pytest.mark.gpu
 
@@ -98,3 +98,38 @@ def test_first_pass_keyed(gpu, key_bytes):
 
     for fp in (1, 2):
         assert_same(_with_params(gpu, dict(first_pass=fp), body), want, f"K={key_bytes} first_pass={fp}")
+
+
+@pytest.mark.parametrize("first_pass,key_bytes,digit_bits,n", [
+    (1, 10, 8, 3 * 8192 + 77), (1, 10, 8, 200_003), (2, 10, 8, 200_003), (1, 4, 8, 100_000),
+    (1, 9, 5, 150_001), (2, 10, 6, 90_001), (2, 3, 8, 70_001), (1, 10, 8, 1), (2, 10, 4, 5)])
+def test_first_pass_step(gpu, first_pass, key_bytes, digit_bits, n):
+    """The fused pass alone (as the sort launches it): bucket d holds the
+    tuples of the records whose leading digit is d, in input order, i.e. the
+    tuples stably sorted by that digit; with the record copy the records come
+    in the same order and a tuple carries its position inside its bucket.  A
+    third of the records share a 3-byte prefix, so one bucket spans many
+    chunks and most tiles' runs start inside a chunk another tile took."""
+    import torch
+    rec = datagen.uniform(n, 33)
+    rec[: n // 3, :3] = rec[0, :3]
+
+    def body():
+        out = gpu.debug_first_pass(torch.from_numpy(rec).cuda(), first_pass, key_bytes)
+        torch.cuda.synchronize()
+        return [None if x is None else x.cpu().numpy() for x in out]
+
+    hi, lo, count, recs = _with_params(gpu, dict(digit_bits=digit_bits), body)
+    want_hi, want_lo = _want_tuples(rec, key_bytes)
+    lead = (want_hi >> np.uint64(64 - digit_bits)).astype(np.int64)
+    order = np.argsort(lead, kind="stable")
+    want_count = np.bincount(lead, minlength=256)
+    np.testing.assert_array_equal(count, want_count)
+    np.testing.assert_array_equal(hi.view(np.uint64), want_hi[order])
+    if first_pass == 1:
+        np.testing.assert_array_equal(lo.view(np.uint64), want_lo[order])
+    else:
+        base = np.concatenate([[0], np.cumsum(want_count)[:-1]])
+        pos = (np.arange(n) - base[lead[order]]).astype(np.uint64)
+        np.testing.assert_array_equal(lo.view(np.uint64), (want_lo[order] & np.uint64(0xFFFF00000000)) | pos)
+        np.testing.assert_array_equal(recs, rec[order])

@@ -46,9 +46,10 @@ def test_status_strings_and_param_checks():
     p = ley.get_params()
     assert p["digit_bits"] == 8 and p["local_capacity"] == 2048 and p["scatter_threads"] == 1024
     assert p["local_threads"] == 512 and p["tile_items"] == 32 and p["tiny_threshold"] == 128
+    assert p["first_pass"] == 1
     for bad in [dict(tile_items=3), dict(big_threshold=0), dict(big_threshold=4096), dict(tiny_threshold=0),
                 dict(tiny_threshold=257), dict(digit_bits=3), dict(digit_bits=9), dict(digit_bits=16),
-                dict(scatter_threads=384),
+                dict(scatter_threads=384), dict(first_pass=3),
                 dict(local_threads=128)]:
         with pytest.raises(ley.LeyendaError):
             ley.set_params(**bad)
@@ -123,3 +124,26 @@ def test_keyed_sort_argument_checks():
     assert lib.leyenda_sort_keyed(None, 10, 20, None, None) == einval  # NULL buffers
     assert lib.leyenda_sort_keyed(ctypes.c_void_p(4096), 10, 20, ctypes.c_void_p(4098), None) == einval  # misaligned
     assert lib.leyenda_sort_keyed(ctypes.c_void_p(4096), 10, 20, ctypes.c_void_p(4096 + 500), None) == einval  # overlap
+
+
+def test_first_pass_rule():
+    """The fused first passes run only for sorts split into output parts whose
+    partition tile holds a fused tile (8,192 keys; 4,096 with the record copy)."""
+    import paper_1909_08006_amd as ley
+    old = ley.get_params()
+    try:
+        ley.set_params(first_pass=1, tile_items=32)
+        assert [ley.first_pass(n) for n in (1000, 8 * 2**20 - 1, 8 * 2**20, 10**8)] == [0, 0, 1, 1]
+        ley.set_params(first_pass=1, tile_items=16)
+        assert ley.first_pass(10**8) == 0
+        ley.set_params(first_pass=2, tile_items=16)
+        assert ley.first_pass(10**8) == 2
+        ley.set_params(first_pass=2, tile_items=8)
+        assert ley.first_pass(10**8) == 0
+        ley.set_params(first_pass=0, tile_items=32)
+        assert ley.first_pass(10**8) == 0
+        import pytest
+        with pytest.raises(ley.LeyendaError):
+            ley.set_params(first_pass=3)
+    finally:
+        ley.set_params(**old)
