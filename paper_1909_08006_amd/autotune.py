@@ -3,8 +3,9 @@
 Sweeps the partition digit width (4..8 bits: 2^digit_bits buckets per level
 of Algorithm 1), the partition tile (keys per thread), the big-bucket
 threshold (Algorithm 1's bigBucketThreshold: buckets above it get another
-device-wide pass) and the radix-vs-comparison cutoff inside the local sort
-(tinyBucketThreshold), times each candidate on the GPU with HIP events on a
+device-wide pass), the radix-vs-comparison cutoff inside the local sort
+(tinyBucketThreshold), the workgroup shapes and the first pass (separate
+extraction and partition, or one fused pass), times each candidate on the GPU with HIP events on a
 seeded workload, checks that every candidate returns exactly the bytes of the
 default parameters (they may change speed only), and writes the fastest set
 as a flat JSON object that ``leyenda_load_params`` reads.
@@ -31,6 +32,7 @@ DEFAULT_SPACE = {
     "tiny_threshold": [32, 64, 128, 192],
     "scatter_threads": [512, 1024],
     "local_threads": [256, 512],
+    "first_pass": [0, 1],
 }
 
 
