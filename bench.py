@@ -456,6 +456,8 @@ def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9
     # keys-only: 200 B/record up (the input read once in order, then every
     # record again by the gather) and 100 B/record down
     keys_bound = max(n * 200 / (rates["h2d"] * 1e9), n * 100 / (rates["d2h"] * 1e9))
+    duplex = rates["both_ways"] > 1.2 * max(rates["h2d"], rates["d2h"])
+    duplex_bound = n * 400 / (rates["both_ways"] * 1e9) if duplex else None
     if "t_runs_s" in pinned:
         pinned["pcie_frac"] = round(both_bound / (pinned["t_runs_s"] + pinned["t_merge_s"]), 3)
         if keys_skip is None:
@@ -470,7 +472,12 @@ def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9
             "gbs_records_end_to_end_first_touch": round(n * 100 / (t_runs + t_merge[0]) / 1e9, 2),
             "pcie_measured_gbs": rates,
             "pcie_bound": {"bytes_per_record_each_way": 200, "bound_s_each_way_rates_overlapped": round(both_bound, 3),
-                           "frac": round(both_bound / (t_runs + t_merge[1]), 3)},
+                           "frac": round(both_bound / (t_runs + t_merge[1]), 3),
+                           # the same bytes at the rate both directions reached together
+                           # (only when the two copies did overlap: above 1.2x one way)
+                           "bound_s_both_ways_rate": round(duplex_bound, 3) if duplex_bound else None,
+                           "frac_both_ways_rate": round(duplex_bound / (t_runs + t_merge[1]), 3)
+                           if duplex_bound else None},
             "sampled_order_ok": ok,
             "keys_only": {"skipped": keys_skip} if keys_skip is not None else
                          {"t_s": round(t_keys, 3), "gbs_records_end_to_end": round(n * 100 / t_keys / 1e9, 2),

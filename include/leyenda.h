@@ -94,12 +94,12 @@ uint64_t leyenda_noalloc_max_records(void);
  * prefix sort with the prefix bytes past the key ignored.  key_bytes > 10: the
  * prefix sort, then rounds over the runs of output records whose leading bytes
  * tie, each round ordering every run by its next six key bytes with one
- * stable sort of (run number, next bytes, position) entries and permuting the
- * runs' records to match; rounds end when no tie is left or the key is used
- * up.  Buffers and errors as leyenda_sort, plus LEYENDA_EINVAL for key_bytes
- * outside 1..100 and LEYENDA_ENOMEM when the rounds' scratch (216 bytes per
- * record inside a tie run, plus one byte per record and 24 bytes per 1,024
- * records) cannot be allocated.  With key_bytes > 10 the call returns after the stream has
+ * sort of (run number + next bytes, entry number) key-pointer tuples and
+ * permuting the runs' records to match; rounds end when no tie is left or the
+ * key is used up.  Buffers and errors as leyenda_sort, plus LEYENDA_EINVAL for
+ * key_bytes outside 1..100 and LEYENDA_ENOMEM when the rounds' scratch (about
+ * 180 bytes per record inside a tie run, plus one byte per record and 24
+ * bytes per 1,024 records, kept per stream between calls) cannot be allocated.  With key_bytes > 10 the call returns after the stream has
  * drained (it reads each round's tie count on the host). */
 int leyenda_sort_keyed(const void *records_dev, uint64_t n, uint32_t key_bytes, void *out_dev, void *stream);
 
@@ -129,7 +129,7 @@ uint32_t leyenda_sort_parts(uint64_t n);
  * partition.  host_records and host_runs must be pinned (hipHostMalloc,
  * leyenda_host_alloc, or torch pin_memory()): the copy engines read them and
  * the merge's co-rank kernel reads run keys from them directly.  host_out may
- * be pinned (written by the copy engine) or pageable (written through two
+ * be pinned (written by the copy engine) or pageable (written through
  * pinned bounce buffers by host threads).  Both calls are synchronous: they
  * return when the host output is complete.
  *
@@ -141,7 +141,7 @@ uint32_t leyenda_sort_parts(uint64_t n);
  *              host_records (in-place run formation).
  *   run_bounds: array of k_max + 1 entries; on success run r covers records
  *              [run_bounds[r], run_bounds[r+1]) and run_bounds[0] = 0,
- *              run_bounds[k] = n.
+ *              run_bounds[k] = n (the runs leyenda_plan_runs describes).
  *   k_out: number of runs written.
  *   Returns LEYENDA_EBUDGET if the budget cannot hold the smallest run plan or
  *   more than k_max runs would be needed.
@@ -188,8 +188,8 @@ int leyenda_host_alloc(uint64_t bytes, void **out);
 int leyenda_host_free(void *p);
 
 /* Run plan of leyenda_sort_runs for n records under a budget: records per run
- * and number of runs (host-only arithmetic, no GPU work).  LEYENDA_EBUDGET if
- * the budget is too small. */
+ * and number of runs (equal runs, the last possibly shorter; host-only
+ * arithmetic, no GPU work).  LEYENDA_EBUDGET if the budget is too small. */
 int leyenda_plan_runs(uint64_t n, uint64_t device_budget_bytes, uint64_t *run_records,
                       uint64_t *num_runs);
 

@@ -271,9 +271,13 @@ void *pinned_device_ptr(const void *p) {
     return a.devicePointer;
 }
 
+// Buffers a streaming loop cycles through (the merge uses three so the upload of
+// chunk c + 1 never waits for the download of chunk c - 1; the others two).
+constexpr int kPipeBufs = 3;
+
 struct Pipe {
     hipStream_t cs = nullptr, h2d = nullptr, d2h = nullptr;
-    hipEvent_t ev[3][2] = {};  // [h2d_done, compute_done, d2h_done][buffer]
+    hipEvent_t ev[3][kPipeBufs] = {};  // [h2d_done, compute_done, d2h_done][buffer]
     void *arena = nullptr;
     int init(hipStream_t caller) {
         hipError_t e;
@@ -390,8 +394,22 @@ struct Bounce {
 // (so upload, sort and download overlap) plus the sort's workspace.
 uint64_t run_bytes(uint64_t r, const Tune &t) { return 4 * a256(r * kRec) + plan_layout(r, 1, t).total + 4096; }
 
-int plan_runs_t(uint64_t n, uint64_t budget, const Tune &t, uint64_t *R, uint64_t *K) {
-    if (n == 0) { *R = 0; *K = 0; return LEYENDA_OK; }
+// Boundaries of n records cut into equal pieces of at most `cap`.  (First and
+// last pieces of an eighth, to shorten the one-way head and tail of the
+// streaming loops, measured slower on the 60 GB workload: merge 2.03 against
+// 1.5-1.7 s, runs no faster.)
+std::vector<uint64_t> equal_bounds(uint64_t n, uint64_t cap) {
+    std::vector<uint64_t> b{0};
+    if (n == 0) return b;
+    const uint64_t k = (n + cap - 1) / cap, r = (n + k - 1) / k;
+    for (uint64_t o = r; o < n; o += r) b.push_back(o);
+    b.push_back(n);
+    return b;
+}
+
+int plan_runs_t(uint64_t n, uint64_t budget, const Tune &t, uint64_t *R, uint64_t *K,
+                std::vector<uint64_t> *bounds = nullptr) {
+    if (n == 0) { *R = 0; *K = 0; if (bounds) *bounds = {0}; return LEYENDA_OK; }
     uint64_t lo = 1, hi = std::min<uint64_t>(n, LEYENDA_MAX_RECORDS);
     if (run_bytes(1, t) > budget) return fail(LEYENDA_EBUDGET, "budget of %llu bytes is below one run's footprint",
                                               (unsigned long long)budget);
@@ -399,9 +417,12 @@ int plan_runs_t(uint64_t n, uint64_t budget, const Tune &t, uint64_t *R, uint64_
         const uint64_t m = lo + (hi - lo + 1) / 2;
         if (run_bytes(m, t) <= budget) lo = m; else hi = m - 1;
     }
-    const uint64_t k = (n + lo - 1) / lo;
-    *K = k;
-    *R = (n + k - 1) / k;  // equal runs
+    const std::vector<uint64_t> b = equal_bounds(n, lo);
+    uint64_t longest = 0;
+    for (size_t i = 0; i + 1 < b.size(); i++) longest = std::max(longest, b[i + 1] - b[i]);
+    *K = b.size() - 1;
+    *R = longest;
+    if (bounds) *bounds = b;
     return LEYENDA_OK;
 }
 
@@ -449,7 +470,8 @@ extern "C" int leyenda_sort_runs(const void *host_records, uint64_t n, uint64_t 
         return fail(LEYENDA_EINVAL, "leyenda_sort_runs: host buffers must be pinned (hipHostMalloc / pin_memory)");
     const Tune t = tune_of(current_params());
     uint64_t R = 0, K = 0;
-    int rc = plan_runs_t(n, device_budget_bytes, t, &R, &K);
+    std::vector<uint64_t> run_off;
+    int rc = plan_runs_t(n, device_budget_bytes, t, &R, &K, &run_off);
     if (rc) return rc;
     if (K > k_max) return fail(LEYENDA_EBUDGET, "leyenda_sort_runs: %llu runs needed, k_max is %llu",
                                (unsigned long long)K, (unsigned long long)k_max);
@@ -469,7 +491,7 @@ extern "C" int leyenda_sort_runs(const void *host_records, uint64_t n, uint64_t 
     if (e != hipSuccess) return hip_fail(e, "leyenda_sort_runs: guard word");
     for (uint64_t r = 0; r < K; r++) {
         const int b = (int)(r & 1);
-        const uint64_t off = r * R, len = std::min<uint64_t>(R, n - off);
+        const uint64_t off = run_off[r], len = run_off[r + 1] - run_off[r];
         run_bounds[r] = off;
         // upload after the sort that last read in[b]
         if (r >= 2) e = hipStreamWaitEvent(P.h2d, P.ev[1][b], 0);
@@ -529,7 +551,10 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
         return a256((k + 1) * 8) + a256(chunks * 8) + a256((chunks + 1) * k * 8) +
                a256(chunks * (rounds + 1) * ((k + 1) / 2 + 1) * sizeof(MergePair)) + 256;
     };
-    auto buf_bytes = [&](uint64_t m) -> uint64_t { return 4 * a256(m * kRec) + 4 * a256(m * 8); };
+    // three staging and three output buffers (records), two tuple buffer pairs
+    auto buf_bytes = [&](uint64_t m) -> uint64_t {
+        return 2 * kPipeBufs * a256(m * kRec) + 4 * a256(m * 8);
+    };
     // largest chunk whose buffers fit next to the tables its chunk count needs
     uint64_t lo = 0, tab = tables_for(1);
     for (int it = 0; it < 64; it++) {
@@ -544,8 +569,10 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
         tab = t2;
     }
     if (lo == 0) return fail(LEYENDA_EBUDGET, "leyenda_merge: budget too small");
-    const uint64_t nch = (n + lo - 1) / lo;
-    const uint64_t C = (n + nch - 1) / nch;  // equal chunks
+    const std::vector<uint64_t> cb = equal_bounds(n, lo);  // output chunks
+    const uint64_t nch = cb.size() - 1;
+    uint64_t C = 0;  // longest chunk (buffer size)
+    for (uint64_t c = 0; c < nch; c++) C = std::max(C, cb[c + 1] - cb[c]);
 
     Pipe P;
     int rc = P.init(static_cast<hipStream_t>(stream));
@@ -553,14 +580,17 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
     const size_t sb = a256(C * kRec), tb = a256(C * 8);
     const size_t n_tab = (size_t)(nch + 1) * k;
     const size_t pair_cap = (size_t)nch * (rounds + 1) * ((k + 1) / 2 + 1);
-    if ((rc = P.alloc(4 * sb + 4 * tb + tables_for(nch)))) return rc;
+    if ((rc = P.alloc(2 * kPipeBufs * sb + 4 * tb + tables_for(nch)))) return rc;
     char *base = static_cast<char *>(P.arena);
-    uint8_t *stage[2] = {reinterpret_cast<uint8_t *>(base), reinterpret_cast<uint8_t *>(base + sb)};
-    uint8_t *outb[2] = {reinterpret_cast<uint8_t *>(base + 2 * sb), reinterpret_cast<uint8_t *>(base + 3 * sb)};
-    uint64_t *TH[2] = {reinterpret_cast<uint64_t *>(base + 4 * sb), reinterpret_cast<uint64_t *>(base + 4 * sb + tb)};
-    uint64_t *TL[2] = {reinterpret_cast<uint64_t *>(base + 4 * sb + 2 * tb),
-                       reinterpret_cast<uint64_t *>(base + 4 * sb + 3 * tb)};
-    char *tp = base + 4 * sb + 4 * tb;
+    uint8_t *stage[kPipeBufs], *outb[kPipeBufs];
+    for (int i = 0; i < kPipeBufs; i++) {
+        stage[i] = reinterpret_cast<uint8_t *>(base + i * sb);
+        outb[i] = reinterpret_cast<uint8_t *>(base + (kPipeBufs + i) * sb);
+    }
+    char *const tbase = base + 2 * kPipeBufs * sb;
+    uint64_t *TH[2] = {reinterpret_cast<uint64_t *>(tbase), reinterpret_cast<uint64_t *>(tbase + tb)};
+    uint64_t *TL[2] = {reinterpret_cast<uint64_t *>(tbase + 2 * tb), reinterpret_cast<uint64_t *>(tbase + 3 * tb)};
+    char *tp = tbase + 4 * tb;
     uint64_t *d_off = reinterpret_cast<uint64_t *>(tp); tp += a256((k + 1) * 8);
     uint64_t *d_tgt = reinterpret_cast<uint64_t *>(tp); tp += a256(nch * 8);
     uint64_t *d_split = reinterpret_cast<uint64_t *>(tp); tp += a256(n_tab * 8);
@@ -574,7 +604,7 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
     if (e != hipSuccess) return hip_fail(e, "leyenda_merge: error word");
     if (nch > 1) {
         std::vector<uint64_t> tgt(nch - 1);
-        for (uint64_t c = 1; c < nch; c++) tgt[c - 1] = c * C;
+        for (uint64_t c = 1; c < nch; c++) tgt[c - 1] = cb[c];
         e = hipMemcpyAsync(d_off, run_bounds, (k + 1) * 8, hipMemcpyHostToDevice, P.cs);
         if (e == hipSuccess) e = hipMemcpyAsync(d_tgt, tgt.data(), (nch - 1) * 8, hipMemcpyHostToDevice, P.cs);
         if (e != hipSuccess) return hip_fail(e, "leyenda_merge: tables");
@@ -595,7 +625,7 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
                     return fail(LEYENDA_EINTERNAL, "leyenda_merge: co-rank out of order");
                 s += a;
             }
-            if (s != c * C) return fail(LEYENDA_EINTERNAL, "leyenda_merge: co-rank sums to the wrong rank");
+            if (s != cb[c]) return fail(LEYENDA_EINTERNAL, "leyenda_merge: co-rank sums to the wrong rank");
         }
     }
 
@@ -647,59 +677,68 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
         if (e != hipSuccess) return hip_fail(e, "leyenda_merge: pair table");
     }
 
-    // 3. stream the chunks: upload slices | merge + gather | download
+    // 3. stream the chunks: upload slices | merge + gather | download, over
+    //    three buffers.  A pageable output drains through the host (blocking
+    //    this thread) two chunks behind: while chunk c - 2 drains, the uploads
+    //    of chunks c - 1 and c are already queued, so the host-to-device copies
+    //    never wait for a drain to return, and chunk c's buffers were freed by
+    //    the drain of chunk c - 3 one step earlier.
     const uint8_t *runs_h = static_cast<const uint8_t *>(host_runs);
     uint8_t *out_h = static_cast<uint8_t *>(host_out);
     const int cus = device_cus();
+    constexpr uint64_t kLag = kPipeBufs - 1;
     Bounce bounce;
     if (!direct_out && (rc = bounce.init())) return rc;
-    uint64_t prev_first = 0, prev_len = 0;
-    for (uint64_t c = 0; c < nch; c++) {
-        const int b = (int)(c & 1);
-        const uint64_t out_first = c * C;
-        uint64_t clen = 0;
-        for (uint64_t i = 0; i < k; i++) clen += slice_len[c][i];
-        if (c >= 2) e = hipStreamWaitEvent(P.h2d, P.ev[1][b], 0);
-        for (uint64_t i = 0; i < k && e == hipSuccess; i++) {
-            const uint64_t len = slice_len[c][i];
-            if (!len) continue;
-            e = hipMemcpyAsync(stage[b] + slice_off[c][i] * kRec, runs_h + (run_bounds[i] + split[c * k + i]) * kRec,
-                               len * kRec, hipMemcpyHostToDevice, P.h2d);
-        }
-        if (e == hipSuccess) e = hipEventRecord(P.ev[0][b], P.h2d);
-        if (e == hipSuccess) e = hipStreamWaitEvent(P.cs, P.ev[0][b], 0);
-        if (e == hipSuccess && c >= 2 && direct_out) e = hipStreamWaitEvent(P.cs, P.ev[2][b], 0);
-        if (e != hipSuccess) return hip_fail(e, "leyenda_merge: enqueue");
-        k_merge_extract<<<dim3((uint32_t)((clen + kWG - 1) / kWG)), dim3(kWG), 0, P.cs>>>(stage[b], clen, TH[0], TL[0]);
-        for (const Round &rd : plan[c]) {
-            const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>(rd.ntiles, (uint32_t)cus * 8));
-            k_merge_pairs<<<dim3(g), dim3(kWG), 0, P.cs>>>(d_pairs + rd.pair_first, rd.npairs, rd.ntiles,
-                                                            TH[rd.in_buf], TL[rd.in_buf], TH[rd.in_buf ^ 1],
-                                                            TL[rd.in_buf ^ 1]);
-        }
-        k_gather_lo<<<dim3((uint32_t)((clen + kWG - 1) / kWG)), dim3(kWG), 0, P.cs>>>(stage[b], TL[final_buf[c]],
-                                                                                   outb[b], clen, d_err);
-        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "merge kernels");
-        e = hipEventRecord(P.ev[1][b], P.cs);
-        if (e != hipSuccess) return hip_fail(e, "leyenda_merge: enqueue");
-        if (direct_out) {
-            e = hipStreamWaitEvent(P.d2h, P.ev[1][b], 0);
-            if (e == hipSuccess) e = hipMemcpyAsync(out_h + out_first * kRec, outb[b], clen * kRec,
-                                                    hipMemcpyDeviceToHost, P.d2h);
-            if (e == hipSuccess) e = hipEventRecord(P.ev[2][b], P.d2h);
+    std::vector<uint64_t> chunk_len(nch, 0);
+    for (uint64_t c = 0; c < nch; c++)
+        for (uint64_t i = 0; i < k; i++) chunk_len[c] += slice_len[c][i];
+    for (uint64_t c = 0; c < nch + (direct_out ? 0 : kLag); c++) {
+        if (c < nch) {
+            const int b = (int)(c % kPipeBufs);
+            const uint64_t out_first = cb[c], clen = chunk_len[c];
+            // the staging buffer's last reader was the merge of chunk c - 3
+            if (c >= (uint64_t)kPipeBufs) e = hipStreamWaitEvent(P.h2d, P.ev[1][b], 0);
+            for (uint64_t i = 0; i < k && e == hipSuccess; i++) {
+                const uint64_t len = slice_len[c][i];
+                if (!len) continue;
+                e = hipMemcpyAsync(stage[b] + slice_off[c][i] * kRec,
+                                   runs_h + (run_bounds[i] + split[c * k + i]) * kRec, len * kRec,
+                                   hipMemcpyHostToDevice, P.h2d);
+            }
+            if (e == hipSuccess) e = hipEventRecord(P.ev[0][b], P.h2d);
+            if (e == hipSuccess) e = hipStreamWaitEvent(P.cs, P.ev[0][b], 0);
+            // the output buffer's last reader: the download of chunk c - 3 (a
+            // pageable output's drain of it returned before this step)
+            if (e == hipSuccess && c >= (uint64_t)kPipeBufs && direct_out) e = hipStreamWaitEvent(P.cs, P.ev[2][b], 0);
             if (e != hipSuccess) return hip_fail(e, "leyenda_merge: enqueue");
-        } else {
-            // chunk c - 1 drains while chunk c uploads and merges
-            if (c >= 1 && (rc = bounce.drain(outb[b ^ 1], out_h + prev_first * kRec, prev_len * kRec,
-                                             P.ev[1][b ^ 1], P.d2h)))
+            k_merge_extract<<<dim3((uint32_t)((clen + kWG - 1) / kWG)), dim3(kWG), 0, P.cs>>>(stage[b], clen, TH[0],
+                                                                                             TL[0]);
+            for (const Round &rd : plan[c]) {
+                const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>(rd.ntiles, (uint32_t)cus * 8));
+                k_merge_pairs<<<dim3(g), dim3(kWG), 0, P.cs>>>(d_pairs + rd.pair_first, rd.npairs, rd.ntiles,
+                                                                TH[rd.in_buf], TL[rd.in_buf], TH[rd.in_buf ^ 1],
+                                                                TL[rd.in_buf ^ 1]);
+            }
+            k_gather_lo<<<dim3((uint32_t)((clen + kWG - 1) / kWG)), dim3(kWG), 0, P.cs>>>(stage[b], TL[final_buf[c]],
+                                                                                       outb[b], clen, d_err);
+            if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "merge kernels");
+            e = hipEventRecord(P.ev[1][b], P.cs);
+            if (e != hipSuccess) return hip_fail(e, "leyenda_merge: enqueue");
+            if (direct_out) {
+                e = hipStreamWaitEvent(P.d2h, P.ev[1][b], 0);
+                if (e == hipSuccess) e = hipMemcpyAsync(out_h + out_first * kRec, outb[b], clen * kRec,
+                                                        hipMemcpyDeviceToHost, P.d2h);
+                if (e == hipSuccess) e = hipEventRecord(P.ev[2][b], P.d2h);
+                if (e != hipSuccess) return hip_fail(e, "leyenda_merge: enqueue");
+            }
+        }
+        if (!direct_out && c >= kLag) {
+            const uint64_t d = c - kLag;
+            const int bd = (int)(d % kPipeBufs);
+            if ((rc = bounce.drain(outb[bd], out_h + cb[d] * kRec, chunk_len[d] * kRec, P.ev[1][bd], P.d2h)))
                 return rc;
-            prev_first = out_first;
-            prev_len = clen;
         }
     }
-    if (!direct_out && (rc = bounce.drain(outb[(nch - 1) & 1], out_h + prev_first * kRec, prev_len * kRec,
-                                          P.ev[1][(nch - 1) & 1], P.d2h)))
-        return rc;
     if ((rc = P.finish())) return rc;
     uint32_t err = 0;
     e = hipMemcpy(&err, d_err, 4, hipMemcpyDeviceToHost);

@@ -1,13 +1,11 @@
 // Host-side parallel copy used by the external sorts' pageable outputs.
 // Plain C++ (no HIP), so it also builds and is tested on its own.
 #pragma once
-#include <emmintrin.h>
 #include <sched.h>
 
 #include <algorithm>
 #include <condition_variable>
 #include <cstdint>
-#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <thread>
@@ -50,33 +48,11 @@ class CopyTeam {
         done_cv_.wait(lk, [this] { return left_ == 0; });
     }
 
-    // Copy with non-temporal (streaming) stores: the destination lines are not
-    // read first and do not displace the cache (the output is not read back here).
-    static void copy_stream(uint8_t *d, const uint8_t *s, size_t n) {
-        size_t i = 0;
-        while (i < n && (reinterpret_cast<uintptr_t>(d + i) & 15u)) { d[i] = s[i]; i++; }
-        for (; i + 64 <= n; i += 64) {
-            const __m128i x0 = _mm_loadu_si128(reinterpret_cast<const __m128i *>(s + i));
-            const __m128i x1 = _mm_loadu_si128(reinterpret_cast<const __m128i *>(s + i + 16));
-            const __m128i x2 = _mm_loadu_si128(reinterpret_cast<const __m128i *>(s + i + 32));
-            const __m128i x3 = _mm_loadu_si128(reinterpret_cast<const __m128i *>(s + i + 48));
-            _mm_stream_si128(reinterpret_cast<__m128i *>(d + i), x0);
-            _mm_stream_si128(reinterpret_cast<__m128i *>(d + i + 16), x1);
-            _mm_stream_si128(reinterpret_cast<__m128i *>(d + i + 32), x2);
-            _mm_stream_si128(reinterpret_cast<__m128i *>(d + i + 48), x3);
-        }
-        for (; i < n; i++) d[i] = s[i];
-        _mm_sfence();
-    }
-
   private:
     void part(unsigned t) {
         const size_t per = (bytes_ + n_ - 1) / n_ / 64 * 64 + 64;
         const size_t a = std::min(bytes_, t * per), b = std::min(bytes_, a + per);
-        if (a >= b) return;
-        static const bool nt = getenv("LEY_NT_COPY") != nullptr;
-        if (nt) copy_stream(dst_ + a, src_ + a, b - a);
-        else std::memcpy(dst_ + a, src_ + a, b - a);
+        if (a < b) std::memcpy(dst_ + a, src_ + a, b - a);
     }
     void work(unsigned t) {
         uint64_t seen = 0;
