@@ -158,6 +158,26 @@ int leyenda_sort_runs(const void *host_records, uint64_t n, uint64_t device_budg
 int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, uint64_t k, void *host_out,
                   uint64_t device_budget_bytes, void *stream);
 
+/* Runs + merge in one call (Section 3.2, "Overlapping Computation with I/O"):
+ * leyenda_sort_runs then leyenda_merge, except that the last run stays in
+ * device memory after its sort instead of being written to host_runs and read
+ * back for the merge: its download would have had nothing to overlap with,
+ * and its slices reach the merge by device copies.  The merge takes the rest of
+ * the run stage's device memory, so the whole call stays within
+ * device_budget_bytes.
+ *   host_records: n records in pinned host memory (read only unless aliased).
+ *   host_runs:    n records of pinned host memory for the runs (may equal
+ *                 host_records; the last run's range is left unwritten).
+ *   host_out:     n records of host memory, pinned or pageable, overlapping
+ *                 neither of the above.
+ * Output: the stable sort of the records by their 10-byte key, the same bytes
+ * as leyenda_sort.  Synchronous.  LEYENDA_EINVAL (NULL, misaligned,
+ * overlapping, unpinned input or runs), LEYENDA_EBUDGET (the budget holds no
+ * run, or more runs than the merge takes), LEYENDA_ENOMEM, LEYENDA_EHIP,
+ * LEYENDA_EINTERNAL (a device-side guard fired). */
+int leyenda_sort_external(const void *host_records, uint64_t n, uint64_t device_budget_bytes, void *host_runs,
+                          void *host_out, void *stream);
+
 /* Keys-only external sort (Section 3.2: key-pointer tuples extracted while
  * the input is read, sorted, then the records scattered by the sorted
  * tuples).  The input streams host -> device in chunks and every record's

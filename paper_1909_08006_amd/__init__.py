@@ -84,6 +84,7 @@ def load():
         "leyenda_sort_runs": ([vp, u64, u64, vp, P64, u64, P64, vp], i32),
         "leyenda_merge": ([vp, P64, u64, vp, u64, vp], i32),
         "leyenda_sort_external_keys": ([vp, u64, u64, vp, vp], i32),
+        "leyenda_sort_external": ([vp, u64, u64, vp, vp, vp], i32),
         "leyenda_plan_runs": ([u64, u64, P64, P64], i32),
         "leyenda_sort_batch": ([ctypes.POINTER(Segment), u64, vp], i32),
         "leyenda_get_params": ([ctypes.POINTER(Params)], i32),
@@ -260,6 +261,24 @@ def merge(host_runs, run_bounds: Sequence[int], budget_bytes: int, host_out=None
         raise ValueError("run_bounds must end at the record count")
     _check(load().leyenda_merge(host_runs.data_ptr(), b, k, host_out.data_ptr(), budget_bytes, _stream_ptr(stream)),
            "leyenda_merge")
+    return host_out
+
+
+def sort_external(host_records, budget_bytes: int, host_runs=None, host_out=None, stream=None):
+    """Runs + merge in one call (the last run stays on the device between the
+    two stages).  ``host_runs``: pinned scratch for the runs, by default
+    ``host_records`` itself (overwritten); ``host_out``: pinned or pageable (a
+    new pageable tensor by default).  Returns ``host_out``."""
+    import torch
+    n = _nrec(host_records)
+    if host_runs is None:
+        host_runs = host_records
+    if host_out is None:
+        host_out = torch.empty_like(host_records, pin_memory=False)
+    elif _nrec(host_out) != n or _nrec(host_runs) != n:
+        raise ValueError("host_runs and host_out must hold as many records as host_records")
+    _check(load().leyenda_sort_external(host_records.data_ptr(), n, budget_bytes, host_runs.data_ptr(),
+                                        host_out.data_ptr(), _stream_ptr(stream)), "leyenda_sort_external")
     return host_out
 
 

@@ -66,8 +66,16 @@ __device__ __forceinline__ bool tuple_less(const Key80 &a, uint32_t ra, uint64_t
 // search, and move lo (v below the boundary) or hi (v above it).  Every step
 // halves one interval, so it ends after at most sum(log2 len_i) + k steps.
 
+// Record m of run i: in the pinned runs, or (last non-null) for run k - 1 in
+// device memory.
+__device__ __forceinline__ const uint8_t *run_rec(const uint8_t *runs, const uint64_t *run_off, uint32_t k,
+                                                  const uint8_t *last, uint32_t i, uint64_t m) {
+    return (last && i + 1 == k) ? last + m * kRec : runs + (run_off[i] + m) * kRec;
+}
+
 __global__ __launch_bounds__(kWG) void k_corank(const uint8_t *runs, const uint64_t *run_off, uint32_t k,
-                                                const uint64_t *targets, uint64_t *splits, uint32_t *err) {
+                                                const uint8_t *last, const uint64_t *targets, uint64_t *splits,
+                                                uint32_t *err) {
     __shared__ uint64_t lo[kMaxRuns], hi[kMaxRuns];
     __shared__ unsigned long long red_w[kWaves];
     __shared__ uint32_t red_i[kWaves];
@@ -75,7 +83,6 @@ __global__ __launch_bounds__(kWG) void k_corank(const uint8_t *runs, const uint6
     __shared__ Key80 s_v;
     const uint32_t i = threadIdx.x, lane = i & 63, wv = i >> 6;
     const uint64_t b = targets[blockIdx.x];
-    const uint64_t off_i = i < k ? run_off[i] : 0;
     const uint64_t len_i = i < k ? run_off[i + 1] - run_off[i] : 0;
     lo[i] = 0;
     hi[i] = len_i;
@@ -101,7 +108,7 @@ __global__ __launch_bounds__(kWG) void k_corank(const uint8_t *runs, const uint6
             if (red_w[q] > bw || (red_w[q] == bw && red_i[q] < j)) { bw = red_w[q]; j = red_i[q]; }
         if (bw == 0 || step >= max_steps) break;
         const uint64_t mid = (lo[j] + hi[j]) >> 1;
-        if (i == 0) s_v = load_key(runs + (run_off[j] + mid) * kRec);
+        if (i == 0) s_v = load_key(run_rec(runs, run_off, k, last, j, mid));
         __syncthreads();
         const Key80 v = s_v;
         // records of run i below v, over the whole run
@@ -113,7 +120,7 @@ __global__ __launch_bounds__(kWG) void k_corank(const uint8_t *runs, const uint6
                 uint64_t a = 0, c = len_i;
                 while (a < c) {
                     const uint64_t m = (a + c) >> 1;
-                    const Key80 e = load_key(runs + (off_i + m) * kRec);
+                    const Key80 e = load_key(run_rec(runs, run_off, k, last, i, m));
                     if (tuple_less(e, i, m, v, j, mid)) a = m + 1; else c = m;
                 }
                 r = a;
@@ -520,30 +527,18 @@ extern "C" int leyenda_sort_runs(const void *host_records, uint64_t n, uint64_t 
     return LEYENDA_OK;
 }
 
-extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, uint64_t k, void *host_out,
-                             uint64_t device_budget_bytes, void *stream) {
-    if (!run_bounds) return fail(LEYENDA_EINVAL, "leyenda_merge: NULL run_bounds");
-    if (k == 0) return LEYENDA_OK;
-    if (k > (uint64_t)kMaxRuns) return fail(LEYENDA_EINVAL, "leyenda_merge: at most %d runs", kMaxRuns);
-    if (run_bounds[0] != 0) return fail(LEYENDA_EINVAL, "leyenda_merge: run_bounds[0] must be 0");
-    for (uint64_t i = 0; i < k; i++)
-        if (run_bounds[i + 1] < run_bounds[i]) return fail(LEYENDA_EINVAL, "leyenda_merge: run_bounds decrease");
-    const uint64_t n = run_bounds[k];
-    if (n == 0) return LEYENDA_OK;
-    if (!host_runs || !host_out) return fail(LEYENDA_EINVAL, "leyenda_merge: NULL buffer");
-    if ((reinterpret_cast<uintptr_t>(host_runs) | reinterpret_cast<uintptr_t>(host_out)) & 3u)
-        return fail(LEYENDA_EINVAL, "leyenda_merge: buffers must be 4-byte aligned");
-    if (overlaps(host_runs, n * kRec, host_out, n * kRec))
-        return fail(LEYENDA_EINVAL, "leyenda_merge: host_out overlaps host_runs");
-    const uint8_t *runs_dev = static_cast<const uint8_t *>(pinned_device_ptr(host_runs));
-    if (!runs_dev) return fail(LEYENDA_EINVAL, "leyenda_merge: host_runs must be pinned (hipHostMalloc / pin_memory)");
-    // pinned output: chunks go straight device -> host_out; pageable output:
-    // through two pinned bounce buffers drained by host copies
-    const bool direct_out = pinned_device_ptr(host_out) != nullptr;
-    for (uint64_t i = 0; i < k; i++)
-        if (run_bounds[i + 1] - run_bounds[i] > LEYENDA_MAX_RECORDS)
-            return fail(LEYENDA_ETOOBIG, "leyenda_merge: run %llu too long", (unsigned long long)i);
+namespace ley {
+namespace {
 
+// The merge of k sorted runs (validated by the caller) into host_out, on the
+// streams of P.  runs_dev is the device view of the pinned runs.  arena: device
+// memory of `budget` bytes to use (null: allocate `budget` at most).  last:
+// run k - 1 lives in device memory there (its records are not read from the
+// pinned runs).
+int merge_impl(Pipe &P, const uint8_t *runs_dev, const uint8_t *runs_h, const uint64_t *run_bounds, uint64_t k,
+               uint8_t *out_h, bool direct_out, uint64_t device_budget_bytes, char *arena, const uint8_t *last) {
+    const uint64_t n = run_bounds[k];
+    int rc = LEYENDA_OK;
     // chunk size from the budget: staging, output and tuple buffers plus the
     // tables (run offsets, boundaries, co-rank splits, merge pair lists)
     const uint32_t rounds = [&] { uint32_t r = 0; while ((1ull << r) < k) r++; return r; }();
@@ -574,14 +569,14 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
     uint64_t C = 0;  // longest chunk (buffer size)
     for (uint64_t c = 0; c < nch; c++) C = std::max(C, cb[c + 1] - cb[c]);
 
-    Pipe P;
-    int rc = P.init(static_cast<hipStream_t>(stream));
-    if (rc) return rc;
     const size_t sb = a256(C * kRec), tb = a256(C * 8);
     const size_t n_tab = (size_t)(nch + 1) * k;
     const size_t pair_cap = (size_t)nch * (rounds + 1) * ((k + 1) / 2 + 1);
-    if ((rc = P.alloc(2 * kPipeBufs * sb + 4 * tb + tables_for(nch)))) return rc;
-    char *base = static_cast<char *>(P.arena);
+    if (!arena) {
+        if ((rc = P.alloc(2 * kPipeBufs * sb + 4 * tb + tables_for(nch)))) return rc;
+        arena = static_cast<char *>(P.arena);
+    }
+    char *base = arena;
     uint8_t *stage[kPipeBufs], *outb[kPipeBufs];
     for (int i = 0; i < kPipeBufs; i++) {
         stage[i] = reinterpret_cast<uint8_t *>(base + i * sb);
@@ -608,8 +603,8 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
         e = hipMemcpyAsync(d_off, run_bounds, (k + 1) * 8, hipMemcpyHostToDevice, P.cs);
         if (e == hipSuccess) e = hipMemcpyAsync(d_tgt, tgt.data(), (nch - 1) * 8, hipMemcpyHostToDevice, P.cs);
         if (e != hipSuccess) return hip_fail(e, "leyenda_merge: tables");
-        k_corank<<<dim3((uint32_t)(nch - 1)), dim3(kWG), 0, P.cs>>>(runs_dev, d_off, (uint32_t)k, d_tgt, d_split,
-                                                                   d_err);
+        k_corank<<<dim3((uint32_t)(nch - 1)), dim3(kWG), 0, P.cs>>>(runs_dev, d_off, (uint32_t)k, last, d_tgt,
+                                                                   d_split, d_err);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "co-rank kernel");
         uint32_t err = 0;
         e = hipMemcpyAsync(split.data() + k, d_split, (nch - 1) * k * 8, hipMemcpyDeviceToHost, P.cs);
@@ -683,8 +678,6 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
     //    of chunks c - 1 and c are already queued, so the host-to-device copies
     //    never wait for a drain to return, and chunk c's buffers were freed by
     //    the drain of chunk c - 3 one step earlier.
-    const uint8_t *runs_h = static_cast<const uint8_t *>(host_runs);
-    uint8_t *out_h = static_cast<uint8_t *>(host_out);
     const int cus = device_cus();
     constexpr uint64_t kLag = kPipeBufs - 1;
     Bounce bounce;
@@ -701,9 +694,13 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
             for (uint64_t i = 0; i < k && e == hipSuccess; i++) {
                 const uint64_t len = slice_len[c][i];
                 if (!len) continue;
-                e = hipMemcpyAsync(stage[b] + slice_off[c][i] * kRec,
-                                   runs_h + (run_bounds[i] + split[c * k + i]) * kRec, len * kRec,
-                                   hipMemcpyHostToDevice, P.h2d);
+                if (last && i + 1 == k)  // the run held in device memory
+                    e = hipMemcpyAsync(stage[b] + slice_off[c][i] * kRec, last + split[c * k + i] * kRec, len * kRec,
+                                       hipMemcpyDeviceToDevice, P.h2d);
+                else
+                    e = hipMemcpyAsync(stage[b] + slice_off[c][i] * kRec,
+                                       runs_h + (run_bounds[i] + split[c * k + i]) * kRec, len * kRec,
+                                       hipMemcpyHostToDevice, P.h2d);
             }
             if (e == hipSuccess) e = hipEventRecord(P.ev[0][b], P.h2d);
             if (e == hipSuccess) e = hipStreamWaitEvent(P.cs, P.ev[0][b], 0);
@@ -745,6 +742,128 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
     if (e != hipSuccess) return hip_fail(e, "leyenda_merge: error word");
     if (err) return fail(LEYENDA_EINTERNAL, "leyenda_merge: a merged index fell outside its chunk (0x%x)", err);
     return LEYENDA_OK;
+}
+
+}  // namespace
+}  // namespace ley
+
+extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, uint64_t k, void *host_out,
+                             uint64_t device_budget_bytes, void *stream) {
+    if (!run_bounds) return fail(LEYENDA_EINVAL, "leyenda_merge: NULL run_bounds");
+    if (k == 0) return LEYENDA_OK;
+    if (k > (uint64_t)kMaxRuns) return fail(LEYENDA_EINVAL, "leyenda_merge: at most %d runs", kMaxRuns);
+    if (run_bounds[0] != 0) return fail(LEYENDA_EINVAL, "leyenda_merge: run_bounds[0] must be 0");
+    for (uint64_t i = 0; i < k; i++)
+        if (run_bounds[i + 1] < run_bounds[i]) return fail(LEYENDA_EINVAL, "leyenda_merge: run_bounds decrease");
+    const uint64_t n = run_bounds[k];
+    if (n == 0) return LEYENDA_OK;
+    if (!host_runs || !host_out) return fail(LEYENDA_EINVAL, "leyenda_merge: NULL buffer");
+    if ((reinterpret_cast<uintptr_t>(host_runs) | reinterpret_cast<uintptr_t>(host_out)) & 3u)
+        return fail(LEYENDA_EINVAL, "leyenda_merge: buffers must be 4-byte aligned");
+    if (overlaps(host_runs, n * kRec, host_out, n * kRec))
+        return fail(LEYENDA_EINVAL, "leyenda_merge: host_out overlaps host_runs");
+    const uint8_t *runs_dev = static_cast<const uint8_t *>(pinned_device_ptr(host_runs));
+    if (!runs_dev) return fail(LEYENDA_EINVAL, "leyenda_merge: host_runs must be pinned (hipHostMalloc / pin_memory)");
+    // pinned output: chunks go straight device -> host_out; pageable output:
+    // through two pinned bounce buffers drained by host copies
+    const bool direct_out = pinned_device_ptr(host_out) != nullptr;
+    for (uint64_t i = 0; i < k; i++)
+        if (run_bounds[i + 1] - run_bounds[i] > LEYENDA_MAX_RECORDS)
+            return fail(LEYENDA_ETOOBIG, "leyenda_merge: run %llu too long", (unsigned long long)i);
+    Pipe P;
+    int rc = P.init(static_cast<hipStream_t>(stream));
+    if (rc) return rc;
+    return merge_impl(P, runs_dev, static_cast<const uint8_t *>(host_runs), run_bounds, k,
+                      static_cast<uint8_t *>(host_out), direct_out, device_budget_bytes, nullptr, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Runs + merge in one call: the same two stages, except that the last run
+// stays in device memory after its sort instead of going to host_runs and
+// coming back for the merge (it is the one run whose download would have
+// nothing to overlap with, and its slices then reach the merge by device
+// copies).  The merge uses the rest of the run stage's device memory.
+
+extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint64_t device_budget_bytes,
+                                     void *host_runs, void *host_out, void *stream) {
+    if (n == 0) return LEYENDA_OK;
+    if (!host_records || !host_runs || !host_out) return fail(LEYENDA_EINVAL, "leyenda_sort_external: NULL buffer");
+    if ((reinterpret_cast<uintptr_t>(host_records) | reinterpret_cast<uintptr_t>(host_runs) |
+         reinterpret_cast<uintptr_t>(host_out)) & 3u)
+        return fail(LEYENDA_EINVAL, "leyenda_sort_external: buffers must be 4-byte aligned");
+    if (host_records != host_runs && overlaps(host_records, n * kRec, host_runs, n * kRec))
+        return fail(LEYENDA_EINVAL, "leyenda_sort_external: host_runs partly overlaps host_records");
+    if (overlaps(host_out, n * kRec, host_runs, n * kRec) || overlaps(host_out, n * kRec, host_records, n * kRec))
+        return fail(LEYENDA_EINVAL, "leyenda_sort_external: host_out overlaps the input or the runs");
+    const uint8_t *runs_dev = static_cast<const uint8_t *>(pinned_device_ptr(host_runs));
+    if (!pinned_device_ptr(host_records) || !runs_dev)
+        return fail(LEYENDA_EINVAL, "leyenda_sort_external: host_records and host_runs must be pinned");
+    const bool direct_out = pinned_device_ptr(host_out) != nullptr;
+    const Tune t = tune_of(current_params());
+    uint64_t R = 0, K = 0;
+    int rc = plan_runs_t(n, device_budget_bytes, t, &R, &K);
+    if (rc) return rc;
+    if (K > (uint64_t)kMaxRuns)
+        return fail(LEYENDA_EBUDGET, "leyenda_sort_external: %llu runs needed, the merge takes at most %d",
+                    (unsigned long long)K, kMaxRuns);
+    Pipe P;
+    if ((rc = P.init(static_cast<hipStream_t>(stream)))) return rc;
+    const size_t rb = a256(R * kRec);
+    const size_t ws_bytes = plan_layout(R, 1, t).total;
+    const size_t total = 4 * rb + ws_bytes + 256;
+    if ((rc = P.alloc(total))) return rc;
+    char *base = static_cast<char *>(P.arena);
+    // the output buffer the last run sorts into comes first, so the rest of the
+    // memory is one block for the merge
+    uint8_t *const keep = reinterpret_cast<uint8_t *>(base);
+    uint8_t *in[2] = {reinterpret_cast<uint8_t *>(base + rb), reinterpret_cast<uint8_t *>(base + 2 * rb)};
+    uint8_t *out[2] = {keep, reinterpret_cast<uint8_t *>(base + 3 * rb)};
+    void *ws = base + 4 * rb;
+    uint32_t *guard = reinterpret_cast<uint32_t *>(base + 4 * rb + a256(ws_bytes));
+    const uint8_t *src = static_cast<const uint8_t *>(host_records);
+    uint8_t *dst = static_cast<uint8_t *>(host_runs);
+    std::vector<uint64_t> bounds(K + 1, n);
+    hipError_t e = hipMemsetAsync(guard, 0, 4, P.cs);
+    if (e != hipSuccess) return hip_fail(e, "leyenda_sort_external: guard word");
+    for (uint64_t r = 0; r < K; r++) {
+        const int b = (int)((K - 1 - r) & 1);  // the last run sorts into out[0]
+        const uint64_t off = r * R, len = std::min<uint64_t>(R, n - off);
+        bounds[r] = off;
+        if (r >= 2) e = hipStreamWaitEvent(P.h2d, P.ev[1][b], 0);
+        if (e == hipSuccess) e = hipMemcpyAsync(in[b], src + off * kRec, len * kRec, hipMemcpyHostToDevice, P.h2d);
+        if (e == hipSuccess) e = hipEventRecord(P.ev[0][b], P.h2d);
+        if (e == hipSuccess) e = hipStreamWaitEvent(P.cs, P.ev[0][b], 0);
+        if (e == hipSuccess && r >= 2) e = hipStreamWaitEvent(P.cs, P.ev[2][b], 0);
+        if (e != hipSuccess) return hip_fail(e, "leyenda_sort_external: enqueue");
+        if ((rc = sort_device_ws(in[b], len, out[b], P.cs, t, ws))) return rc;
+        e = launch_guard_or(ws, len, t, guard, P.cs);
+        if (e == hipSuccess) e = hipEventRecord(P.ev[1][b], P.cs);
+        if (e == hipSuccess && r + 1 < K) {
+            e = hipStreamWaitEvent(P.d2h, P.ev[1][b], 0);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(dst + off * kRec, out[b], len * kRec, hipMemcpyDeviceToHost, P.d2h);
+            if (e == hipSuccess) e = hipEventRecord(P.ev[2][b], P.d2h);
+        }
+        if (e != hipSuccess) return hip_fail(e, "leyenda_sort_external: enqueue");
+    }
+    if ((rc = P.finish())) return rc;
+    uint32_t g = 0;
+    e = hipMemcpy(&g, guard, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "leyenda_sort_external: guard word");
+    if (g) return fail(LEYENDA_EINTERNAL, "leyenda_sort_external: a device-side guard fired in a run's sort (0x%x)", g);
+    uint8_t *out_h = static_cast<uint8_t *>(host_out);
+    if (K == 1) {  // one run: it is the output
+        if (direct_out) {
+            e = hipMemcpyAsync(out_h, keep, n * kRec, hipMemcpyDeviceToHost, P.d2h);
+            if (e != hipSuccess) return hip_fail(e, "leyenda_sort_external: download");
+            return P.finish();
+        }
+        Bounce bounce;
+        if ((rc = bounce.init())) return rc;
+        if ((rc = bounce.drain(keep, out_h, n * kRec, P.ev[1][0], P.d2h))) return rc;
+        return P.finish();
+    }
+    return merge_impl(P, runs_dev, dst, bounds.data(), K, out_h, direct_out, total - rb, base + rb, keep);
 }
 
 // ---------------------------------------------------------------------------

@@ -154,3 +154,52 @@ def test_keys_only_budget_and_errors(gpu):
     with pytest.raises(gpu.LeyendaError) as ei:  # pageable input: the gather reads it from the device
         gpu.sort_external_keys(torch.from_numpy(rec.reshape(-1).copy()), need)
     assert ei.value.status == -1
+
+
+# ---- runs + merge in one call, the last run kept on the device ----
+
+@pytest.mark.parametrize("runs,kind,in_place,pinned_out", [
+    (1, "uniform", True, False), (2, "ties", True, True), (3, "uniform", False, False),
+    (7, "ties", True, False), (10, "uniform", True, True), (23, "few", False, True)])
+def test_sort_external_matches_oracle(gpu, runs, kind, in_place, pinned_out):
+    """The last run's slices reach the merge by device copies and its keys are
+    read from device memory by the co-rank; ties straddle every run (the
+    resident run included), and with many runs the merge has many chunks."""
+    import torch
+    n = 150_001
+    if kind == "uniform":
+        rec = datagen.uniform(n, 90 + runs)
+    elif kind == "ties":
+        rec = datagen.skewed(n, 91 + runs, nvals=40, dup_frac=0.3)
+    else:
+        rec = datagen.uniform(n, 92)
+        rec[:, :10] = datagen.uniform(8, 93)[np.arange(n) % 8, :10]
+    host = pinned(rec)
+    budget = budget_for_runs(gpu, n, runs)
+    _, k = gpu.plan_runs(n, budget)
+    assert k <= runs
+    host_runs = None if in_place else torch.empty(n * 100, dtype=torch.uint8, pin_memory=True)
+    out = torch.empty(n * 100, dtype=torch.uint8, pin_memory=pinned_out)
+    gpu.sort_external(host, budget, host_runs=host_runs, host_out=out)
+    np.testing.assert_array_equal(out.numpy().reshape(n, 100), oracle.sort(rec))
+    if not in_place:
+        np.testing.assert_array_equal(host.numpy().reshape(n, 100), rec)  # the input is left as it was
+
+
+def test_sort_external_tiny_and_errors(gpu):
+    import torch
+    for n in (1, 2, 5, 2049):
+        rec = datagen.skewed(n, 95, nvals=4, dup_frac=0.5) if n > 2 else datagen.uniform(n, 95)
+        out = gpu.sort_external(pinned(rec), 64 << 20)
+        np.testing.assert_array_equal(out.numpy().reshape(n, 100), oracle.sort(rec))
+    rec = datagen.uniform(1000, 96)
+    with pytest.raises(gpu.LeyendaError) as ei:  # pageable input
+        gpu.sort_external(torch.from_numpy(rec.reshape(-1).copy()), 64 << 20)
+    assert ei.value.status == -1
+    with pytest.raises(gpu.LeyendaError) as ei:
+        gpu.sort_external(pinned(rec), 1000)  # below one run's footprint
+    assert ei.value.status == -3
+    h = pinned(rec)
+    with pytest.raises(gpu.LeyendaError) as ei:  # the output over the runs
+        gpu.sort_external(h, 64 << 20, host_runs=h, host_out=h)
+    assert ei.value.status == -1

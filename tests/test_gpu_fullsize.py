@@ -102,6 +102,33 @@ def test_external_60gb_30gb_budget(gpu):
 
 
 @pytest.mark.timeout(1500)
+def test_external_60gb_one_call(gpu):
+    """The same 60 GB workload through leyenda_sort_external (runs + merge, the
+    last run kept on the device), runs written over the input."""
+    import torch
+    n = 600_000_000
+    budget = 30 * 10**9
+    a = gpu.pinned_empty(n * 100)
+    datagen.fill_uniform(a.data_ptr(), n, datagen.SEED_EXTERNAL)
+    rec = a.numpy().reshape(n, 100)
+    h_in = oracle.multiset_hash(rec)
+    probes = rec[np.random.default_rng(5).integers(0, n, 32)].copy()
+    out = np.empty((n, 100), dtype=np.uint8)
+    t0 = time.perf_counter()
+    gpu.sort_external(a, budget, host_out=torch.from_numpy(out).view(-1))
+    dt = time.perf_counter() - t0
+    print(f"external 60 GB in one call: {dt:.2f} s ({n * 100 / dt / 1e9:.1f} GB/s of records)", flush=True)
+    assert oracle.first_unsorted(out) == -1
+    assert oracle.multiset_hash(out) == h_in
+    assert oracle.equal_neighbours(out) == 0
+    pos = oracle.count_less(out, probes)
+    for p, r in zip(pos, probes):
+        np.testing.assert_array_equal(out[int(p)], r)
+    del rec, out
+    gpu.pinned_free(a)
+
+
+@pytest.mark.timeout(1500)
 def test_external_60gb_keys_only(gpu):
     """The same 60 GB input, keys-only: all 600,000,000 tuples sorted on the
     device within the 30 GB budget, records gathered from the pinned input."""
