@@ -646,7 +646,7 @@ __device__ __forceinline__ uint32_t fuse_chunk_take(const Work &w) {
 typedef uint32_t u32x3a __attribute__((ext_vector_type(3), aligned(4)));
 typedef const __attribute__((address_space(1))) u32x3a gu32x3;
 
-template <int FWG, int FI, bool RECORDS, bool PF = false>
+template <int FWG, int FI, bool RECORDS>
 __global__ __launch_bounds__(FWG, 1) void k_fuse0(Work w, Tune tu) {
     constexpr int FT = FWG * FI;
     constexpr int NW = FWG / 64;
@@ -669,65 +669,42 @@ __global__ __launch_bounds__(FWG, 1) void k_fuse0(Work w, Tune tu) {
     const uint32_t ndig = 1u << tu.digit;
     const uint32_t shift = 64u - tu.digit;
     const uint64_t pool_keys = (uint64_t)w.max_chunks * C;
-    // keys of a tile: wave wv holds keys [wv * FI * 64, (wv + 1) * FI * 64)
-    // of the tile, item u of lane l being key wv * FI * 64 + u * 64 + l; a, b,
-    // c are the first three dwords of those records, loaded ahead of their use
-    uint32_t a[FI], b[FI], c[FI];
-    auto issue = [&](uint32_t t_, uint32_t wv_, uint32_t lane_) {
-        const uint64_t l0 = (uint64_t)t_ * FT;
-        const uint32_t nv = (uint32_t)min<uint64_t>(FT, n - l0);
-#pragma unroll
-        for (int u = 0; u < FI; u++) {
-            const uint32_t q = wv_ * (FI * 64) + u * 64 + lane_;
-            const uint32_t qc = q < nv ? q : nv - 1;  // loads stay branch-free
-            const gu32 *p = (const gu32 *)(rq.in + (l0 + qc) * kRec);
-            if (RECORDS) {  // the record is copied below: keep its lines in the caches
-                a[u] = p[0]; b[u] = p[1]; c[u] = p[2];
-            } else {  // each line is read once here: non-temporal
-                const u32x3a v = __builtin_nontemporal_load((gu32x3 *)p);
-                a[u] = v.x; b[u] = v.y; c[u] = v.z;
-            }
-        }
-    };
-    // PF: each workgroup takes its next tile while it works on the current
-    // one, and waves 4.. load their keys of it then; waves 0..3 hold the digit
-    // lanes, whose waits on look-back words would also wait on such loads, so
-    // they load theirs when the tile becomes current
-    uint32_t tile = 0;
-    bool loaded = false;  // a, b, c hold this wave's keys of `tile`
-    if (PF) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(&w.ctl->ftile_ctr, 1u);
-        __syncthreads();
-        tile = s_tile;
-        if (tile < nft) issue(tile, threadIdx.x >> 6, threadIdx.x & 63);
-        loaded = true;
-    }
     for (;;) {
         uint32_t tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         const uint32_t wv = tid >> 6, lane = tid & 63;
         __syncthreads();
-        if (tid == 0) s_tile = atomicAdd(&w.ctl->ftile_ctr, 1u);  // PF: the next tile
+        if (tid == 0) s_tile = atomicAdd(&w.ctl->ftile_ctr, 1u);
         for (uint32_t i = tid; i < NW * kRadix; i += FWG) (&cnt[0][0])[i] = 0;
         __syncthreads();
-        uint32_t next = 0;
-        if (PF) next = s_tile; else tile = s_tile;
+        const uint32_t tile = s_tile;
         if (tile >= nft) break;
         const uint64_t local0 = (uint64_t)tile * FT;
         const uint32_t nvalid = (uint32_t)min<uint64_t>(FT, n - local0);
-        if (!loaded) issue(tile, wv, lane);
+        // keys of the tile: wave wv holds keys [wv * FI * 64, (wv + 1) * FI * 64)
+        // of the tile, item u of lane l being key wv * FI * 64 + u * 64 + l
         uint64_t h[FI], l[FI];
+        {
+            uint32_t a[FI], b[FI], c[FI];
 #pragma unroll
-        for (int u = 0; u < FI; u++) {
-            const uint32_t q = wv * (FI * 64) + u * 64 + lane;
-            h[u] = __builtin_bswap64(((uint64_t)b[u] << 32) | a[u]) & w.kmask_h;
-            const uint64_t k16 = __builtin_bswap16((uint16_t)(c[u] & 0xFFFFu)) & w.kmask_l;
-            l[u] = (k16 << 32) | (uint32_t)(local0 + q);
-        }
-        loaded = false;
-        if (PF && wv >= 4) {
-            if (next < nft) issue(next, wv, lane);
-            loaded = true;
+            for (int u = 0; u < FI; u++) {
+                const uint32_t q = wv * (FI * 64) + u * 64 + lane;
+                const uint32_t qc = q < nvalid ? q : nvalid - 1;  // loads stay branch-free
+                const gu32 *p = (const gu32 *)(rq.in + (local0 + qc) * kRec);
+                if (RECORDS) {  // the record is copied below: keep its lines in the caches
+                    a[u] = p[0]; b[u] = p[1]; c[u] = p[2];
+                } else {  // each line is read once here: non-temporal
+                    const u32x3a v = __builtin_nontemporal_load((gu32x3 *)p);
+                    a[u] = v.x; b[u] = v.y; c[u] = v.z;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < FI; u++) {
+                const uint32_t q = wv * (FI * 64) + u * 64 + lane;
+                h[u] = __builtin_bswap64(((uint64_t)b[u] << 32) | a[u]) & w.kmask_h;
+                const uint64_t k16 = __builtin_bswap16((uint16_t)(c[u] & 0xFFFFu)) & w.kmask_l;
+                l[u] = (k16 << 32) | (uint32_t)(local0 + q);
+            }
         }
         // stable ranks by the leading digit (eight items at a time)
         uint32_t pk[FI];
@@ -864,7 +841,6 @@ __global__ __launch_bounds__(FWG, 1) void k_fuse0(Work w, Tune tu) {
                 }
             }
         }
-        if (PF) tile = next;
         if (RECORDS) {
             __syncthreads();
             // records to their pool slots, 25 dwords each, staged order (the
@@ -1798,8 +1774,6 @@ static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uin
         // one workgroup per CU (the staging takes most of the LDS); tiles from a counter
         if (st.first == kFirstRecords)
             k_fuse0<kFuseWG, fuse_items(kFirstRecords), true><<<dim3(cus), dim3(kFuseWG), 0, s>>>(w, t);
-        else if (getenv("LEY_FUSE_PF"))
-            k_fuse0<kFuseWG, fuse_items(kFirstFused), false, true><<<dim3(cus), dim3(kFuseWG), 0, s>>>(w, t);
         else
             k_fuse0<kFuseWG, fuse_items(kFirstFused), false><<<dim3(cus), dim3(kFuseWG), 0, s>>>(w, t);
         k_plan0<<<dim3(cus * 2), dim3(kWG), 0, s>>>(w, t, ft);
