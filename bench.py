@@ -347,15 +347,21 @@ def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9
     keys-only variant on the regenerated input.  (n and budget: smaller
     instances of the same workload, e.g. under a profiler.)"""
     import numpy as np
-    # PCIe rates with a pinned 2 GB buffer (HIP events, best of 3): each way
-    # alone, and both ways at once on two streams
+    # PCIe rates with a pinned 2 GB buffer (host clock, best of several): each
+    # way alone, and both ways at once on two streams.  Streams share the
+    # process's few hardware queues, so one pair can serialise its copies; the
+    # both-ways attempts go over different pairs of four streams.
     part = ley.pinned_empty(2_000_000_000)
     part2 = ley.pinned_empty(2_000_000_000)
     dev = torch.empty(2_000_000_000, dtype=torch.uint8, device="cuda:0")
     dev2 = torch.empty_like(dev)
-    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    pairs = [(0, 1), (2, 3), (0, 2), (1, 3), (0, 3), (1, 2)]
+    attempt = [0]
 
     def both():
+        s1, s2 = (streams[i] for i in pairs[attempt[0] % len(pairs)])
+        attempt[0] += 1
         with torch.cuda.stream(s1):
             dev.copy_(part, non_blocking=True)
         with torch.cuda.stream(s2):
@@ -364,11 +370,11 @@ def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9
         s2.synchronize()
 
     rates = {}
-    for name, fn, nbytes in (("h2d", lambda: dev.copy_(part, non_blocking=True), 2e9),
-                             ("d2h", lambda: part.copy_(dev, non_blocking=True), 2e9),
-                             ("both_ways", both, 4e9)):
+    for name, fn, nbytes, tries in (("h2d", lambda: dev.copy_(part, non_blocking=True), 2e9, 3),
+                                    ("d2h", lambda: part.copy_(dev, non_blocking=True), 2e9, 3),
+                                    ("both_ways", both, 4e9, len(pairs))):
         best = None
-        for _ in range(3):
+        for _ in range(tries):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             fn()
