@@ -530,28 +530,29 @@ extern "C" int leyenda_sort_runs(const void *host_records, uint64_t n, uint64_t 
 namespace ley {
 namespace {
 
-// The merge of k sorted runs (validated by the caller) into host_out, on the
-// streams of P.  runs_dev is the device view of the pinned runs.  arena: device
-// memory of `budget` bytes to use (null: allocate `budget` at most).  last:
-// run k - 1 lives in device memory there (its records are not read from the
-// pinned runs).
-int merge_impl(Pipe &P, const uint8_t *runs_dev, const uint8_t *runs_h, const uint64_t *run_bounds, uint64_t k,
-               uint8_t *out_h, bool direct_out, uint64_t device_budget_bytes, char *arena, const uint8_t *last) {
-    const uint64_t n = run_bounds[k];
-    int rc = LEYENDA_OK;
-    // chunk size from the budget: staging, output and tuple buffers plus the
-    // tables (run offsets, boundaries, co-rank splits, merge pair lists)
-    const uint32_t rounds = [&] { uint32_t r = 0; while ((1ull << r) < k) r++; return r; }();
-    auto tables_for = [&](uint64_t chunks) -> uint64_t {
-        return a256((k + 1) * 8) + a256(chunks * 8) + a256((chunks + 1) * k * 8) +
-               a256(chunks * (rounds + 1) * ((k + 1) / 2 + 1) * sizeof(MergePair)) + 256;
-    };
-    // three staging and three output buffers (records), two tuple buffer pairs
-    auto buf_bytes = [&](uint64_t m) -> uint64_t {
-        return 2 * kPipeBufs * a256(m * kRec) + 4 * a256(m * 8);
-    };
-    // largest chunk whose buffers fit next to the tables its chunk count needs
-    uint64_t lo = 0, tab = tables_for(1);
+// Rounds of the in-chunk pairwise merge of k runs: ceil(log2 k).
+uint32_t merge_rounds(uint64_t k) {
+    uint32_t r = 0;
+    while ((1ull << r) < k) r++;
+    return r;
+}
+
+// Device tables of a merge of k runs in `chunks` output chunks: run offsets,
+// chunk targets, co-rank splits, merge pair lists, the error word.
+uint64_t merge_tables_bytes(uint64_t k, uint64_t chunks) {
+    const uint32_t rounds = merge_rounds(k);
+    return a256((k + 1) * 8) + a256(chunks * 8) + a256((chunks + 1) * k * 8) +
+           a256(chunks * (rounds + 1) * ((k + 1) / 2 + 1) * sizeof(MergePair)) + 256;
+}
+
+// The merge's output chunks under a device budget: the largest chunk whose
+// buffers (three staging and three output buffers of records, two tuple
+// buffer pairs) fit next to the tables its chunk count needs.  Returns the
+// chunk bounds (empty when the budget is too small) and the device bytes the
+// merge then uses in *bytes.
+std::vector<uint64_t> merge_plan(uint64_t n, uint64_t k, uint64_t device_budget_bytes, uint64_t *bytes) {
+    auto buf_bytes = [&](uint64_t m) -> uint64_t { return 2 * kPipeBufs * a256(m * kRec) + 4 * a256(m * 8); };
+    uint64_t lo = 0, tab = merge_tables_bytes(k, 1);
     for (int it = 0; it < 64; it++) {
         if (tab + buf_bytes(1) > device_budget_bytes) break;
         uint64_t a = 1, c = std::min<uint64_t>(n, LEYENDA_MAX_RECORDS);
@@ -559,12 +560,32 @@ int merge_impl(Pipe &P, const uint8_t *runs_dev, const uint8_t *runs_h, const ui
             const uint64_t m = a + (c - a + 1) / 2;
             if (buf_bytes(m) + tab <= device_budget_bytes) a = m; else c = m - 1;
         }
-        const uint64_t t2 = tables_for((n + a - 1) / a);
+        const uint64_t t2 = merge_tables_bytes(k, (n + a - 1) / a);
         if (t2 <= tab) { lo = a; break; }
         tab = t2;
     }
-    if (lo == 0) return fail(LEYENDA_EBUDGET, "leyenda_merge: budget too small");
-    const std::vector<uint64_t> cb = equal_bounds(n, lo);  // output chunks
+    *bytes = 0;
+    if (lo == 0) return {};
+    std::vector<uint64_t> cb = equal_bounds(n, lo);
+    uint64_t C = 0;  // longest chunk (buffer size)
+    for (size_t c = 0; c + 1 < cb.size(); c++) C = std::max(C, cb[c + 1] - cb[c]);
+    *bytes = buf_bytes(C) + merge_tables_bytes(k, cb.size() - 1);
+    return cb;
+}
+
+// The merge of k sorted runs (validated by the caller) into host_out, on the
+// streams of P.  runs_dev is the device view of the pinned runs.  The chunks
+// come from merge_plan under device_budget_bytes; arena: device memory of at
+// least the plan's bytes (null: allocate them).  last: run k - 1 lives in
+// device memory there (its records are not read from the pinned runs).
+int merge_impl(Pipe &P, const uint8_t *runs_dev, const uint8_t *runs_h, const uint64_t *run_bounds, uint64_t k,
+               uint8_t *out_h, bool direct_out, uint64_t device_budget_bytes, char *arena, const uint8_t *last) {
+    const uint64_t n = run_bounds[k];
+    int rc = LEYENDA_OK;
+    const uint32_t rounds = merge_rounds(k);
+    uint64_t need = 0;
+    const std::vector<uint64_t> cb = merge_plan(n, k, device_budget_bytes, &need);  // output chunks
+    if (cb.empty()) return fail(LEYENDA_EBUDGET, "leyenda_merge: budget too small");
     const uint64_t nch = cb.size() - 1;
     uint64_t C = 0;  // longest chunk (buffer size)
     for (uint64_t c = 0; c < nch; c++) C = std::max(C, cb[c + 1] - cb[c]);
@@ -573,7 +594,7 @@ int merge_impl(Pipe &P, const uint8_t *runs_dev, const uint8_t *runs_h, const ui
     const size_t n_tab = (size_t)(nch + 1) * k;
     const size_t pair_cap = (size_t)nch * (rounds + 1) * ((k + 1) / 2 + 1);
     if (!arena) {
-        if ((rc = P.alloc(2 * kPipeBufs * sb + 4 * tb + tables_for(nch)))) return rc;
+        if ((rc = P.alloc(need))) return rc;
         arena = static_cast<char *>(P.arena);
     }
     char *base = arena;
@@ -782,7 +803,10 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
 // stays in device memory after its sort instead of going to host_runs and
 // coming back for the merge (it is the one run whose download would have
 // nothing to overlap with, and its slices then reach the merge by device
-// copies).  The merge uses the rest of the run stage's device memory.
+// copies).  The merge plans its chunks within the budget less that run; when
+// that is too little for a merge of the runs (many tiny runs under a budget
+// near one run's footprint), the last run goes to host_runs too and the merge
+// runs as leyenda_merge would with the whole budget.
 
 extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint64_t device_budget_bytes,
                                      void *host_runs, void *host_out, void *stream) {
@@ -810,8 +834,13 @@ extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint6
     if ((rc = P.init(static_cast<hipStream_t>(stream)))) return rc;
     const size_t rb = a256(R * kRec);
     const size_t ws_bytes = plan_layout(R, 1, t).total;
-    const size_t total = 4 * rb + ws_bytes + 256;
-    if ((rc = P.alloc(total))) return rc;
+    const size_t total = 4 * rb + ws_bytes + 256;  // <= the budget (plan_runs_t)
+    // the merge plans its chunks within the budget less the kept run; when
+    // that leaves too little for its tables (many tiny runs), the last run is
+    // downloaded like the others and the merge plans within the whole budget
+    uint64_t merge_bytes = 0;
+    const bool keep_last = K == 1 || !merge_plan(n, K, device_budget_bytes - rb, &merge_bytes).empty();
+    if ((rc = P.alloc(keep_last ? std::max<uint64_t>(total, rb + merge_bytes) : total))) return rc;
     char *base = static_cast<char *>(P.arena);
     // the output buffer the last run sorts into comes first, so the rest of the
     // memory is one block for the merge
@@ -838,7 +867,7 @@ extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint6
         if ((rc = sort_device_ws(in[b], len, out[b], P.cs, t, ws))) return rc;
         e = launch_guard_or(ws, len, t, guard, P.cs);
         if (e == hipSuccess) e = hipEventRecord(P.ev[1][b], P.cs);
-        if (e == hipSuccess && r + 1 < K) {
+        if (e == hipSuccess && (r + 1 < K || !keep_last)) {
             e = hipStreamWaitEvent(P.d2h, P.ev[1][b], 0);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(dst + off * kRec, out[b], len * kRec, hipMemcpyDeviceToHost, P.d2h);
@@ -863,7 +892,14 @@ extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint6
         if ((rc = bounce.drain(keep, out_h, n * kRec, P.ev[1][0], P.d2h))) return rc;
         return P.finish();
     }
-    return merge_impl(P, runs_dev, dst, bounds.data(), K, out_h, direct_out, total - rb, base + rb, keep);
+    if (!keep_last) {  // every run is in host_runs: the merge as leyenda_merge runs it
+        (void)hipFree(P.arena);
+        P.arena = nullptr;
+        return merge_impl(P, runs_dev, dst, bounds.data(), K, out_h, direct_out, device_budget_bytes, nullptr,
+                          nullptr);
+    }
+    return merge_impl(P, runs_dev, dst, bounds.data(), K, out_h, direct_out, device_budget_bytes - rb, base + rb,
+                      keep);
 }
 
 // ---------------------------------------------------------------------------

@@ -203,3 +203,20 @@ def test_sort_external_tiny_and_errors(gpu):
     with pytest.raises(gpu.LeyendaError) as ei:  # the output over the runs
         gpu.sort_external(h, 64 << 20, host_runs=h, host_out=h)
     assert ei.value.status == -1
+
+
+def test_sort_external_many_tiny_runs(gpu):
+    """21 runs of about 340 records under a budget near one run's footprint:
+    the budget less the kept run is too small for the merge's tables, so the
+    call downloads the last run too and merges within the whole budget (found
+    by a random case)."""
+    import torch
+    n = 7111
+    rec = oracle.sort(datagen.uniform(n, 97))  # sorted input
+    host = pinned(rec)
+    budget = budget_for_runs(gpu, n, 21)
+    _, k = gpu.plan_runs(n, budget)
+    assert k == 21
+    runs = torch.empty(n * 100, dtype=torch.uint8, pin_memory=True)
+    out = gpu.sort_external(host, budget, host_runs=runs)
+    np.testing.assert_array_equal(out.numpy().reshape(n, 100), rec)
