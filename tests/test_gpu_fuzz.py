@@ -1,6 +1,6 @@
 """Seeded random cases against the CPU oracle: random sizes, key structures,
 tuning parameters and key lengths, random batches, and random cases of the
-limited-memory path.
+limited-memory path and of the sort that allocates nothing.
 
 Each case draws its size log-uniformly (1 to 2.5 M records, plus two cases
 above the 8 Mi threshold of the fused first pass), a key structure (uniform,
@@ -21,7 +21,7 @@ from tests.test_gpu_sort import assert_same
 pytestmark = pytest.mark.gpu
 
 SEED = 20261203
-N_CASES = 96
+N_CASES = 200
 
 
 def _records(rng, n: int) -> tuple[np.ndarray, str]:
@@ -117,7 +117,7 @@ def test_fuzz_sort(gpu, case):
         assert st["guard"] == 0
 
 
-@pytest.mark.parametrize("seed", [11, 12, 13, 14])
+@pytest.mark.parametrize("seed", range(11, 19))
 def test_fuzz_batch(gpu, seed):
     """Random batches: 1 to 40 requests of 0 to 300,000 records, mixed key
     structures, one launch sequence; each request must equal its oracle sort."""
@@ -143,7 +143,7 @@ def test_fuzz_batch(gpu, seed):
         assert_same(o.cpu().numpy().reshape(-1, 100), oracle.sort(r), f"batch {seed} request {k}")
 
 
-@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("seed", range(24))
 def test_fuzz_external(gpu, seed):
     """The limited-memory path with random sizes (1,000 to 600,000 records),
     run counts (1 to 24), merge budgets (1.5 to 48 MB, so 1 to hundreds of
@@ -182,3 +182,29 @@ def test_fuzz_external(gpu, seed):
     finally:
         gpu.set_params(**old)
     assert_same(out.numpy().reshape(n, 100), want, f"external {seed}")
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_fuzz_noalloc(gpu, seed):
+    """leyenda_sort_noalloc through the C ABI with random parameters and sizes
+    up to what its fixed array holds under them; calls follow each other on
+    the same array."""
+    import torch
+    rng = np.random.default_rng(SEED + 200 + seed)
+    params = _params(rng)
+    lib = gpu.load()
+    old = gpu.get_params()
+    try:
+        gpu.set_params(**params)
+        cap = int(lib.leyenda_noalloc_max_records())
+        n = int(np.exp(rng.uniform(0, np.log(cap))))
+        rec, what = _records(rng, n)
+        print(f"fuzz noalloc {seed}: n={n} (cap {cap}) keys={what} params={params}", flush=True)
+        d = _dev(rec)
+        out = torch.empty_like(d)
+        rc = lib.leyenda_sort_noalloc(d.data_ptr(), n, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        assert rc == 0, lib.leyenda_last_error()
+        torch.cuda.synchronize()
+    finally:
+        gpu.set_params(**old)
+    assert_same(out.cpu().numpy().reshape(-1, 100), oracle.sort(rec), f"noalloc {seed}")
