@@ -1,6 +1,7 @@
 """Seeded random cases against the CPU oracle: random sizes, key structures,
 tuning parameters and key lengths, random batches, and random cases of the
-limited-memory path and of the sort that allocates nothing.
+limited-memory path, of the sort that allocates nothing and of the serving
+engine.
 
 Each case draws its size log-uniformly (1 to 2.5 M records, plus two cases
 above the 8 Mi threshold of the fused first pass), a key structure (uniform,
@@ -208,3 +209,71 @@ def test_fuzz_noalloc(gpu, seed):
     finally:
         gpu.set_params(**old)
     assert_same(out.cpu().numpy().reshape(-1, 100), oracle.sort(rec), f"noalloc {seed}")
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_fuzz_server(gpu, seed):
+    """The serving engine with random slots, batch limits, budgets and
+    parameters, batched or not; requests of random sizes and key structures
+    arrive in waves while earlier ones run, and completed outputs are held a
+    while before release (so admission waits on the output arena).  Every
+    output must equal its oracle sort."""
+    import time
+    import torch
+    rng = np.random.default_rng(SEED + 300 + seed)
+    params = _params(rng)
+    batched = bool(rng.integers(0, 2))
+    slots = int(rng.integers(1, 5))
+    max_batch = int(rng.integers(1, 49))
+    mbr = int(rng.integers(50_000, 400_001))
+    count = int(rng.integers(60, 151))
+    sizes = [int(np.exp(rng.uniform(0, np.log(mbr)))) for _ in range(count)]
+    recs, whats = [], []
+    for n in sizes:
+        r, w = _records(rng, n)
+        recs.append(r)
+        whats.append(w)
+    print(f"fuzz server {seed}: batched={batched} slots={slots} max_batch={max_batch} max_batch_records={mbr} "
+          f"requests={count} records={sum(sizes)} params={params}", flush=True)
+    ins = [_dev(r).view(-1) for r in recs]
+    old = gpu.get_params()
+    outs = {}
+    try:
+        gpu.set_params(**params)
+        ws = gpu.workspace_bytes(mbr)
+        budget = slots * (2 * ws + (64 << 20)) + mbr * 100 * int(rng.integers(1, 5))
+        srv = gpu.Server(budget_bytes=budget, slots=slots, max_batch=max_batch, max_batch_records=mbr,
+                         batched=batched)
+        try:
+            nxt, held, idle_since = 0, [], time.monotonic()
+            while len(outs) < count:
+                # a wave of submissions
+                wave = int(rng.integers(0, 25))
+                for _ in range(wave):
+                    if nxt < count:
+                        srv.submit(ins[nxt], nxt)
+                        nxt += 1
+                got = srv.poll(timeout_s=0.2)
+                for dn in got:
+                    assert dn["status"] == 0, dn
+                    assert dn["n"] == sizes[dn["tag"]]
+                    outs[dn["tag"]] = srv.output(dn).cpu().numpy()
+                    held.append(dn["tag"])
+                hold = int(rng.integers(0, 9))
+                if not got or len(held) > hold:
+                    for t in held[: len(held) - (hold if got else 0)]:
+                        srv.release(t)
+                    held = held[len(held) - (hold if got else 0):]
+                if got:
+                    idle_since = time.monotonic()
+                elif nxt >= count and time.monotonic() - idle_since > 60:
+                    raise AssertionError(f"no completion for 60 s with {count - len(outs)} requests left")
+            for t in held:
+                srv.release(t)
+            torch.cuda.synchronize()
+        finally:
+            srv.close()
+    finally:
+        gpu.set_params(**old)
+    for i, r in enumerate(recs):
+        assert_same(outs[i], oracle.sort(r), f"server {seed} request {i} ({whats[i]}, n={sizes[i]})")
