@@ -16,20 +16,22 @@
 // followed by key bytes [P, P + 6) of the record (bytes at or past K read as
 // zero) and whose index is the entry's own number (entries are numbered in
 // output-position order), written straight into the tuple buffers of a sort
-// workspace, plus the record's position.  One sort of the tuples (the in-HBM
-// sort's partition and local-sort stages, no record gather) orders every run
-// by its next six key bytes at once: the run number keeps runs apart and in
-// place, and equal keys keep entry order, which is position order and so
-// input order.  The records of the runs are then gathered in the sorted order
-// and written back over their runs.  A tie on [0, P + 6) implies a tie on
-// [0, P), so a round looks only at the previous round's entries: in sorted
+// workspace.  One sort of the tuples (the in-HBM sort's partition and
+// local-sort stages, no record gather) orders every run by its next six key
+// bytes at once: the run number keeps runs apart and in place, and equal keys
+// keep entry order, which is position order and so input order.  The rounds
+// move record indices, not records: the q-th entry in sorted order takes the
+// q-th position of the round, and each position's input record index is
+// carried to the next round; after the last round one gather copies every
+// tied position's record from the input.  A tie on [0, P + 6) implies a tie
+// on [0, P), so a round looks only at the previous round's entries: in sorted
 // order they describe the records now at consecutive positions of each run,
-// and two neighbours tie exactly when their entries' keys agree.  The first round's ties come
-// from the prefix sort itself: its record gather marks every output record
-// whose key bytes 0..9 equal those of the record before it, so no round reads
-// the records to find ties.  Rounds stop when no run is left or P reaches K.  The
-// host reads the entry count of each round (one stream synchronisation per
-// round).
+// and two neighbours tie exactly when their entries' keys agree.  The first
+// round's ties come from the prefix sort itself: its record gather marks every
+// output record whose key bytes 0..9 equal those of the record before it, so
+// no round reads the records to find ties.  Rounds stop when no run is left
+// or P reaches K.  The host reads the entry count of each round (one stream
+// synchronisation per round).
 #include <hip/hip_runtime.h>
 
 #include "runtime.h"
@@ -38,27 +40,27 @@ namespace ley {
 namespace {
 
 constexpr int kTB = 256;                // threads per block
-constexpr int kTPer = 4;                // positions per thread
+constexpr int kTPer = 16;               // consecutive positions per thread (one 16-byte load of tie marks)
 constexpr int kTSpan = kTB * kTPer;     // positions per block
 constexpr int kRecWords = kRec / 4;     // dwords per record
 constexpr uint32_t kWindow = 6;         // key bytes resolved per round
 
 constexpr int kTWaves = kTB / 64;
 
-// Exclusive counts of two flags over the block's threads in thread order (a
-// ballot and a bit count per wave, then the waves' totals through LDS);
+// Exclusive sums of two per-thread counts over the block's threads in thread
+// order (wave scans by lane shuffles, then the waves' totals through LDS);
 // *ta, *tb get the block totals.  Whole block.
-__device__ __forceinline__ void block_count2(bool fa, bool fb, uint32_t *ea, uint32_t *eb, uint32_t *ta,
-                                             uint32_t *tb) {
+__device__ __forceinline__ void block_scan2(uint32_t a, uint32_t b, uint32_t *ea, uint32_t *eb, uint32_t *ta,
+                                            uint32_t *tb) {
     __shared__ uint32_t wa[kTWaves], wb[kTWaves];
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint64_t ba = __ballot(fa), bb = __ballot(fb);
-    const uint32_t below_a = __builtin_amdgcn_mbcnt_hi((uint32_t)(ba >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ba, 0u));
-    const uint32_t below_b = __builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0u));
-    if (lane == 0) {
-        wa[w] = (uint32_t)__popcll(ba);
-        wb[w] = (uint32_t)__popcll(bb);
+    uint32_t ia = a, ib = b;  // inclusive within the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t xa = __shfl_up(ia, d), xb = __shfl_up(ib, d);
+        if (lane >= (uint32_t)d) { ia += xa; ib += xb; }
     }
+    if (lane == 63) { wa[w] = ia; wb[w] = ib; }
     __syncthreads();
     uint32_t pa = 0, pb = 0, sa = 0, sb = 0;
 #pragma unroll
@@ -69,8 +71,8 @@ __device__ __forceinline__ void block_count2(bool fa, bool fb, uint32_t *ea, uin
         sb += wb[k];
     }
     __syncthreads();
-    *ea = pa + below_a;
-    *eb = pb + below_b;
+    *ea = pa + ia - a;
+    *eb = pb + ib - b;
     *ta = sa;
     *tb = sb;
 }
@@ -93,70 +95,114 @@ __global__ __launch_bounds__(kTB) void k_tie_eq(const uint64_t *SKh, const uint3
     }
 }
 
-// Candidate c is inside a run of at least two (it ties with a neighbour) and
-// whether such a run starts there.
-__device__ __forceinline__ void run_flags(const uint8_t *P, uint64_t nc, uint64_t c, bool *in_run, bool *starts) {
-    const bool eq_prev = c > 0 && P[c] != 0;
-    const bool eq_next = c + 1 < nc && P[c + 1] != 0;
-    *in_run = eq_prev || eq_next;
-    *starts = eq_next && !eq_prev;
+// The tie flags of the thread's kTPer candidates c0 + k (c0 = block base +
+// kTPer * thread): bit k of *in_run when candidate c0 + k lies inside a run of
+// at least two (it ties with a neighbour), of *starts when such a run starts
+// there.  One 16-byte load of the marks (P is 16-byte aligned) and one byte
+// for the next thread's first mark.
+__device__ __forceinline__ void tie_bits(const uint8_t *P, uint64_t nc, uint64_t c0, uint32_t *in_run,
+                                         uint32_t *starts) {
+    uint32_t eq = 0;  // bit k: candidate c0 + k ties with the candidate before it
+    if (c0 + kTPer <= nc) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(P + c0);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < kTPer; k++) eq |= (((w[k >> 2] >> (8 * (k & 3))) & 0xFFu) != 0u ? 1u : 0u) << k;
+    } else {
+        for (int k = 0; k < kTPer; k++)
+            if (c0 + k < nc && P[c0 + k] != 0) eq |= 1u << k;
+    }
+    if (c0 == 0) eq &= ~1u;  // the first candidate has no predecessor
+    const uint32_t next = (c0 + kTPer < nc && P[c0 + kTPer] != 0) ? 1u : 0u;
+    const uint32_t eq_next = (eq >> 1) | (next << (kTPer - 1));  // bit k: c0 + k ties with c0 + k + 1
+    const uint32_t valid = c0 >= nc ? 0u : (nc - c0 >= (uint64_t)kTPer ? 0xFFFFu : ((1u << (nc - c0)) - 1u));
+    *in_run = (eq | eq_next) & valid;
+    *starts = eq_next & ~eq & valid;
 }
 
 // Per block of kTSpan candidates: candidates inside runs and run starts.
 __global__ __launch_bounds__(kTB) void k_tie_count(const uint8_t *P, uint64_t nc, uint32_t *cnt_in,
                                                    uint32_t *cnt_start) {
-    const uint64_t base = (uint64_t)blockIdx.x * kTSpan;
-    uint32_t ci = 0, cs = 0;
-    for (int u = 0; u < kTPer; u++) {
-        const uint64_t c = base + (uint64_t)u * kTB + threadIdx.x;
-        if (c < nc) {
-            bool r, s;
-            run_flags(P, nc, c, &r, &s);
-            ci += r;
-            cs += s;
-        }
-    }
-    __shared__ uint32_t s_i, s_s;
-    if (threadIdx.x == 0) { s_i = 0; s_s = 0; }
-    __syncthreads();
-    ci = __ockl_wfred_add_u32(ci);
-    cs = __ockl_wfred_add_u32(cs);
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&s_i, ci);
-        atomicAdd(&s_s, cs);
-    }
-    __syncthreads();
+    const uint64_t c0 = (uint64_t)blockIdx.x * kTSpan + (uint64_t)threadIdx.x * kTPer;
+    uint32_t r, st;
+    tie_bits(P, nc, c0, &r, &st);
+    uint32_t ei, es, ti, ts;
+    block_scan2((uint32_t)__popc(r), (uint32_t)__popc(st), &ei, &es, &ti, &ts);
     if (threadIdx.x == 0) {
-        cnt_in[blockIdx.x] = s_i;
-        cnt_start[blockIdx.x] = s_s;
+        cnt_in[blockIdx.x] = ti;
+        cnt_start[blockIdx.x] = ts;
     }
 }
 
-// One block: exclusive scans of both per-block counts (each thread sums a
-// contiguous range of blocks, the range totals are scanned in LDS, then each
-// thread writes its range's offsets); totals[0] = positions inside runs,
-// totals[1] = runs.
-constexpr int kSB = 1024;
-__global__ __launch_bounds__(kSB) void k_tie_scan(const uint32_t *cnt_in, const uint32_t *cnt_start, uint64_t nb,
-                                                  uint64_t *off_in, uint64_t *off_start, uint64_t *totals) {
+// Exclusive scans of both per-block counts, in three launches: per group of
+// kSG counts its sums (up), the groups' offsets (top, one block), then every
+// count's offset (down); totals[0] = positions inside runs, totals[1] = runs.
+constexpr int kSB = 1024;            // threads per scan block
+constexpr int kSPer = 4;             // counts per thread
+constexpr int kSG = kSB * kSPer;     // counts per group
+
+__device__ __forceinline__ void load_counts(const uint32_t *ci, const uint32_t *cs, uint64_t nb, uint64_t b0,
+                                            uint32_t *vi, uint32_t *vs) {
+#pragma unroll
+    for (int k = 0; k < kSPer; k++) {
+        vi[k] = b0 + k < nb ? ci[b0 + k] : 0u;
+        vs[k] = b0 + k < nb ? cs[b0 + k] : 0u;
+    }
+}
+
+// Exclusive scan of a uint32 pair over the kSB threads of a block (wave
+// shuffles, then the wave totals through LDS).  Whole block.
+__device__ __forceinline__ void scan_block_pair(uint32_t a, uint32_t b, uint32_t *ea, uint32_t *eb, uint32_t *ta,
+                                                uint32_t *tb) {
+    constexpr int W = kSB / 64;
+    __shared__ uint32_t wa[W], wb[W];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t ia = a, ib = b;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t xa = __shfl_up(ia, d), xb = __shfl_up(ib, d);
+        if (lane >= (uint32_t)d) { ia += xa; ib += xb; }
+    }
+    if (lane == 63) { wa[w] = ia; wb[w] = ib; }
+    __syncthreads();
+    uint32_t pa = 0, pb = 0, sa = 0, sb = 0;
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+        pa += k < (int)w ? wa[k] : 0u;
+        pb += k < (int)w ? wb[k] : 0u;
+        sa += wa[k];
+        sb += wb[k];
+    }
+    __syncthreads();
+    *ea = pa + ia - a;
+    *eb = pb + ib - b;
+    *ta = sa;
+    *tb = sb;
+}
+
+__global__ __launch_bounds__(kSB) void k_tie_scan_up(const uint32_t *cnt_in, const uint32_t *cnt_start, uint64_t nb,
+                                                     uint64_t *grp_in, uint64_t *grp_start) {
+    uint32_t vi[kSPer], vs[kSPer];
+    load_counts(cnt_in, cnt_start, nb, (uint64_t)blockIdx.x * kSG + (uint64_t)threadIdx.x * kSPer, vi, vs);
+    uint32_t si = 0, ss = 0;
+#pragma unroll
+    for (int k = 0; k < kSPer; k++) { si += vi[k]; ss += vs[k]; }
+    uint32_t ei, es, ti, ts;
+    scan_block_pair(si, ss, &ei, &es, &ti, &ts);
+    if (threadIdx.x == 0) {
+        grp_in[blockIdx.x] = ti;
+        grp_start[blockIdx.x] = ts;
+    }
+}
+
+// One block: exclusive scan of the ng <= kSB group sums in place, and the totals.
+__global__ __launch_bounds__(kSB) void k_tie_scan_top(uint64_t *grp_in, uint64_t *grp_start, uint64_t ng,
+                                                      uint64_t *totals) {
     __shared__ uint64_t si[kSB], ss[kSB];
     const uint32_t t = threadIdx.x;
-    const uint64_t per = (nb + kSB - 1) / kSB;
-    const uint64_t b0 = min(nb, (uint64_t)t * per), b1 = min(nb, b0 + per);
-    constexpr int kG = 16;  // loads in flight per thread
-    uint64_t ti = 0, ts = 0;
-    for (uint64_t b = b0; b < b1; b += kG) {
-        uint32_t vi[kG], vs[kG];
-#pragma unroll
-        for (int k = 0; k < kG; k++) {
-            vi[k] = b + k < b1 ? cnt_in[b + k] : 0u;
-            vs[k] = b + k < b1 ? cnt_start[b + k] : 0u;
-        }
-#pragma unroll
-        for (int k = 0; k < kG; k++) { ti += vi[k]; ts += vs[k]; }
-    }
-    si[t] = ti;
-    ss[t] = ts;
+    const uint64_t vi = t < ng ? grp_in[t] : 0ull, vs = t < ng ? grp_start[t] : 0ull;
+    si[t] = vi;
+    ss[t] = vs;
     __syncthreads();
     for (uint32_t off = 1; off < (uint32_t)kSB; off <<= 1) {
         const uint64_t ai = t >= off ? si[t - off] : 0ull, as = t >= off ? ss[t - off] : 0ull;
@@ -165,23 +211,9 @@ __global__ __launch_bounds__(kSB) void k_tie_scan(const uint32_t *cnt_in, const 
         ss[t] += as;
         __syncthreads();
     }
-    uint64_t ci = si[t] - ti, cs = ss[t] - ts;
-    for (uint64_t b = b0; b < b1; b += kG) {
-        uint32_t vi[kG], vs[kG];
-#pragma unroll
-        for (int k = 0; k < kG; k++) {
-            vi[k] = b + k < b1 ? cnt_in[b + k] : 0u;
-            vs[k] = b + k < b1 ? cnt_start[b + k] : 0u;
-        }
-#pragma unroll
-        for (int k = 0; k < kG; k++) {
-            if (b + k < b1) {
-                off_in[b + k] = ci;
-                off_start[b + k] = cs;
-            }
-            ci += vi[k];
-            cs += vs[k];
-        }
+    if (t < ng) {
+        grp_in[t] = si[t] - vi;
+        grp_start[t] = ss[t] - vs;
     }
     if (t == kSB - 1) {
         totals[0] = si[t];
@@ -189,110 +221,147 @@ __global__ __launch_bounds__(kSB) void k_tie_scan(const uint32_t *cnt_in, const 
     }
 }
 
-// Entries of the round: for candidate c inside a run, entry t (its rank among
-// such candidates) gets the tuple key = run number (big-endian) + key bytes
-// [p, p + 6) of the record at its position j, masked to the key, with index t
-// (TH[t], TL[t]: the sort's tuple words), the same key in Kh[t], Kl[t] (kept
-// for the next round's tie marks), and dest[t] = j.  j = c in the first round,
-// else the previous round's dest[c].
-__global__ __launch_bounds__(kTB) void k_tie_emit(const uint32_t *A, const uint8_t *P, uint64_t nc,
-                                                  const uint64_t *cand, uint32_t p, uint32_t key_bytes,
-                                                  const uint64_t *off_in, const uint64_t *off_start, uint64_t *TH,
-                                                  uint64_t *TL, uint64_t *Kh, uint32_t *Kl, uint64_t *dest) {
-    const uint64_t base = (uint64_t)blockIdx.x * kTSpan;
-    uint64_t ci = off_in[blockIdx.x], cs = off_start[blockIdx.x];
-    const uint8_t *Ab = reinterpret_cast<const uint8_t *>(A);
-    for (int u = 0; u < kTPer; u++) {
-        const uint64_t c = base + (uint64_t)u * kTB + threadIdx.x;
-        bool r = false, s = false;
-        if (c < nc) run_flags(P, nc, c, &r, &s);
-        uint32_t ei, es, ti, ts;
-        block_count2(r, s, &ei, &es, &ti, &ts);
-        if (r) {
-            const uint64_t t = ci + ei;
-            const uint64_t j = cand ? cand[c] : c;
-            // the run holding c began at the latest start at or before c
-            const uint32_t run = (uint32_t)(cs + es + (s ? 1u : 0u) - 1u);
-            uint8_t kb[kWindow];
-            for (uint32_t k = 0; k < kWindow; k++) {
-                const uint32_t b = p + k;
-                kb[k] = b < key_bytes ? Ab[j * kRec + b] : (uint8_t)0;
-            }
-            const uint64_t h = ((uint64_t)run << 32) | ((uint32_t)kb[0] << 24) | ((uint32_t)kb[1] << 16) |
-                               ((uint32_t)kb[2] << 8) | (uint32_t)kb[3];
-            const uint32_t w = ((uint32_t)kb[4] << 8) | (uint32_t)kb[5];
-            TH[t] = h;
-            TL[t] = ((uint64_t)w << 32) | (uint32_t)t;
-            Kh[t] = h;
-            Kl[t] = w;
-            dest[t] = j;
+__global__ __launch_bounds__(kSB) void k_tie_scan_down(const uint32_t *cnt_in, const uint32_t *cnt_start, uint64_t nb,
+                                                       const uint64_t *grp_in, const uint64_t *grp_start,
+                                                       uint64_t *off_in, uint64_t *off_start) {
+    const uint64_t b0 = (uint64_t)blockIdx.x * kSG + (uint64_t)threadIdx.x * kSPer;
+    uint32_t vi[kSPer], vs[kSPer];
+    load_counts(cnt_in, cnt_start, nb, b0, vi, vs);
+    uint32_t si = 0, ss = 0;
+#pragma unroll
+    for (int k = 0; k < kSPer; k++) { si += vi[k]; ss += vs[k]; }
+    uint32_t ei, es, ti, ts;
+    scan_block_pair(si, ss, &ei, &es, &ti, &ts);
+    uint64_t ci = grp_in[blockIdx.x] + ei, cs = grp_start[blockIdx.x] + es;
+#pragma unroll
+    for (int k = 0; k < kSPer; k++) {
+        if (b0 + k < nb) {
+            off_in[b0 + k] = ci;
+            off_start[b0 + k] = cs;
         }
-        ci += ti;
-        cs += ts;
+        ci += vi[k];
+        cs += vs[k];
     }
 }
 
-// Sorted entries q of a block of kTB (idx[q] = the entry number t): out[q] =
-// A[dest[t]] and the entry's key in SKh[q], SKl[q] (sorted order, for the next
-// round's tie marks).  Each thread looks up one entry's position into LDS,
-// then the block copies its records a dword per thread (contiguous stores).
-// An entry number or position out of range, which only a failed entry sort
-// could leave, is not read: it sets *err, and the call reports
-// LEYENDA_EINTERNAL.
-__global__ __launch_bounds__(kTB) void k_tie_gather(const uint32_t *A, uint64_t n, const uint32_t *idx,
-                                                    const uint64_t *dest, const uint64_t *Kh, const uint32_t *Kl,
-                                                    uint64_t m, uint32_t *out, uint64_t *SKh, uint32_t *SKl,
-                                                    uint32_t *err) {
-    __shared__ uint64_t sj[kTB];
-    const uint64_t q0 = (uint64_t)blockIdx.x * kTB;
-    const uint32_t nr = (uint32_t)min<uint64_t>(kTB, m - q0);
-    if (threadIdx.x < nr) {
-        const uint64_t q = q0 + threadIdx.x;
-        const uint32_t t = idx[q];
-        uint64_t j = ~0ull;
-        if (t < m) {
-            j = dest[t];
-            SKh[q] = Kh[t];
-            SKl[q] = Kl[t];
+// Entries of the round: for candidate c inside a run, entry t (its rank among
+// such candidates) gets the tuple key = run number (big-endian) + key bytes
+// [p, p + 6) of its record, masked to the key, with index t (TH[t], TL[t]: the
+// sort's tuple words), the same key in Kh[t], Kl[t] (kept for the next round's
+// tie marks), its record's input index srcx[t] and its first-round entry
+// number e0x[t].  First round (src_prev null): candidate c is output position
+// c, holding input record pidx[c] (the prefix sort's order), whose bytes are
+// read from the sorted output A; e0x[t] = t and slot0[t] = c.  Later rounds:
+// candidate c is the previous round's sorted entry c, holding input record
+// src_prev[c] (its bytes read from the input) at the position of first-round
+// entry e0_prev[c].  An index out of range, which only a failed sort could
+// leave, is not read: it sets *err.
+__global__ __launch_bounds__(kTB) void k_tie_emit(const uint8_t *A, const uint8_t *in, uint64_t n,
+                                                  const uint8_t *P, uint64_t nc, const uint32_t *pidx,
+                                                  const uint32_t *src_prev, const uint32_t *e0_prev, uint32_t p,
+                                                  uint32_t key_bytes, const uint64_t *off_in,
+                                                  const uint64_t *off_start, uint64_t *TH, uint64_t *TL,
+                                                  uint64_t *Kh, uint32_t *Kl, uint32_t *srcx, uint32_t *e0x,
+                                                  uint64_t *slot0, uint32_t *err) {
+    const uint64_t c0 = (uint64_t)blockIdx.x * kTSpan + (uint64_t)threadIdx.x * kTPer;
+    uint32_t r, st;
+    tie_bits(P, nc, c0, &r, &st);
+    uint32_t ei, es, ti, ts;
+    block_scan2((uint32_t)__popc(r), (uint32_t)__popc(st), &ei, &es, &ti, &ts);
+    uint64_t t = off_in[blockIdx.x] + ei;                   // entry number of the thread's first tied candidate
+    const uint64_t runs_before = off_start[blockIdx.x] + es;  // runs started before c0
+    // key bytes past the key read as zero: byte mask of the six window bytes
+    uint32_t keep = 0;
+    for (uint32_t k = 0; k < kWindow; k++)
+        if (p + k < key_bytes) keep |= 1u << k;
+    while (r) {
+        const int k = __builtin_ctz(r);
+        r &= r - 1;
+        const uint64_t c = c0 + (uint64_t)k;
+        const uint32_t src = src_prev ? src_prev[c] : pidx[c];
+        const uint32_t e0 = src_prev ? e0_prev[c] : (uint32_t)t;
+        // the run holding c began at the latest start at or before c
+        const uint32_t run = (uint32_t)(runs_before + (uint32_t)__popc(st & ((2u << k) - 1u)) - 1u);
+        const bool ok = src < n;
+        if (!ok) atomicOr(err, 1u << 17);
+        // the window's six bytes from two aligned dwords (the record offset and
+        // p are even; the two dwords end inside the record for every p < 100)
+        uint32_t b6[kWindow] = {0, 0, 0, 0, 0, 0};
+        if (ok) {
+            const uint64_t o = (src_prev ? (uint64_t)src : c) * kRec + p;
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(src_prev ? in : A) + (o >> 2);
+            const uint64_t v = ((uint64_t)w[1] << 32) | w[0];
+            const uint32_t sh = (uint32_t)(o & 3u) * 8u;
+#pragma unroll
+            for (uint32_t j = 0; j < kWindow; j++) b6[j] = (keep >> j & 1u) ? (uint32_t)(v >> (sh + 8u * j)) & 0xFFu : 0u;
         }
-        if (j >= n) { atomicOr(err, 1u << 16); j = ~0ull; }
-        sj[threadIdx.x] = j;
+        const uint64_t h = ((uint64_t)run << 32) | (b6[0] << 24) | (b6[1] << 16) | (b6[2] << 8) | b6[3];
+        const uint32_t wl = (b6[4] << 8) | b6[5];
+        TH[t] = h;
+        TL[t] = ((uint64_t)wl << 32) | (uint32_t)t;
+        Kh[t] = h;
+        Kl[t] = wl;
+        srcx[t] = src;
+        e0x[t] = e0;
+        if (!src_prev) slot0[t] = c;
+        t++;
+    }
+}
+
+// After the entry sort (idx[q] = the entry number t in sorted position q):
+// the entry's key in SKh[q], SKl[q] (sorted order, for the next round's tie
+// marks) and its record's input index in src_s[q]; the q-th sorted entry takes
+// the position of entry q, which belongs to first-round entry e0x[q], so
+// final_src[e0x[q]] = that input index.  An entry number or first-round entry
+// out of range, which only a failed entry sort could leave, sets *err.
+__global__ __launch_bounds__(kTB) void k_tie_perm(const uint32_t *idx, uint64_t m, const uint64_t *Kh,
+                                                  const uint32_t *Kl, const uint32_t *srcx, const uint32_t *e0x,
+                                                  uint64_t m0, uint64_t *SKh, uint32_t *SKl, uint32_t *src_s,
+                                                  uint32_t *final_src, uint32_t *err) {
+    const uint64_t q = (uint64_t)blockIdx.x * kTB + threadIdx.x;
+    if (q >= m) return;
+    const uint32_t t = idx[q];
+    if (t >= m) { atomicOr(err, 1u << 16); return; }
+    const uint32_t src = srcx[t];
+    SKh[q] = Kh[t];
+    SKl[q] = Kl[t];
+    src_s[q] = src;
+    const uint32_t e = e0x[q];
+    if (e < m0) final_src[e] = src;
+    else atomicOr(err, 1u << 16);
+}
+
+// The tied positions' records, once after the last round: A[slot0[t]] =
+// in[final_src[t]] for the first-round entries t of a block of kTB (positions
+// through LDS, then a dword per thread, every load in flight before the
+// stores).  A position or index out of range sets *err and is skipped.
+__global__ __launch_bounds__(kTB) void k_tie_final(const uint32_t *in, uint64_t n, const uint64_t *slot0,
+                                                   const uint32_t *final_src, uint64_t m0, uint32_t *A,
+                                                   uint32_t *err) {
+    __shared__ uint64_t sd[kTB];
+    __shared__ uint32_t ss[kTB];
+    const uint64_t t0 = (uint64_t)blockIdx.x * kTB;
+    const uint32_t nr = (uint32_t)min<uint64_t>(kTB, m0 - t0);
+    if (threadIdx.x < nr) {
+        const uint64_t d = slot0[t0 + threadIdx.x];
+        const uint32_t sidx = final_src[t0 + threadIdx.x];
+        const bool ok = d < n && sidx < n;
+        if (!ok) atomicOr(err, 1u << 18);
+        sd[threadIdx.x] = ok ? d : ~0ull;
+        ss[threadIdx.x] = sidx;
     }
     __syncthreads();
-    uint32_t *o = out + q0 * kRecWords;
-    uint32_t v[kRecWords];  // every load of the thread in flight before the stores
+    uint32_t v[kRecWords];
 #pragma unroll
     for (int u = 0; u < kRecWords; u++) {
         const uint32_t g = threadIdx.x + kTB * u, r = g / kRecWords, d = g - r * kRecWords;
         v[u] = 0;
-        if (r < nr && sj[r] != ~0ull) v[u] = A[sj[r] * kRecWords + d];
-    }
-#pragma unroll
-    for (int u = 0; u < kRecWords; u++) {
-        const uint32_t g = threadIdx.x + kTB * u, r = g / kRecWords;
-        if (r < nr && sj[r] != ~0ull) o[g] = v[u];
-    }
-}
-
-// A[dest[t]] = R[t] for the entries t of a block of kTB (positions through LDS).
-__global__ __launch_bounds__(kTB) void k_tie_scatter(const uint32_t *R, const uint64_t *dest, uint64_t m,
-                                                     uint64_t n, uint32_t *A) {
-    __shared__ uint64_t sj[kTB];
-    const uint64_t t0 = (uint64_t)blockIdx.x * kTB;
-    const uint32_t nr = (uint32_t)min<uint64_t>(kTB, m - t0);
-    if (threadIdx.x < nr) sj[threadIdx.x] = dest[t0 + threadIdx.x];
-    __syncthreads();
-    const uint32_t *rr = R + t0 * kRecWords;
-    uint32_t v[kRecWords];
-#pragma unroll
-    for (int u = 0; u < kRecWords; u++) {
-        const uint32_t g = threadIdx.x + kTB * u;
-        v[u] = g < nr * (uint32_t)kRecWords ? rr[g] : 0u;
+        if (r < nr && sd[r] != ~0ull) v[u] = in[(uint64_t)ss[r] * kRecWords + d];
     }
 #pragma unroll
     for (int u = 0; u < kRecWords; u++) {
         const uint32_t g = threadIdx.x + kTB * u, r = g / kRecWords, d = g - r * kRecWords;
-        if (r < nr && sj[r] < n) A[sj[r] * kRecWords + d] = v[u];
+        if (r < nr && sd[r] != ~0ull) A[sd[r] * kRecWords + d] = v[u];
     }
 }
 
@@ -304,12 +373,12 @@ size_t a256(size_t v) { return (v + 255) / 256 * 256; }
 struct RoundTables {
     uint8_t *P;
     uint32_t *cnt_in, *cnt_start;
-    uint64_t *off_in, *off_start, *totals;
+    uint64_t *off_in, *off_start, *grp, *totals;
 };
 
 size_t tables_bytes(uint64_t n) {
     const uint64_t nb = (n + kTSpan - 1) / kTSpan;
-    return a256(n) + 2 * a256(nb * 4) + 2 * a256(nb * 8) + 256;
+    return a256(n) + 2 * a256(nb * 4) + 2 * a256(nb * 8) + a256(2 * kSB * 8) + 256;
 }
 
 RoundTables bind_tables(void *base, uint64_t n) {
@@ -321,39 +390,50 @@ RoundTables bind_tables(void *base, uint64_t n) {
     r.cnt_start = reinterpret_cast<uint32_t *>(b); b += a256(nb * 4);
     r.off_in = reinterpret_cast<uint64_t *>(b); b += a256(nb * 8);
     r.off_start = reinterpret_cast<uint64_t *>(b); b += a256(nb * 8);
+    r.grp = reinterpret_cast<uint64_t *>(b); b += a256(2 * kSB * 8);  // group sums of the count scan
     r.totals = reinterpret_cast<uint64_t *>(b);  // tie count, run count, error word
     return r;
 }
 
-// Rounds over the tie runs of the prefix-sorted records in A (n records);
-// tb.P (n bytes) holds the first round's tie marks and is reused by later
-// rounds.  The entries live in the stream's pooled slot 1.
-int resolve_ties(uint32_t *A, uint64_t n, uint32_t key_bytes, hipStream_t s, const Tune &t, const RoundTables &tb) {
+// Rounds over the tie runs of the prefix-sorted records in A (n records,
+// sorted from the input `in` on stream s, whose pooled workspace still holds
+// that sort's order); tb.P (n bytes) holds the first round's tie marks and is
+// reused by later rounds.  The entries live in the stream's pooled slot 1.
+int resolve_ties(const uint32_t *in, uint32_t *A, uint64_t n, uint32_t key_bytes, hipStream_t s, const Tune &t,
+                 const RoundTables &tb) {
     int rc;
     uint8_t *P = tb.P;
     uint32_t *cnt_in = tb.cnt_in, *cnt_start = tb.cnt_start;
     uint64_t *off_in = tb.off_in, *off_start = tb.off_start;
-    uint64_t *totals = tb.totals;
+    uint64_t *grp = tb.grp, *totals = tb.totals;
     // error word next to the totals: the sorts' device-side guard words
-    // (capacity guards, bounded waits) and the entry gather's bound check
+    // (capacity guards, bounded waits) and the rounds' index checks
     uint32_t *err = reinterpret_cast<uint32_t *>(totals + 2);
     hipError_t e0 = hipMemsetAsync(err, 0, 4, s);
     if (e0 != hipSuccess) return hip_fail(e0, "leyenda_sort_keyed: error word");
     if ((rc = guard_or_pooled(s, err))) return rc;  // the prefix sort
-    // scratch of the rounds (room for the first round's count, which is the largest):
-    // the entry sort's workspace, the entries' keys (Kh, Kl) and in sorted order
-    // (SKh, SKl), the records of the runs in sorted order (R), the entries' positions
+    const uint32_t *pidx = pooled_sort_idx(s, n);   // its input index per output position
+    if (!pidx) return fail(LEYENDA_EINTERNAL, "leyenda_sort_keyed: the prefix sort's order is not in its workspace");
+    // scratch of the rounds, sized by the first round's count (the largest):
+    // the entry sort's workspace; the entries' keys (Kh, Kl) and in sorted
+    // order (SKh, SKl); their records' input indices (srcx) and in sorted order
+    // (src_s); their first-round entry numbers by round parity (e0x); per
+    // first-round entry its position (slot0) and final input index (final_src)
     char *ws = nullptr;
-    uint64_t *Kh = nullptr, *SKh = nullptr;
-    uint32_t *Kl = nullptr, *SKl = nullptr, *R = nullptr;
-    uint64_t *dest[2] = {nullptr, nullptr};  // positions of the entries, by round parity
+    uint64_t *Kh = nullptr, *SKh = nullptr, *slot0 = nullptr;
+    uint32_t *Kl = nullptr, *SKl = nullptr, *srcx = nullptr, *src_s = nullptr, *final_src = nullptr;
+    uint32_t *e0x[2] = {nullptr, nullptr};
     uint64_t cap = 0, nc = n;
     int r = 0;
     for (uint32_t p = kKeyBytes; p < key_bytes; p += kWindow, r++) {
         const uint64_t nb = (nc + kTSpan - 1) / kTSpan;
         if (r) k_tie_eq<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(SKh, SKl, nc, P);
+        const uint64_t ng = (nb + kSG - 1) / kSG;
         k_tie_count<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(P, nc, cnt_in, cnt_start);
-        k_tie_scan<<<dim3(1), dim3(kSB), 0, s>>>(cnt_in, cnt_start, nb, off_in, off_start, totals);
+        k_tie_scan_up<<<dim3((uint32_t)ng), dim3(kSB), 0, s>>>(cnt_in, cnt_start, nb, grp, grp + kSB);
+        k_tie_scan_top<<<dim3(1), dim3(kSB), 0, s>>>(grp, grp + kSB, ng, totals);
+        k_tie_scan_down<<<dim3((uint32_t)ng), dim3(kSB), 0, s>>>(cnt_in, cnt_start, nb, grp, grp + kSB, off_in,
+                                                                  off_start);
         uint64_t h[3] = {0, 0, 0};  // tie count, run count, error word
         hipError_t e = hipMemcpyAsync(h, totals, sizeof(h), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -366,34 +446,43 @@ int resolve_ties(uint32_t *A, uint64_t n, uint32_t key_bytes, hipStream_t s, con
             cap = m;
             const size_t wsb = a256(plan_layout(cap, 1, t).total);
             void *base = nullptr;
-            if ((rc = get_aux(s, 1, wsb + 2 * a256(cap * 8) + 2 * a256(cap * 4) + a256(cap * kRec) + 2 * a256(cap * 8),
-                              &base)))
-                return rc;
+            if ((rc = get_aux(s, 1, wsb + 3 * a256(cap * 8) + 7 * a256(cap * 4), &base))) return rc;
             char *b = static_cast<char *>(base);
             ws = b; b += wsb;
             Kh = reinterpret_cast<uint64_t *>(b); b += a256(cap * 8);
             SKh = reinterpret_cast<uint64_t *>(b); b += a256(cap * 8);
+            slot0 = reinterpret_cast<uint64_t *>(b); b += a256(cap * 8);
             Kl = reinterpret_cast<uint32_t *>(b); b += a256(cap * 4);
             SKl = reinterpret_cast<uint32_t *>(b); b += a256(cap * 4);
-            R = reinterpret_cast<uint32_t *>(b); b += a256(cap * kRec);
-            dest[0] = reinterpret_cast<uint64_t *>(b); b += a256(cap * 8);
-            dest[1] = reinterpret_cast<uint64_t *>(b);
+            srcx = reinterpret_cast<uint32_t *>(b); b += a256(cap * 4);
+            src_s = reinterpret_cast<uint32_t *>(b); b += a256(cap * 4);
+            final_src = reinterpret_cast<uint32_t *>(b); b += a256(cap * 4);
+            e0x[0] = reinterpret_cast<uint32_t *>(b); b += a256(cap * 4);
+            e0x[1] = reinterpret_cast<uint32_t *>(b);
         }
         // the entries go straight into the tuple buffers of a workspace laid out for m tuples
         const Layout Lm = plan_layout(m, 1, t);
         uint64_t *TH = reinterpret_cast<uint64_t *>(ws + Lm.off_H0);
         uint64_t *TL = reinterpret_cast<uint64_t *>(ws + Lm.off_L0);
         const uint32_t *idx = reinterpret_cast<const uint32_t *>(ws + Lm.off_idx);
-        k_tie_emit<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(A, P, nc, r ? dest[(r - 1) & 1] : nullptr, p, key_bytes,
-                                                             off_in, off_start, TH, TL, Kh, Kl, dest[r & 1]);
+        k_tie_emit<<<dim3((uint32_t)nb), dim3(kTB), 0, s>>>(
+            reinterpret_cast<const uint8_t *>(A), reinterpret_cast<const uint8_t *>(in), n, P, nc, pidx,
+            r ? src_s : nullptr, r ? e0x[(r - 1) & 1] : nullptr, p, key_bytes, off_in, off_start, TH, TL, Kh, Kl,
+            srcx, e0x[r & 1], slot0, err);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: entries");
         if ((rc = sort_tuples_ws(m, s, t, ws))) return rc;
         if ((e = launch_guard_or(ws, m, t, err, s)) != hipSuccess) return hip_fail(e, "guard kernel");
         const uint64_t blocks = (m + kTB - 1) / kTB;
-        k_tie_gather<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(A, n, idx, dest[r & 1], Kh, Kl, m, R, SKh, SKl, err);
-        k_tie_scatter<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(R, dest[r & 1], m, n, A);
-        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: permute");
+        k_tie_perm<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(idx, m, Kh, Kl, srcx, e0x[r & 1], cap, SKh, SKl,
+                                                                 src_s, final_src, err);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: order");
         nc = m;  // the next round looks only inside these runs
+    }
+    if (cap) {  // the tied positions' records, from the input
+        const uint64_t blocks = (cap + kTB - 1) / kTB;
+        k_tie_final<<<dim3((uint32_t)blocks), dim3(kTB), 0, s>>>(in, n, slot0, final_src, cap, A, err);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "leyenda_sort_keyed: records");
     }
     uint32_t eh = 0;
     hipError_t e = hipMemcpyAsync(&eh, err, 4, hipMemcpyDeviceToHost, s);
@@ -423,5 +512,6 @@ extern "C" int leyenda_sort_keyed(const void *records_dev, uint64_t n, uint32_t 
     if ((rc = get_aux(s, 0, tables_bytes(n), &tab))) return rc;
     const RoundTables tb = bind_tables(tab, n);
     if ((rc = sort_device(records_dev, n, out_dev, s, t, kKeyBytes, tb.P))) return rc;
-    return resolve_ties(static_cast<uint32_t *>(out_dev), n, key_bytes, s, t, tb);
+    return resolve_ties(static_cast<const uint32_t *>(records_dev), static_cast<uint32_t *>(out_dev), n, key_bytes, s,
+                        t, tb);
 }

@@ -34,6 +34,10 @@ void apply_key_mask(Work &w, uint32_t key_bytes);
 hipError_t launch_guard_or(const void *ws, uint64_t n, const Tune &t, uint32_t *acc, hipStream_t s);
 // The same for the last sort on `stream`'s pooled workspace (no-op if none ran).
 int guard_or_pooled(hipStream_t stream, uint32_t *acc);
+// Input record index per output position of the last sort of n records on
+// `stream`'s pooled workspace (valid until the next sort there); null when no
+// such sort ran or its indices name record-pool slots.
+const uint32_t *pooled_sort_idx(hipStream_t stream, uint64_t n);
 // Sorts n (key, index) tuples already written to buffer 0 (H[0], L[0]) of a
 // workspace of plan_layout(n, 1, t).total bytes; the indices in key order end
 // up in the workspace's idx array.  One output part, on stream s.

@@ -518,6 +518,13 @@ int guard_or_pooled(hipStream_t stream, uint32_t *acc) {
     return e == hipSuccess ? LEYENDA_OK : hip_fail(e, "guard kernel");
 }
 
+const uint32_t *pooled_sort_idx(hipStream_t stream, uint64_t n) {
+    void *ws = nullptr;
+    Layout L{};
+    if (find_workspace(stream, &ws, &L) != LEYENDA_OK || L.n != n || L.first_pass == kFirstRecords) return nullptr;
+    return reinterpret_cast<const uint32_t *>(static_cast<const char *>(ws) + L.off_idx);
+}
+
 int sort_tuples_ws(uint64_t n, hipStream_t s, const Tune &t, void *ws) {
     if (n == 0) return LEYENDA_OK;
     const Layout L = plan_layout(n, 1, t);

@@ -3,7 +3,9 @@ oracle's stable sort on K-byte keys.
 
 The GPU path sorts by the 10-byte prefix, then resolves runs of equal leading
 bytes six key bytes per round with one stable sort of (run number, window
-bytes, position) entries.  This model takes the same steps in numpy, so the
+bytes, position) entries; the rounds carry record indices, and the tied
+positions take their records from the input once at the end.  This model
+takes the same steps in numpy, so the
 reasoning behind them (run numbering, windows masked to the key, only the
 previous round's entries looked at, stability through positions) is checked on
 many inputs without a GPU; the GPU tests compare the kernels with the oracle.
@@ -22,15 +24,17 @@ def _stable_order(keys10: np.ndarray) -> np.ndarray:
 
 
 def model_keyed(rec: np.ndarray, kb: int) -> np.ndarray:
-    out = oracle.sort(rec)  # the 10-byte prefix sort (stable)
+    out, perm = oracle.sort(rec, return_perm=True)  # the 10-byte prefix sort (stable) and its order
     n = out.shape[0]
     # first round's tie marks: P[c] = record c ties record c - 1 on bytes 0..9
     P = np.zeros(n, dtype=bool)
     P[1:] = (out[1:, :10] == out[:-1, :10]).all(axis=1)
-    cand = np.arange(n)  # candidate c -> output position
+    cand_src = perm.astype(np.int64)  # candidate c -> input index of the record at its position
+    cand_e0 = None                    # candidate c -> first-round entry owning its position
+    slot0 = final_src = None          # per first-round entry: its position, its final record
     p = 10
     while p < kb:
-        nc = cand.size
+        nc = cand_src.size
         eq_prev = P[:nc].copy()
         eq_next = np.zeros(nc, dtype=bool)
         eq_next[:-1] = P[1:nc]
@@ -40,21 +44,29 @@ def model_keyed(rec: np.ndarray, kb: int) -> np.ndarray:
             break
         run = np.cumsum(starts) - 1  # the run holding c began at the latest start
         sel = np.nonzero(in_run)[0]
-        pos = cand[sel]
+        src = cand_src[sel]
+        if slot0 is None:  # first round: entries are output positions
+            e0 = np.arange(sel.size)
+            slot0 = sel.copy()
+            final_src = src.copy()
+        else:
+            e0 = cand_e0[sel]
         ent = np.zeros((sel.size, 10), dtype=np.uint8)
         ent[:, :4] = run[sel].astype(">u4").view(np.uint8).reshape(-1, 4)
-        w = [b for b in range(p, p + 6)]
-        for k, b in enumerate(w):
+        for k, b in enumerate(range(p, p + 6)):
             if b < kb:
-                ent[:, 4 + k] = out[pos, b]
+                ent[:, 4 + k] = rec[src, b]
         order = _stable_order(ent)  # entries in position order; the sort is stable
-        src = pos[order]
-        out[pos] = out[src]  # the runs' records in entry order, written over their runs
+        s_sorted = src[order]
+        # the q-th sorted entry takes the position of entry q (first-round entry e0[q])
+        final_src[e0] = s_sorted
         e2 = ent[order]
         P = np.zeros(sel.size, dtype=bool)  # later rounds: neighbours of sorted entries
         P[1:] = (e2[1:] == e2[:-1]).all(axis=1)
-        cand = pos  # the records at these positions, in sorted-entry order
+        cand_src, cand_e0 = s_sorted, e0
         p += 6
+    if slot0 is not None:  # the tied positions take their records from the input
+        out[slot0] = rec[final_src]
     return out
 
 
