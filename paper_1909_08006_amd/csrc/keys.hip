@@ -263,25 +263,36 @@ __global__ __launch_bounds__(kTB) void k_tie_emit(const uint8_t *A, const uint8_
                                                   const uint64_t *off_start, uint64_t *TH, uint64_t *TL,
                                                   uint64_t *Kh, uint32_t *Kl, uint32_t *srcx, uint32_t *e0x,
                                                   uint64_t *slot0, uint32_t *err) {
-    const uint64_t c0 = (uint64_t)blockIdx.x * kTSpan + (uint64_t)threadIdx.x * kTPer;
+    // the block's entries are the contiguous range [off_in[block], + total):
+    // their candidates are listed in LDS first, then each thread takes every
+    // kTB-th entry, so the entry stores are contiguous across the block
+    __shared__ uint16_t s_c[kTSpan];    // candidate offset in the block
+    __shared__ uint16_t s_run[kTSpan];  // runs started in the block up to it (0: a run from an earlier block)
+    const uint64_t cb = (uint64_t)blockIdx.x * kTSpan;
+    const uint32_t c_off = threadIdx.x * kTPer;
     uint32_t r, st;
-    tie_bits(P, nc, c0, &r, &st);
+    tie_bits(P, nc, cb + c_off, &r, &st);
     uint32_t ei, es, ti, ts;
     block_scan2((uint32_t)__popc(r), (uint32_t)__popc(st), &ei, &es, &ti, &ts);
-    uint64_t t = off_in[blockIdx.x] + ei;                   // entry number of the thread's first tied candidate
-    const uint64_t runs_before = off_start[blockIdx.x] + es;  // runs started before c0
+    for (uint32_t j = ei; r; j++) {
+        const int k = __builtin_ctz(r);
+        r &= r - 1;
+        s_c[j] = (uint16_t)(c_off + (uint32_t)k);
+        s_run[j] = (uint16_t)(es + (uint32_t)__popc(st & ((2u << k) - 1u)));
+    }
+    __syncthreads();
+    const uint64_t t0 = off_in[blockIdx.x], runs0 = off_start[blockIdx.x];
     // key bytes past the key read as zero: byte mask of the six window bytes
     uint32_t keep = 0;
     for (uint32_t k = 0; k < kWindow; k++)
         if (p + k < key_bytes) keep |= 1u << k;
-    while (r) {
-        const int k = __builtin_ctz(r);
-        r &= r - 1;
-        const uint64_t c = c0 + (uint64_t)k;
+    for (uint32_t j = threadIdx.x; j < ti; j += kTB) {
+        const uint64_t c = cb + s_c[j];
+        const uint64_t t = t0 + j;
+        // the run holding c began at the latest start at or before c
+        const uint32_t run = (uint32_t)(runs0 + s_run[j] - 1u);
         const uint32_t src = src_prev ? src_prev[c] : pidx[c];
         const uint32_t e0 = src_prev ? e0_prev[c] : (uint32_t)t;
-        // the run holding c began at the latest start at or before c
-        const uint32_t run = (uint32_t)(runs_before + (uint32_t)__popc(st & ((2u << k) - 1u)) - 1u);
         const bool ok = src < n;
         if (!ok) atomicOr(err, 1u << 17);
         // the window's six bytes from two aligned dwords (the record offset and
@@ -293,7 +304,7 @@ __global__ __launch_bounds__(kTB) void k_tie_emit(const uint8_t *A, const uint8_
             const uint64_t v = ((uint64_t)w[1] << 32) | w[0];
             const uint32_t sh = (uint32_t)(o & 3u) * 8u;
 #pragma unroll
-            for (uint32_t j = 0; j < kWindow; j++) b6[j] = (keep >> j & 1u) ? (uint32_t)(v >> (sh + 8u * j)) & 0xFFu : 0u;
+            for (uint32_t q = 0; q < kWindow; q++) b6[q] = (keep >> q & 1u) ? (uint32_t)(v >> (sh + 8u * q)) & 0xFFu : 0u;
         }
         const uint64_t h = ((uint64_t)run << 32) | (b6[0] << 24) | (b6[1] << 16) | (b6[2] << 8) | b6[3];
         const uint32_t wl = (b6[4] << 8) | b6[5];
@@ -304,7 +315,6 @@ __global__ __launch_bounds__(kTB) void k_tie_emit(const uint8_t *A, const uint8_
         srcx[t] = src;
         e0x[t] = e0;
         if (!src_prev) slot0[t] = c;
-        t++;
     }
 }
 
