@@ -1675,12 +1675,26 @@ template <bool TIES>
 __device__ __forceinline__ void gather_body(const uint8_t *rec, uint64_t n_rec, const uint32_t *idx, uint8_t *out,
                                             uint64_t n, uint8_t *ties, int has_prev) {
     __shared__ uint32_t sidx[kWG];
-    __shared__ uint32_t skey[TIES ? 3 * kWG : 1];
+    __shared__ uint32_t skey[TIES ? 3 * (kWG / 64) : 1];  // key words of each wave's last record
     const uint64_t g0 = (uint64_t)blockIdx.x * kWG;
     const uint32_t nr = (uint32_t)min<uint64_t>(kWG, n - g0);
-    if (threadIdx.x < nr) sidx[threadIdx.x] = idx[g0 + threadIdx.x];
-    __syncthreads();
     const uint32_t *src = reinterpret_cast<const uint32_t *>(rec);
+    // TIES: thread r loads key bytes 0..9 of output record g0 + r (dwords 0, 1
+    // and half of 2) apart from the copy below, so the copy keeps the plain
+    // gather's registers; the loads hit the lines the copy fetches
+    uint32_t k0 = 0, k1 = 0, k2 = 0;
+    bool have = false;
+    if (threadIdx.x < nr) {
+        const uint32_t j = idx[g0 + threadIdx.x];
+        sidx[threadIdx.x] = j;
+        if (TIES && j < n_rec) {
+            k0 = src[(uint64_t)j * 25];
+            k1 = src[(uint64_t)j * 25 + 1];
+            k2 = src[(uint64_t)j * 25 + 2] & 0xFFFFu;
+            have = true;
+        }
+    }
+    __syncthreads();
     uint32_t *dst = reinterpret_cast<uint32_t *>(out) + g0 * 25;
     uint32_t v[25];
 #pragma unroll
@@ -1689,38 +1703,37 @@ __device__ __forceinline__ void gather_body(const uint8_t *rec, uint64_t n_rec, 
         v[u] = 0;
         if (r < nr && sidx[r] < n_rec) v[u] = src[(uint64_t)sidx[r] * 25 + kk];
     }
-    if (TIES) {  // key bytes 0..9 of each record to LDS (dwords 0, 1 and half of 2)
-#pragma unroll
-        for (int u = 0; u < 25; u++) {
-            const uint32_t q = threadIdx.x + kWG * u, r = q / 25u, kk = q - 25u * r;
-            if (r < nr && kk < 3) skey[3 * r + kk] = kk == 2 ? (v[u] & 0xFFFFu) : v[u];
-        }
-    }
 #pragma unroll
     for (int u = 0; u < 25; u++) {
         const uint32_t q = threadIdx.x + kWG * u, r = q / 25u;
         if (r < nr) __builtin_nontemporal_store(v[u], dst + q);
     }
     if (TIES) {
+        // the previous record's key: lane l - 1 of the wave, the last lane of
+        // the previous wave through LDS, or (first record of the block) read
+        // through the index array (idx[-1]: the last record of the part before)
+        const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        uint32_t p0 = __shfl_up(k0, 1), p1 = __shfl_up(k1, 1), p2 = __shfl_up(k2, 1);
+        bool phave = __shfl_up(have ? 1 : 0, 1) != 0;
+        if (lane == 63) { skey[3 * wv] = have ? k0 : ~0u; skey[3 * wv + 1] = k1; skey[3 * wv + 2] = have ? k2 : ~0u; }
         __syncthreads();
         const uint32_t r = threadIdx.x;
         if (r < nr) {
             const uint64_t g = g0 + r;
-            uint32_t p0 = 0, p1 = 0, p2 = 0;
-            bool have = true;
-            if (r > 0) {
-                p0 = skey[3 * r - 3]; p1 = skey[3 * r - 2]; p2 = skey[3 * r - 1];
-            } else if (g > 0 || has_prev) {
-                const uint32_t j = idx[(int64_t)g - 1];  // idx[-1]: the last record of the part before
-                if (j < n_rec) {
-                    p0 = src[(uint64_t)j * 25]; p1 = src[(uint64_t)j * 25 + 1]; p2 = src[(uint64_t)j * 25 + 2] & 0xFFFFu;
-                } else {
-                    have = false;
+            if (lane == 0 && wv > 0) {
+                p0 = skey[3 * wv - 3]; p1 = skey[3 * wv - 2]; p2 = skey[3 * wv - 1];
+                phave = p2 != ~0u;  // a key's third word has its upper half clear
+            } else if (r == 0) {
+                phave = false;
+                if (g > 0 || has_prev) {
+                    const uint32_t j = idx[(int64_t)g - 1];
+                    if (j < n_rec) {
+                        p0 = src[(uint64_t)j * 25]; p1 = src[(uint64_t)j * 25 + 1]; p2 = src[(uint64_t)j * 25 + 2] & 0xFFFFu;
+                        phave = true;
+                    }
                 }
-            } else {
-                have = false;
             }
-            ties[g] = (have && p0 == skey[3 * r] && p1 == skey[3 * r + 1] && p2 == skey[3 * r + 2]) ? 1 : 0;
+            ties[g] = (have && phave && p0 == k0 && p1 == k1 && p2 == k2) ? 1 : 0;
         }
     }
 }
