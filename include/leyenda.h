@@ -100,8 +100,8 @@ uint64_t leyenda_noalloc_max_records(void);
  * records_dev (which must stay unchanged until the call returns).  Buffers and
  * errors as leyenda_sort, plus LEYENDA_EINVAL for key_bytes outside 1..100 and
  * LEYENDA_ENOMEM when the rounds' scratch (about 92 bytes per record inside a
- * tie run, plus one byte per record and 24 bytes per 1,024 records, kept per
- * stream between calls) cannot be allocated.  With key_bytes > 10 the call
+ * tie run, plus one byte per record and about 6 bytes per 1,024 records, kept
+ * per stream between calls) cannot be allocated.  With key_bytes > 10 the call
  * returns after the stream has drained (it reads each round's tie count on the
  * host). */
 int leyenda_sort_keyed(const void *records_dev, uint64_t n, uint32_t key_bytes, void *out_dev, void *stream);
