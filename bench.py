@@ -336,6 +336,65 @@ def ascii_keys(ley, torch, datagen, steps: int) -> dict:
             "output_keys_ordered": ok, "guard": guard}
 
 
+def pcie_rates(ley, nbytes: int = 2_000_000_000, tries: int = 3) -> dict:
+    """PCIe rates between pinned host memory and device memory, the way the
+    external calls move data: hipMemcpyAsync on non-blocking streams of the
+    HIP runtime the library uses (host clock, best of `tries`): each way alone,
+    and both ways at once on two streams.  Streams share the process's few
+    hardware queues and copy engines, so one pair can serialise its copies; the
+    both-ways attempts go over every pair of four streams."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    hip.hipMalloc.argtypes = [ctypes.POINTER(vp), sz]
+    hip.hipFree.argtypes = [vp]
+    hip.hipStreamCreateWithFlags.argtypes = [ctypes.POINTER(vp), ctypes.c_uint]
+    hip.hipStreamDestroy.argtypes = [vp]
+    hip.hipStreamSynchronize.argtypes = [vp]
+    hip.hipMemcpyAsync.argtypes = [vp, vp, sz, ctypes.c_int, vp]
+    h2d_kind, d2h_kind = 1, 2
+    host = [ley.pinned_empty(nbytes), ley.pinned_empty(nbytes)]
+    dev = [vp(), vp()]
+    streams = [vp() for _ in range(4)]
+    try:
+        for d in dev:
+            if hip.hipMalloc(ctypes.byref(d), nbytes) != 0:
+                raise RuntimeError("hipMalloc failed")
+        for st in streams:
+            if hip.hipStreamCreateWithFlags(ctypes.byref(st), 1) != 0:
+                raise RuntimeError("hipStreamCreateWithFlags failed")
+        h = [vp(t.data_ptr()) for t in host]
+
+        def run(copies):
+            t0 = time.perf_counter()
+            for dst, src, kind, st in copies:
+                if hip.hipMemcpyAsync(dst, src, nbytes, kind, st) != 0:
+                    raise RuntimeError("hipMemcpyAsync failed")
+            for st in streams:
+                if hip.hipStreamSynchronize(st) != 0:
+                    raise RuntimeError("hipStreamSynchronize failed")
+            return time.perf_counter() - t0
+
+        rates = {}
+        for name, kind, dst, src in (("h2d", h2d_kind, dev[0], h[0]), ("d2h", d2h_kind, h[0], dev[0])):
+            best = min(run([(dst, src, kind, streams[0])]) for _ in range(tries))
+            rates[name] = round(nbytes / best / 1e9, 2)
+        pairs = [(a, b) for a in range(4) for b in range(4) if a != b]
+        best = min(run([(dev[0], h[0], h2d_kind, streams[a]), (h[1], dev[1], d2h_kind, streams[b])])
+                   for a, b in pairs)
+        rates["both_ways"] = round(2 * nbytes / best / 1e9, 2)
+        return rates
+    finally:
+        for st in streams:
+            if st.value:
+                hip.hipStreamDestroy(st)
+        for d in dev:
+            if d.value:
+                hip.hipFree(d)
+        for t in host:
+            ley.pinned_free(t)
+
+
 def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9) -> dict:
     """The 60 GB limited-memory workload: 600,000,000 records in pinned host
     memory, 30 GB device budget, sorted runs written over the input, then the
@@ -343,49 +402,12 @@ def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9
     again into a second pinned buffer when the host can pin it).  Bound: PCIe, 200 B/record each way, the two directions
     overlapped at their measured single-direction rates.  The merge runs twice
     into the same output: first into fresh memory (its first-touch page faults
-    included), then into the now resident buffer (a reused output).  Then the
-    keys-only variant on the regenerated input.  (n and budget: smaller
-    instances of the same workload, e.g. under a profiler.)"""
+    included), then into the now resident buffer (a reused output).  Then, each
+    on the regenerated input, runs + merge in one call and the keys-only
+    variant.  (n and budget: smaller instances of the same workload, e.g. under
+    a profiler.)"""
     import numpy as np
-    # PCIe rates with a pinned 2 GB buffer (host clock, best of several): each
-    # way alone, and both ways at once on two streams.  Streams share the
-    # process's few hardware queues, so one pair can serialise its copies; the
-    # both-ways attempts go over different pairs of four streams.
-    part = ley.pinned_empty(2_000_000_000)
-    part2 = ley.pinned_empty(2_000_000_000)
-    dev = torch.empty(2_000_000_000, dtype=torch.uint8, device="cuda:0")
-    dev2 = torch.empty_like(dev)
-    streams = [torch.cuda.Stream() for _ in range(4)]
-    pairs = [(0, 1), (2, 3), (0, 2), (1, 3), (0, 3), (1, 2)]
-    attempt = [0]
-
-    def both():
-        s1, s2 = (streams[i] for i in pairs[attempt[0] % len(pairs)])
-        attempt[0] += 1
-        with torch.cuda.stream(s1):
-            dev.copy_(part, non_blocking=True)
-        with torch.cuda.stream(s2):
-            part2.copy_(dev2, non_blocking=True)
-        s1.synchronize()
-        s2.synchronize()
-
-    rates = {}
-    for name, fn, nbytes, tries in (("h2d", lambda: dev.copy_(part, non_blocking=True), 2e9, 3),
-                                    ("d2h", lambda: part.copy_(dev, non_blocking=True), 2e9, 3),
-                                    ("both_ways", both, 4e9, len(pairs))):
-        best = None
-        for _ in range(tries):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            best = dt if best is None else min(best, dt)
-        rates[name] = round(nbytes / best / 1e9, 2)
-    del dev, dev2
-    ley.pinned_free(part)
-    ley.pinned_free(part2)
-    torch.cuda.empty_cache()
+    rates = pcie_rates(ley)
     log(f"external: generating {n:,} records (60 GB, seed {datagen.SEED_EXTERNAL}) ...")
     a = ley.pinned_empty(n * 100)
     datagen.fill_uniform(a.data_ptr(), n, datagen.SEED_EXTERNAL)
@@ -404,7 +426,19 @@ def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9
     keys = out[::step, :10]
     ok = bool(all(bytes(keys[i]) <= bytes(keys[i + 1]) for i in range(len(keys) - 1)))
     del keys, runs
-    # keys-only variant on the same (regenerated) input, into the same output buffer
+    # runs + merge in one call on the same (regenerated) input, the last run
+    # kept on the device; runs over the input
+    log("external: runs + merge in one call ...")
+    datagen.fill_uniform(a.data_ptr(), n, datagen.SEED_EXTERNAL)
+    t0 = time.perf_counter()
+    ley.sort_external(a, budget, host_runs=a, host_out=torch.from_numpy(out).view(-1))
+    t_one = time.perf_counter() - t0
+    keys = out[::step, :10]
+    ok_one = bool(all(bytes(keys[i]) <= bytes(keys[i + 1]) for i in range(len(keys) - 1)))
+    del keys
+    # keys-only variant on the same (regenerated) input, into the same output
+    # buffer; after the copy-engine paths, so each of those starts from the
+    # same state (a freshly written input)
     log("external: keys-only variant ...")
     datagen.fill_uniform(a.data_ptr(), n, datagen.SEED_EXTERNAL)
     keys_skip = None
@@ -418,15 +452,7 @@ def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9
         del keys
     except ley.LeyendaError as exc:  # e.g. a budget below the tuples of the whole input
         keys_skip = str(exc)
-    # runs + merge in one call on the same input (the keys-only variant left it
-    # as it was), the last run kept on the device; runs over the input
-    log("external: runs + merge in one call ...")
-    t0 = time.perf_counter()
-    ley.sort_external(a, budget, host_runs=a, host_out=torch.from_numpy(out).view(-1))
-    t_one = time.perf_counter() - t0
-    keys = out[::step, :10]
-    ok_one = bool(all(bytes(keys[i]) <= bytes(keys[i + 1]) for i in range(len(keys) - 1)))
-    del keys, out
+    del out
     # both paths again with a pinned output buffer (the copy engine writes the
     # host buffer directly, no bounce buffers or host copies), if the host can
     # pin a second 60 GB: keys-only on the input, then runs and merge
@@ -465,8 +491,8 @@ def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9
     ley.pinned_free(a)
     # 200 B/record each way (runs: up + down; merge: up + down); the two directions
     # at their own single-direction rates, fully overlapped, is a lower bound on
-    # any box (the rate of two concurrent copies issued from torch has varied
-    # from box to box, 57-97 GB/s, while the runs moved 89 GB/s both ways)
+    # any box (two concurrent copies have reached 97 GB/s together, not the
+    # 115 GB/s of the two single-direction rates)
     both_bound = max(n * 200 / (rates["h2d"] * 1e9), n * 200 / (rates["d2h"] * 1e9))
     # keys-only: 200 B/record up (the input read once in order, then every
     # record again by the gather) and 100 B/record down
