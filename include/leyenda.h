@@ -23,7 +23,12 @@
  *   - Record buffers are arrays of n * 100 bytes, 4-byte aligned.  The caller
  *     owns every buffer passed in; the library owns only its scratch memory,
  *     drawn from a per-device, per-stream pool that it keeps between calls
- *     (released by leyenda_release_workspaces()).
+ *     (released by leyenda_release_workspaces()).  The external calls
+ *     (leyenda_sort_runs, leyenda_merge, leyenda_sort_external,
+ *     leyenda_sort_external_keys) likewise keep one device arena per device,
+ *     at most the last call's budget, and one set of pinned bounce buffers
+ *     (512 MB) with its host copy threads; a call reuses them when they fit
+ *     its budget, and makes its own when another call holds them.
  *   - On error, output buffers hold unspecified bytes, but nothing is written
  *     outside them.
  */
@@ -382,7 +387,8 @@ int leyenda_profile_read(double *phase_ms, uint64_t *calls);
 
 const char *leyenda_status_string(int status);
 const char *leyenda_last_error(void);
-/* Frees every cached workspace (synchronizes the device first). */
+/* Frees every cached workspace, external arena and bounce buffer not in use
+ * by a running call (synchronizes the device first). */
 int leyenda_release_workspaces(void);
 
 /* ---------------------------------------------------------------------------

@@ -21,6 +21,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -282,10 +284,88 @@ void *pinned_device_ptr(const void *p) {
 // chunk c + 1 never waits for the download of chunk c - 1; the others two).
 constexpr int kPipeBufs = 3;
 
+// Device memory of the external calls, kept between calls, one arena per
+// device: allocating and freeing tens of GB in every call cost 0.1-0.4 s of
+// a 60 GB sort's stages.  A call takes the kept arena when it holds at least
+// what the call needs and no more than the call's budget (the call stays
+// within its budget); otherwise the arena is replaced.  A call that finds the
+// arena in use (another external call on the device) allocates its own and
+// frees it when it returns.  leyenda_release_workspaces frees the arenas.
+struct ExtArena {
+    void *p = nullptr;
+    size_t bytes = 0;
+    bool busy = false;
+};
+std::mutex g_ext_mu;
+ExtArena g_ext[64];
+
+int current_device(int *dev) {
+    const hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (*dev < 0 || *dev >= 64) return fail(LEYENDA_EINVAL, "device %d out of range", *dev);
+    return LEYENDA_OK;
+}
+
+int ext_arena_take(size_t bytes, size_t budget, void **out, bool *pooled) {
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc) return rc;
+    *out = nullptr;
+    *pooled = false;
+    {
+        std::lock_guard<std::mutex> lk(g_ext_mu);
+        ExtArena &a = g_ext[dev];
+        if (!a.busy) {
+            if (a.p && a.bytes >= bytes && a.bytes <= budget) {
+                a.busy = true;
+                *out = a.p;
+                *pooled = true;
+                return LEYENDA_OK;
+            }
+            if (a.p) {  // too small or above this call's budget: replaced
+                (void)hipFree(a.p);
+                a.p = nullptr;
+                a.bytes = 0;
+            }
+            hipError_t e = hipMalloc(&a.p, bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                a.p = nullptr;
+                return fail(LEYENDA_ENOMEM, "hipMalloc(%zu) for the external sort failed", bytes);
+            }
+            a.bytes = bytes;
+            a.busy = true;
+            *out = a.p;
+            *pooled = true;
+            return LEYENDA_OK;
+        }
+    }
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *out = nullptr;
+        return fail(LEYENDA_ENOMEM, "hipMalloc(%zu) for the external sort failed", bytes);
+    }
+    return LEYENDA_OK;
+}
+
+// Returns an arena from ext_arena_take; the caller's work on it has finished.
+void ext_arena_give(void *p, bool pooled) {
+    if (!p) return;
+    if (!pooled) {
+        (void)hipFree(p);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_ext_mu);
+    for (ExtArena &a : g_ext)
+        if (a.p == p) a.busy = false;
+}
+
 struct Pipe {
     hipStream_t cs = nullptr, h2d = nullptr, d2h = nullptr;
     hipEvent_t ev[3][kPipeBufs] = {};  // [h2d_done, compute_done, d2h_done][buffer]
     void *arena = nullptr;
+    bool pooled = false;
     int init(hipStream_t caller) {
         hipError_t e;
         if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
@@ -304,14 +384,13 @@ struct Pipe {
         (void)hipEventDestroy(start);
         return LEYENDA_OK;
     }
-    int alloc(size_t bytes) {
-        hipError_t e = hipMalloc(&arena, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            arena = nullptr;
-            return fail(LEYENDA_ENOMEM, "hipMalloc(%zu) for the external sort failed", bytes);
-        }
-        return LEYENDA_OK;
+    // device memory for the call: `bytes` of a call limited to `budget`
+    int alloc(size_t bytes, size_t budget) { return ext_arena_take(bytes, budget, &arena, &pooled); }
+    // gives the arena back (every stream of the pipe has drained)
+    void release_arena() {
+        ext_arena_give(arena, pooled);
+        arena = nullptr;
+        pooled = false;
     }
     int finish() {
         hipError_t e1 = cs ? hipStreamSynchronize(cs) : hipSuccess;
@@ -326,7 +405,7 @@ struct Pipe {
         if (cs) (void)hipStreamSynchronize(cs);
         if (h2d) (void)hipStreamSynchronize(h2d);
         if (d2h) (void)hipStreamSynchronize(d2h);
-        if (arena) (void)hipFree(arena);
+        release_arena();
         for (auto &row : ev)
             for (auto &x : row)
                 if (x) (void)hipEventDestroy(x);
@@ -389,10 +468,58 @@ struct Bounce {
         }
         return LEYENDA_OK;
     }
+    // waits for every copy into the buffers (before they serve another call)
+    void quiesce() {
+        for (int i = 0; i < kBufs; i++)
+            if (ev[i]) (void)hipEventSynchronize(ev[i]);
+    }
     ~Bounce() {
         for (int i = 0; i < kBufs; i++) {
             if (ev[i]) { (void)hipEventSynchronize(ev[i]); (void)hipEventDestroy(ev[i]); }
             if (buf[i]) (void)hipHostFree(buf[i]);
+        }
+    }
+};
+
+// The bounce buffers and copy threads of pageable outputs, kept between calls
+// like the arena (one set per device; pinning them and starting the threads
+// is work every pageable output would otherwise repeat).  A call that finds
+// them in use makes its own set for the call.
+std::unique_ptr<Bounce> g_bounce[64];
+bool g_bounce_busy[64] = {};
+
+struct BounceLease {
+    Bounce *b = nullptr;
+    bool pooled = false;
+    int dev = 0;
+    int take() {
+        int rc = current_device(&dev);
+        if (rc) return rc;
+        {
+            std::lock_guard<std::mutex> lk(g_ext_mu);
+            if (!g_bounce_busy[dev]) {
+                if (!g_bounce[dev]) {
+                    std::unique_ptr<Bounce> nb(new Bounce());
+                    if ((rc = nb->init())) return rc;
+                    g_bounce[dev] = std::move(nb);
+                }
+                g_bounce_busy[dev] = true;
+                b = g_bounce[dev].get();
+                pooled = true;
+                return LEYENDA_OK;
+            }
+        }
+        b = new Bounce();
+        return b->init();
+    }
+    ~BounceLease() {
+        if (!b) return;
+        if (pooled) {
+            b->quiesce();  // an early error return may leave a download in flight
+            std::lock_guard<std::mutex> lk(g_ext_mu);
+            g_bounce_busy[dev] = false;
+        } else {
+            delete b;
         }
     }
 };
@@ -486,7 +613,7 @@ extern "C" int leyenda_sort_runs(const void *host_records, uint64_t n, uint64_t 
     if ((rc = P.init(static_cast<hipStream_t>(stream)))) return rc;
     const size_t rb = a256(R * kRec);
     const size_t ws_bytes = plan_layout(R, 1, t).total;
-    if ((rc = P.alloc(4 * rb + ws_bytes + 256))) return rc;
+    if ((rc = P.alloc(4 * rb + ws_bytes + 256, device_budget_bytes))) return rc;
     char *base = static_cast<char *>(P.arena);
     uint8_t *in[2] = {reinterpret_cast<uint8_t *>(base), reinterpret_cast<uint8_t *>(base + rb)};
     uint8_t *out[2] = {reinterpret_cast<uint8_t *>(base + 2 * rb), reinterpret_cast<uint8_t *>(base + 3 * rb)};
@@ -594,7 +721,7 @@ int merge_impl(Pipe &P, const uint8_t *runs_dev, const uint8_t *runs_h, const ui
     const size_t n_tab = (size_t)(nch + 1) * k;
     const size_t pair_cap = (size_t)nch * (rounds + 1) * ((k + 1) / 2 + 1);
     if (!arena) {
-        if ((rc = P.alloc(need))) return rc;
+        if ((rc = P.alloc(need, device_budget_bytes))) return rc;
         arena = static_cast<char *>(P.arena);
     }
     char *base = arena;
@@ -701,8 +828,8 @@ int merge_impl(Pipe &P, const uint8_t *runs_dev, const uint8_t *runs_h, const ui
     //    the drain of chunk c - 3 one step earlier.
     const int cus = device_cus();
     constexpr uint64_t kLag = kPipeBufs - 1;
-    Bounce bounce;
-    if (!direct_out && (rc = bounce.init())) return rc;
+    BounceLease bounce;
+    if (!direct_out && (rc = bounce.take())) return rc;
     std::vector<uint64_t> chunk_len(nch, 0);
     for (uint64_t c = 0; c < nch; c++)
         for (uint64_t i = 0; i < k; i++) chunk_len[c] += slice_len[c][i];
@@ -753,7 +880,7 @@ int merge_impl(Pipe &P, const uint8_t *runs_dev, const uint8_t *runs_h, const ui
         if (!direct_out && c >= kLag) {
             const uint64_t d = c - kLag;
             const int bd = (int)(d % kPipeBufs);
-            if ((rc = bounce.drain(outb[bd], out_h + cb[d] * kRec, chunk_len[d] * kRec, P.ev[1][bd], P.d2h)))
+            if ((rc = bounce.b->drain(outb[bd], out_h + cb[d] * kRec, chunk_len[d] * kRec, P.ev[1][bd], P.d2h)))
                 return rc;
         }
     }
@@ -840,7 +967,8 @@ extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint6
     // downloaded like the others and the merge plans within the whole budget
     uint64_t merge_bytes = 0;
     const bool keep_last = K == 1 || !merge_plan(n, K, device_budget_bytes - rb, &merge_bytes).empty();
-    if ((rc = P.alloc(keep_last ? std::max<uint64_t>(total, rb + merge_bytes) : total))) return rc;
+    if ((rc = P.alloc(keep_last ? std::max<uint64_t>(total, rb + merge_bytes) : total, device_budget_bytes)))
+        return rc;
     char *base = static_cast<char *>(P.arena);
     // the output buffer the last run sorts into comes first, so the rest of the
     // memory is one block for the merge
@@ -887,14 +1015,13 @@ extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint6
             if (e != hipSuccess) return hip_fail(e, "leyenda_sort_external: download");
             return P.finish();
         }
-        Bounce bounce;
-        if ((rc = bounce.init())) return rc;
-        if ((rc = bounce.drain(keep, out_h, n * kRec, P.ev[1][0], P.d2h))) return rc;
+        BounceLease bounce;
+        if ((rc = bounce.take())) return rc;
+        if ((rc = bounce.b->drain(keep, out_h, n * kRec, P.ev[1][0], P.d2h))) return rc;
         return P.finish();
     }
     if (!keep_last) {  // every run is in host_runs: the merge as leyenda_merge runs it
-        (void)hipFree(P.arena);
-        P.arena = nullptr;
+        P.release_arena();
         return merge_impl(P, runs_dev, dst, bounds.data(), K, out_h, direct_out, device_budget_bytes, nullptr,
                           nullptr);
     }
@@ -937,7 +1064,7 @@ extern "C" int leyenda_sort_external_keys(const void *host_records, uint64_t n, 
     Pipe P;
     int rc = P.init(static_cast<hipStream_t>(stream));
     if (rc) return rc;
-    if ((rc = P.alloc(need))) return rc;
+    if ((rc = P.alloc(need, device_budget_bytes))) return rc;
     char *base = static_cast<char *>(P.arena);
     uint64_t *H0 = reinterpret_cast<uint64_t *>(base + L.off_H0);
     uint64_t *L0 = reinterpret_cast<uint64_t *>(base + L.off_L0);
@@ -977,8 +1104,8 @@ extern "C" int leyenda_sort_external_keys(const void *host_records, uint64_t n, 
     const uint64_t cap_out = std::min<uint64_t>(L.off_L0 - L.off_H0, L.off_idx - L.off_L0) / kRec;
     const uint64_t C3 = std::max<uint64_t>(1, std::min<uint64_t>(cap_out, 32ull << 20));
     uint8_t *out_h = static_cast<uint8_t *>(host_out);
-    Bounce bounce;
-    if (!direct_out && (rc = bounce.init())) return rc;
+    BounceLease bounce;
+    if (!direct_out && (rc = bounce.take())) return rc;
     uint64_t prev_first = 0, prev_len = 0;
     uint64_t c = 0;
     for (uint64_t c0 = 0; c0 < n; c0 += C3, c++) {
@@ -995,14 +1122,14 @@ extern "C" int leyenda_sort_external_keys(const void *host_records, uint64_t n, 
             if (e != hipSuccess) return hip_fail(e, "leyenda_sort_external_keys: write");
         } else {
             // chunk c - 1 drains while chunk c is gathered
-            if (c >= 1 && (rc = bounce.drain(stage_out[b ^ 1], out_h + prev_first * kRec, prev_len * kRec,
+            if (c >= 1 && (rc = bounce.b->drain(stage_out[b ^ 1], out_h + prev_first * kRec, prev_len * kRec,
                                              P.ev[1][b ^ 1], P.d2h)))
                 return rc;
             prev_first = c0;
             prev_len = len;
         }
     }
-    if (!direct_out && (rc = bounce.drain(stage_out[(c - 1) & 1], out_h + prev_first * kRec, prev_len * kRec,
+    if (!direct_out && (rc = bounce.b->drain(stage_out[(c - 1) & 1], out_h + prev_first * kRec, prev_len * kRec,
                                           P.ev[1][(c - 1) & 1], P.d2h)))
         return rc;
     if ((rc = P.finish())) return rc;
@@ -1012,3 +1139,28 @@ extern "C" int leyenda_sort_external_keys(const void *host_records, uint64_t n, 
     if (g) return fail(LEYENDA_EINTERNAL, "leyenda_sort_external_keys: a device-side guard fired in the sort (0x%x)", g);
     return LEYENDA_OK;
 }
+
+namespace ley {
+
+bool external_holds_any() {
+    std::lock_guard<std::mutex> lk(g_ext_mu);
+    for (int d = 0; d < 64; d++)
+        if (g_ext[d].p || g_bounce[d]) return true;
+    return false;
+}
+
+// Frees the kept arenas and bounce sets that no call is using (the device has
+// been synchronised by the caller).
+void external_release_all() {
+    std::lock_guard<std::mutex> lk(g_ext_mu);
+    for (int d = 0; d < 64; d++) {
+        if (g_ext[d].p && !g_ext[d].busy) {
+            (void)hipFree(g_ext[d].p);
+            g_ext[d].p = nullptr;
+            g_ext[d].bytes = 0;
+        }
+        if (g_bounce[d] && !g_bounce_busy[d]) g_bounce[d].reset();
+    }
+}
+
+}  // namespace ley

@@ -51,6 +51,11 @@ int sort_device_ws(const void *records_dev, uint64_t n, void *out_dev, hipStream
                    uint32_t first_pass = kFirstSplit);
 uint32_t first_pass_for(uint64_t n, const Tune &t, bool ties);
 
+// external.hip: the device arenas and bounce buffers the external calls keep
+// between calls
+bool external_holds_any();
+void external_release_all();
+
 // batch.hip
 int batch_sort(const leyenda_segment *segs, uint64_t count, hipStream_t s);
 // split: two-part launch sequence for the serving loop (see batch.hip); after

@@ -2,6 +2,8 @@
 // checks and the leyenda_sort entry point (C ABI declared in leyenda.h).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -72,15 +74,15 @@ static bool params_ok(const leyenda_params &p) {
 // device facts
 
 int device_cus() {
-    static int cus[64] = {0};
+    static std::atomic<int> cus[64];  // zero-initialised; 0: not yet read
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (!cus[dev]) {
-        int v = 0;
+    int v = cus[dev].load(std::memory_order_relaxed);
+    if (!v) {
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
-        cus[dev] = v;
+        cus[dev].store(v, std::memory_order_relaxed);
     }
-    return cus[dev];
+    return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -335,7 +337,7 @@ void pool_forget(hipStream_t stream) {
 int release_all() {
     // nothing held: leave the HIP runtime alone (this also runs at interpreter
     // exit, where the process may never have used a GPU)
-    bool any = batch_holds_any();
+    bool any = batch_holds_any() || external_holds_any();
     {
         std::lock_guard<std::mutex> lk(g_pool_mu);
         any = any || !g_pool.empty();
@@ -344,6 +346,7 @@ int release_all() {
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     batch_release_all();
+    external_release_all();
     std::lock_guard<std::mutex> lk(g_pool_mu);
     for (auto &kv : g_pool) {
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);

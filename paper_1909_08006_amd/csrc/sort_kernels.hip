@@ -1770,12 +1770,11 @@ template <int ITEMS, int SWG, int LWG>
 static hipError_t launch_levels(const Work &w, const Tune &t, uint32_t nreq, uint32_t tiles0,
                                 hipStream_t s, int cus, hipEvent_t *ev, const Stage &st) {
     constexpr int SITEMS = ITEMS * kWG / SWG;  // same tile, SWG threads
-    static int g_sc = 0, g_hist = 0, g_loc = 0;
-    if (!g_sc) {
-        g_sc = occupancy(reinterpret_cast<const void *>(&k_scatter<SITEMS, SWG>), cus, SWG);
-        g_hist = occupancy(reinterpret_cast<const void *>(&k_hist<ITEMS>), cus);
-        g_loc = occupancy(reinterpret_cast<const void *>(&k_local<LWG, LWG == 512 ? 2 : 3>), cus, LWG);
-    }
+    // grid sizes from the occupancy of each kernel (static locals: initialised
+    // once, safely under concurrent first calls)
+    static const int g_sc = occupancy(reinterpret_cast<const void *>(&k_scatter<SITEMS, SWG>), cus, SWG);
+    static const int g_hist = occupancy(reinterpret_cast<const void *>(&k_hist<ITEMS>), cus);
+    static const int g_loc = occupancy(reinterpret_cast<const void *>(&k_local<LWG, LWG == 512 ? 2 : 3>), cus, LWG);
     const bool fused = st.head && st.first != kFirstSplit;
     if (fused) {
         // one request of w.n records; the workspace was laid out for this first pass
@@ -1852,8 +1851,7 @@ hipError_t launch_gather_batch(const Work &w, hipStream_t s, int gate) {
 template <int LWG>
 static hipError_t local_part(const Work &w, const Tune &t, hipStream_t s, int cus, int part) {
     constexpr int MINB = LWG == 512 ? 2 : 3;
-    static int g_loc = 0;
-    if (!g_loc) g_loc = occupancy(reinterpret_cast<const void *>(&k_local<LWG, MINB>), cus, LWG);
+    static const int g_loc = occupancy(reinterpret_cast<const void *>(&k_local<LWG, MINB>), cus, LWG);
     k_local<LWG, MINB><<<dim3(g_loc), dim3(LWG), 0, s>>>(w, t, kMaxLev, part);
     return hipGetLastError();
 }

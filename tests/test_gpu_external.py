@@ -220,3 +220,44 @@ def test_sort_external_many_tiny_runs(gpu):
     runs = torch.empty(n * 100, dtype=torch.uint8, pin_memory=True)
     out = gpu.sort_external(host, budget, host_runs=runs)
     np.testing.assert_array_equal(out.numpy().reshape(n, 100), rec)
+
+
+def test_external_calls_reuse_and_share_their_memory(gpu):
+    """The external calls keep a device arena and bounce buffers between calls:
+    calls with growing and shrinking budgets reuse or replace them, and two
+    calls at once on different threads (one takes the kept set, the other
+    makes its own) both sort correctly."""
+    import threading
+    import torch
+    recs = [datagen.skewed(60_000 + 7_000 * i, 130 + i, nvals=50, dup_frac=0.2) for i in range(4)]
+    for i, rec in enumerate(recs):  # budgets up and down: the kept arena is reused or replaced
+        n = rec.shape[0]
+        budget = budget_for_runs(gpu, n, [3, 9, 2, 5][i])
+        out = gpu.sort_external(pinned(rec), budget)
+        np.testing.assert_array_equal(out.numpy().reshape(n, 100), oracle.sort(rec))
+        runs, bounds = gpu.sort_runs(pinned(rec), budget)
+        merged = gpu.merge(runs, bounds, budget)
+        np.testing.assert_array_equal(merged.numpy().reshape(n, 100), oracle.sort(rec))
+    results, errors = {}, []
+
+    def work(k):
+        try:
+            rec = recs[k]
+            n = rec.shape[0]
+            budget = budget_for_runs(gpu, n, 4)
+            for _ in range(3):
+                out = gpu.sort_external(pinned(rec), budget, stream=torch.cuda.Stream())
+                results[k] = out.numpy().reshape(n, 100).copy()
+                if not np.array_equal(results[k], oracle.sort(rec)):
+                    errors.append(f"thread {k}: output differs")
+        except Exception as exc:  # reported below
+            errors.append(f"thread {k}: {exc!r}")
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in (0, 1)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=240)
+    assert not errors, errors
+    assert set(results) == {0, 1}
+    gpu.release_workspaces()
