@@ -361,6 +361,10 @@ void ext_arena_give(void *p, bool pooled) {
         if (a.p == p) a.busy = false;
 }
 
+// The streams of an external call: its kernels run on the caller's stream
+// (cs), its uploads and downloads on two streams of its own, so the process
+// holds few streams (streams beyond the device's hardware queues share queues
+// and serialise, and the copy streams must not share one).
 struct Pipe {
     hipStream_t cs = nullptr, h2d = nullptr, d2h = nullptr;
     hipEvent_t ev[3][kPipeBufs] = {};  // [h2d_done, compute_done, d2h_done][buffer]
@@ -368,17 +372,16 @@ struct Pipe {
     bool pooled = false;
     int init(hipStream_t caller) {
         hipError_t e;
-        if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+        cs = caller;
         if ((e = hipStreamCreateWithFlags(&h2d, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
         if ((e = hipStreamCreateWithFlags(&d2h, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
         for (auto &row : ev)
             for (auto &x : row)
                 if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
-        // start after the caller's earlier work on its stream
+        // the copies start after the caller's earlier work on its stream
         hipEvent_t start;
         if ((e = hipEventCreateWithFlags(&start, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
         (void)hipEventRecord(start, caller);
-        (void)hipStreamWaitEvent(cs, start, 0);
         (void)hipStreamWaitEvent(h2d, start, 0);
         (void)hipStreamWaitEvent(d2h, start, 0);
         (void)hipEventDestroy(start);
@@ -409,10 +412,6 @@ struct Pipe {
         for (auto &row : ev)
             for (auto &x : row)
                 if (x) (void)hipEventDestroy(x);
-        if (cs) {
-            pool_forget(cs);  // the side stream a large run's sort made for cs
-            (void)hipStreamDestroy(cs);
-        }
         if (h2d) (void)hipStreamDestroy(h2d);
         if (d2h) (void)hipStreamDestroy(d2h);
     }

@@ -210,15 +210,22 @@ static void aux_free(PoolEntry &pe) {
     }
 }
 
+// Destroys a workspace's side events (the side stream itself is shared).
 static void side_destroy(Side &sd) {
     for (hipEvent_t &e : sd.ready)
         if (e) (void)hipEventDestroy(e), e = nullptr;
     if (sd.done) (void)hipEventDestroy(sd.done), sd.done = nullptr;
-    if (sd.s) (void)hipStreamDestroy(sd.s), sd.s = nullptr;
+    sd.s = nullptr;
 }
 
 static std::mutex g_pool_mu;
 static std::map<std::pair<int, hipStream_t>, PoolEntry> g_pool;
+// One side stream per device, shared by the workspaces of every caller stream
+// (each keeps its own events).  Streams beyond the device's hardware queues
+// share queues and serialise; a side stream per caller stream, kept after a
+// large sort, made a later external sort's copy streams share queues with it
+// (its stages took 2.1-2.2 s instead of 1.3-1.4 s).
+static hipStream_t g_side_stream[64];
 
 // Workspace of at least `bytes` for work on `stream` (one per device and
 // stream, so concurrent sorts on different streams never share scratch).
@@ -294,9 +301,10 @@ static int get_side(hipStream_t stream, Side **out) {
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (dev < 0 || dev >= 64) return fail(LEYENDA_EINVAL, "device %d out of range", dev);
     Side &sd = g_pool[{dev, stream}].side;
     if (!sd.s) {
-        e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking);
+        if (!g_side_stream[dev]) e = hipStreamCreateWithFlags(&g_side_stream[dev], hipStreamNonBlocking);
         for (int k = 0; k < kParts && e == hipSuccess; k++)
             e = hipEventCreateWithFlags(&sd.ready[k], hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.done, hipEventDisableTiming);
@@ -304,6 +312,7 @@ static int get_side(hipStream_t stream, Side **out) {
             side_destroy(sd);
             return hip_fail(e, "side stream");
         }
+        sd.s = g_side_stream[dev];
     }
     *out = &sd;
     return LEYENDA_OK;
@@ -341,6 +350,7 @@ int release_all() {
     {
         std::lock_guard<std::mutex> lk(g_pool_mu);
         any = any || !g_pool.empty();
+        for (hipStream_t st : g_side_stream) any = any || st != nullptr;
     }
     if (!any) return LEYENDA_OK;
     hipError_t e = hipDeviceSynchronize();
@@ -354,6 +364,8 @@ int release_all() {
         side_destroy(kv.second.side);
     }
     g_pool.clear();
+    for (hipStream_t &st : g_side_stream)
+        if (st) (void)hipStreamDestroy(st), st = nullptr;
     return LEYENDA_OK;
 }
 
