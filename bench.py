@@ -512,6 +512,8 @@ def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9
             "gbs_records_end_to_end": round(n * 100 / (t_runs + t_merge[1]) / 1e9, 2),
             "gbs_records_end_to_end_first_touch": round(n * 100 / (t_runs + t_merge[0]) / 1e9, 2),
             "pcie_measured_gbs": rates,
+            # both directions as the run stage used them (120 GB moved over its time)
+            "runs_observed_gbs_both_ways": round(n * 200 / t_runs / 1e9, 1),
             "pcie_bound": {"bytes_per_record_each_way": 200, "bound_s_each_way_rates_overlapped": round(both_bound, 3),
                            "frac": round(both_bound / (t_runs + t_merge[1]), 3),
                            # the same bytes at the rate both directions reached together
