@@ -124,10 +124,11 @@ uint32_t leyenda_first_pass(uint64_t n);
 /* Output parts a leyenda_sort of n records runs in: 1 below 8 Mi records,
  * else 4 (holding 1/16, 1/16, 1/8 and 3/4 of the records in output order).
  * With several parts the local sorts are launched once per part, in
- * output order, and each part's record gather runs on a side stream of the
- * sort's stream as soon as that part is sorted, overlapping the local sorts of
- * the later parts; the sort's stream waits for every gather before it
- * continues, so callers see one ordered operation.  Pure function. */
+ * output order, and each part's record gather runs on the library's side
+ * stream (one per device, shared by every caller stream) as soon as that part
+ * is sorted, overlapping the local sorts of the later parts; the sort's stream
+ * waits for every gather before it continues, so callers see one ordered
+ * operation.  Pure function. */
 uint32_t leyenda_sort_parts(uint64_t n);
 
 /* ---------------------------------------------------------------------------
