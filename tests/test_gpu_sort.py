@@ -293,3 +293,37 @@ def test_error_codes(gpu):
     with pytest.raises(gpu.LeyendaError):
         gpu.set_params(big_threshold=0)
     torch.cuda.synchronize()
+
+
+def test_concurrent_sorts_share_the_side_stream(gpu):
+    """Sorts of 8 Mi records or more on two caller streams at once, from two
+    threads: their output-part gathers share the library's one side stream per
+    device (each stream's sorts keep their own events), and both outputs must
+    equal the oracle's."""
+    import threading
+    import torch
+    n = 8_388_608 + 4_321
+    recs = [datagen.uniform(n, 140), pattern("skewed_narrow", n)]
+    wants = [oracle.sort(r, threads=0) for r in recs]
+    errors = []
+
+    def work(k):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                dev = torch.from_numpy(recs[k]).cuda()
+                out = torch.empty_like(dev)
+                for _ in range(3):
+                    gpu.sort(dev, out=out, stream=s)
+                    s.synchronize()
+                    if not np.array_equal(out.cpu().numpy(), wants[k]):
+                        errors.append(f"stream {k}: output differs")
+        except Exception as exc:  # reported below
+            errors.append(f"stream {k}: {exc!r}")
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in (0, 1)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=240)
+    assert not errors, errors
