@@ -563,7 +563,7 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build sorts on one GPU only; multi-GPU runs are not part of it "
+        print("bench.py: the sorter runs on one GPU; runs on several GPUs are not supported "
               "(run with --gpus 1)", file=sys.stderr)
         return 2
 
