@@ -395,7 +395,7 @@ def pcie_rates(ley, nbytes: int = 2_000_000_000, tries: int = 3) -> dict:
             ley.pinned_free(t)
 
 
-def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9) -> dict:
+def external(ley, torch, datagen, rates: dict, n: int = 600_000_000, budget: int = 30 * 10**9) -> dict:
     """The 60 GB limited-memory workload: 600,000,000 records in pinned host
     memory, 30 GB device budget, sorted runs written over the input, then the
     k-way merge into pageable host memory (and, in `pinned_output`, both paths
@@ -404,10 +404,9 @@ def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9
     into the same output: first into fresh memory (its first-touch page faults
     included), then into the now resident buffer (a reused output).  Then, each
     on the regenerated input, runs + merge in one call and the keys-only
-    variant.  (n and budget: smaller instances of the same workload, e.g. under
-    a profiler.)"""
+    variant.  rates: pcie_rates() of this machine.  (n and budget: smaller
+    instances of the same workload, e.g. under a profiler.)"""
     import numpy as np
-    rates = pcie_rates(ley)
     log(f"external: generating {n:,} records (60 GB, seed {datagen.SEED_EXTERNAL}) ...")
     a = ley.pinned_empty(n * 100)
     datagen.fill_uniform(a.data_ptr(), n, datagen.SEED_EXTERNAL)
@@ -499,6 +498,12 @@ def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9
     keys_bound = max(n * 200 / (rates["h2d"] * 1e9), n * 100 / (rates["d2h"] * 1e9))
     duplex = rates["both_ways"] > 1.2 * max(rates["h2d"], rates["d2h"])
     duplex_bound = n * 400 / (rates["both_ways"] * 1e9) if duplex else None
+    # the one call keeps the last run on the device: that run is neither
+    # downloaded after its sort nor uploaded for the merge (R_last = its records)
+    r_last = bounds[-1] - bounds[-2]
+    one_each_way = (n * 200 - r_last * 100) if len(bounds) > 2 else n * 100
+    one_bound = max(one_each_way / (rates["h2d"] * 1e9), one_each_way / (rates["d2h"] * 1e9))
+    one_duplex = 2 * one_each_way / (rates["both_ways"] * 1e9) if duplex else None
     if "t_runs_s" in pinned:
         pinned["pcie_frac"] = round(both_bound / (pinned["t_runs_s"] + pinned["t_merge_s"]), 3)
         if keys_skip is None:
@@ -528,8 +533,11 @@ def external(ley, torch, datagen, n: int = 600_000_000, budget: int = 30 * 10**9
                                          "bound_s": round(keys_bound, 3), "frac": round(keys_bound / t_keys, 3)},
                           "sampled_order_ok": ok_keys},
             "one_call": {"t_s": round(t_one, 3), "gbs_records_end_to_end": round(n * 100 / t_one / 1e9, 2),
-                         "pcie_frac": round(both_bound / t_one, 3),
-                         "pcie_frac_both_ways_rate": round(duplex_bound / t_one, 3) if duplex_bound else None,
+                         "bytes_per_record_each_way": round(one_each_way / n, 2),
+                         "bound_s_each_way_rates_overlapped": round(one_bound, 3),
+                         "pcie_frac": round(one_bound / t_one, 3),
+                         "bound_s_both_ways_rate": round(one_duplex, 3) if one_duplex else None,
+                         "pcie_frac_both_ways_rate": round(one_duplex / t_one, 3) if one_duplex else None,
                          "sampled_order_ok": ok_one},
             "pinned_output": pinned}
 
@@ -575,6 +583,9 @@ def main() -> int:
     ley.load()
     if args.first_pass is not None:
         ley.set_params(first_pass=args.first_pass)
+    # PCIe rates first, while the process holds no streams of its own yet (a
+    # property of the machine; the external workload's bound uses them)
+    rates = pcie_rates(ley) if not args.no_external else None
     n = args.n
     fill, seed, keys = {
         "uniform": (datagen.fill_uniform, datagen.SEED_INTERNAL, "uniform 10-byte keys"),
@@ -705,7 +716,7 @@ def main() -> int:
         if hasattr(torch._C, "_host_emptyCache"):  # return the cached pinned block (host pinned limit)
             torch._C._host_emptyCache()
         try:
-            res["external"] = external(ley, torch, datagen, args.external_n, args.external_budget)
+            res["external"] = external(ley, torch, datagen, rates, args.external_n, args.external_budget)
         except ley.LeyendaError as exc:  # e.g. the host cannot pin 60 GB: report, keep the line
             res["external"] = {"skipped": str(exc)}
     print(json.dumps(res), flush=True)
