@@ -195,23 +195,27 @@ int leyenda_sort_external(const void *host_records, uint64_t n, uint64_t device_
  * the input is read, sorted, then the records scattered by the sorted
  * tuples).  The input streams host -> device in chunks and every record's
  * 16-byte (key, index) tuple is kept on the device; all n tuples are then
- * sorted in one device-resident pass (Algorithm 1), and the records are
- * gathered in sorted order by device loads straight from the pinned input
- * (PCIe reads of 100-byte records) and streamed to host_out.  No runs, no
+ * sorted in one device-resident pass (Algorithm 1).  A pinned host_out: the
+ * input streams up a second time, in order, and every record is written by
+ * the device straight to its place in host_out (random 100-byte PCIe writes).
+ * A pageable host_out: the records are gathered in sorted order by device
+ * loads straight from the pinned input (random 100-byte PCIe reads) and
+ * streamed out through pinned bounce buffers.  No runs, no
  * merge: it needs the tuples and sort tables of all n records on the device
  * (leyenda_workspace_bytes(n) + 256 bytes, about 43 bytes per record), and
  * returns LEYENDA_EBUDGET, touching nothing, when device_budget_bytes is
  * below that (leyenda_sort_runs + leyenda_merge then fit).
- *   host_records: n records in pinned host memory (read only; the gather
- *                 reads it through its device mapping).
- *   host_out:     n records of host memory, pinned (written by the copy
- *                 engine) or pageable (through pinned bounce buffers and host
- *                 copies); must not overlap host_records.
+ *   host_records: n records in pinned host memory (read only; read by the
+ *                 copy engine, and by the pageable-output gather through its
+ *                 device mapping).
+ *   host_out:     n records of host memory, pinned (written by the device
+ *                 through its mapping) or pageable (through pinned bounce
+ *                 buffers and host copies); must not overlap host_records.
  * Output: the stable sort of the records by their 10-byte key, the same bytes
  * as leyenda_sort.  Synchronous: returns when host_out is complete.
  * LEYENDA_EINVAL (NULL, misaligned, overlapping, unpinned input),
  * LEYENDA_ETOOBIG (n > LEYENDA_MAX_RECORDS), LEYENDA_ENOMEM, LEYENDA_EHIP,
- * LEYENDA_EINTERNAL (a device-side guard of the sort fired). */
+ * LEYENDA_EINTERNAL (a device-side guard of the sort or the scatter fired). */
 int leyenda_sort_external_keys(const void *host_records, uint64_t n, uint64_t device_budget_bytes,
                                void *host_out, void *stream);
 

@@ -284,10 +284,11 @@ def sort_external(host_records, budget_bytes: int, host_runs=None, host_out=None
 
 def sort_external_keys(host_records, budget_bytes: int, host_out=None, stream=None):
     """Keys-only external sort of pinned host records: every (key, index)
-    tuple sorted on the device at once, then the records gathered from the
-    pinned input in sorted order into ``host_out`` (pinned or pageable; a new
-    pageable tensor by default).  Needs ``workspace_bytes(n) + 256`` of device
-    budget."""
+    tuple sorted on the device at once, then the records written into
+    ``host_out``: a pinned output takes a second in-order read of the input
+    that puts every record in its place; a pageable one (a new pageable tensor
+    by default) gets the records gathered from the pinned input in sorted
+    order.  Needs ``workspace_bytes(n) + 256`` of device budget."""
     import torch
     n = _nrec(host_records)
     if host_out is None:

@@ -111,13 +111,15 @@ def test_external_errors(gpu):
     assert lib is not None
 
 
-# ---- keys-only variant: all tuples sorted on the device, records gathered from the pinned input ----
+# ---- keys-only variant: all tuples sorted on the device; records scattered into a pinned output
+#      by a second in-order read, or gathered from the pinned input for a pageable one ----
 
 @pytest.mark.parametrize("kind,pinned_out", [("uniform", True), ("uniform", False), ("ties", True),
                                              ("ties", False), ("few", True)])
 def test_keys_only_matches_oracle(gpu, kind, pinned_out):
-    """The input streams in about twelve chunks and the output leaves in about
-    seven, so equal keys straddle chunk boundaries on both sides."""
+    """The input streams in about twelve chunks (twice for a pinned output)
+    and a pageable output leaves in about seven, so equal keys straddle chunk
+    boundaries on both sides."""
     import torch
     n = 250_007
     if kind == "uniform":
@@ -135,9 +137,26 @@ def test_keys_only_matches_oracle(gpu, kind, pinned_out):
 
 
 def test_keys_only_tiny(gpu):
+    import torch
     for n in (1, 2, 3, 12, 13, 101, 2049):
         rec = datagen.skewed(n, 85, nvals=4, dup_frac=0.5) if n > 3 else datagen.uniform(n, 85)
         out = gpu.sort_external_keys(pinned(rec), 64 << 20)
+        np.testing.assert_array_equal(out.numpy().reshape(n, 100), oracle.sort(rec))
+        pout = torch.empty(n * 100, dtype=torch.uint8, pin_memory=True)
+        gpu.sort_external_keys(pinned(rec), 64 << 20, host_out=pout)
+        np.testing.assert_array_equal(pout.numpy().reshape(n, 100), oracle.sort(rec))
+
+
+def test_keys_only_pinned_output_repeats(gpu):
+    """A pinned output takes the scatter: the places table and the staging
+    areas are sort buffers reused from call to call, a larger call after a
+    smaller one and back; every byte of the output is written (it starts
+    filled with 0xEE)."""
+    import torch
+    for n, seed in ((300_001, 87), (40_000, 88), (300_001, 89)):
+        rec = datagen.skewed(n, seed, nvals=60, dup_frac=0.2)
+        out = torch.full((n * 100,), 0xEE, dtype=torch.uint8).pin_memory()
+        gpu.sort_external_keys(pinned(rec), gpu.workspace_bytes(n) + 256, host_out=out)
         np.testing.assert_array_equal(out.numpy().reshape(n, 100), oracle.sort(rec))
 
 
