@@ -147,6 +147,17 @@ def test_keys_only_tiny(gpu):
         np.testing.assert_array_equal(pout.numpy().reshape(n, 100), oracle.sort(rec))
 
 
+def test_keys_only_pageable_many_pieces(gpu):
+    """A pageable output: the gather writes pieces of 1,342,177 records into
+    the four pinned bounce buffers, which the host empties oldest first; six
+    million records fill five pieces (every buffer used, the first reused)
+    and end in a ragged one."""
+    n = 6_000_001
+    rec = datagen.skewed(n, 95, nvals=200, dup_frac=0.2)
+    out = gpu.sort_external_keys(pinned(rec), gpu.workspace_bytes(n) + 256)
+    np.testing.assert_array_equal(out.numpy().reshape(n, 100), oracle.sort(rec))
+
+
 def test_keys_only_pinned_output_repeats(gpu):
     """A pinned output takes the scatter: the places table and the staging
     areas are sort buffers reused from call to call, a larger call after a
