@@ -407,7 +407,7 @@ def external(ley, torch, datagen, rates: dict, n: int = 600_000_000, budget: int
     variant.  rates: pcie_rates() of this machine.  (n and budget: smaller
     instances of the same workload, e.g. under a profiler.)"""
     import numpy as np
-    log(f"external: generating {n:,} records (60 GB, seed {datagen.SEED_EXTERNAL}) ...")
+    log(f"external: generating {n:,} records ({n * 100 / 1e9:.0f} GB, seed {datagen.SEED_EXTERNAL}) ...")
     a = ley.pinned_empty(n * 100)
     datagen.fill_uniform(a.data_ptr(), n, datagen.SEED_EXTERNAL)
     log("external: runs ...")
