@@ -291,3 +291,42 @@ def test_external_calls_reuse_and_share_their_memory(gpu):
     assert not errors, errors
     assert set(results) == {0, 1}
     gpu.release_workspaces()
+
+
+def test_keys_only_calls_at_once(gpu):
+    """Three calls on three threads at once: keys-only into a pageable output
+    (the gather fills bounce buffers: one thread takes the kept set, another
+    makes its own), keys-only into a pinned output (the scatter), and runs +
+    merge into a pageable output; each twice."""
+    import threading
+    import torch
+    n = 1_500_001  # two bounce pieces
+    recs = [datagen.skewed(n, 140 + i, nvals=80, dup_frac=0.2) for i in range(3)]
+    wants = [oracle.sort(r) for r in recs]
+    errors = []
+
+    def work(k):
+        try:
+            rec = recs[k]
+            for _ in range(2):
+                s = torch.cuda.Stream()
+                if k == 0:
+                    out = gpu.sort_external_keys(pinned(rec), gpu.workspace_bytes(n) + 256, stream=s)
+                elif k == 1:
+                    out = torch.empty(n * 100, dtype=torch.uint8, pin_memory=True)
+                    gpu.sort_external_keys(pinned(rec), gpu.workspace_bytes(n) + 256, host_out=out, stream=s)
+                else:
+                    out = gpu.sort_external(pinned(rec), budget_for_runs(gpu, n, 3), stream=s)
+                if not np.array_equal(out.numpy().reshape(n, 100), wants[k]):
+                    errors.append(f"thread {k}: output differs")
+        except Exception as exc:  # reported below
+            errors.append(f"thread {k}: {exc!r}")
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in (0, 1, 2)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=240)
+    assert not any(th.is_alive() for th in threads)
+    assert not errors, errors
+    gpu.release_workspaces()
