@@ -168,19 +168,21 @@ int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, uint64_t k,
                   uint64_t device_budget_bytes, void *stream);
 
 /* Runs + merge in one call (Section 3.2, "Overlapping Computation with I/O"):
- * leyenda_sort_runs then leyenda_merge, except that the last run stays in
- * device memory after its sort instead of being written to host_runs and read
- * back for the merge: its download would have had nothing to overlap with,
- * and its slices reach the merge by device copies.  The merge plans its chunks
- * within device_budget_bytes less that run, so the whole call stays within the
- * budget; when that is too little for a merge of the runs (many tiny runs
- * under a budget near one run's footprint), the last run is written to
- * host_runs as well and the merge plans within the whole budget, as
- * leyenda_merge does.
+ * leyenda_sort_runs then leyenda_merge, except that the last two runs stay
+ * in device memory after their sorts (the run stage ends with both in its
+ * output buffers) instead of being written to host_runs and read back for the
+ * merge; their slices reach the merge by device copies.  The merge plans its
+ * chunks within the run stage's device memory less the kept runs (else within
+ * device_budget_bytes less them), so the whole call stays within the budget.
+ * When that is too little for a merge of the runs
+ * (many tiny runs under a budget near one run's footprint), only the last run
+ * is kept, and when even that is too little, every run is written to
+ * host_runs and the merge plans within the whole budget, as leyenda_merge
+ * does.
  *   host_records: n records in pinned host memory (read only unless aliased).
  *   host_runs:    n records of pinned host memory for the runs (may equal
- *                 host_records; the last run's range is left unwritten unless
- *                 the merge needs the whole budget).
+ *                 host_records; the ranges of the kept runs are left
+ *                 unwritten).
  *   host_out:     n records of host memory, pinned or pageable, overlapping
  *                 neither of the above.
  * Output: the stable sort of the records by their 10-byte key, the same bytes

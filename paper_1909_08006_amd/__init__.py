@@ -265,7 +265,7 @@ def merge(host_runs, run_bounds: Sequence[int], budget_bytes: int, host_out=None
 
 
 def sort_external(host_records, budget_bytes: int, host_runs=None, host_out=None, stream=None):
-    """Runs + merge in one call (the last run stays on the device between the
+    """Runs + merge in one call (the last two runs stay on the device between the
     two stages).  ``host_runs``: pinned scratch for the runs, by default
     ``host_records`` itself (overwritten); ``host_out``: pinned or pageable (a
     new pageable tensor by default).  Returns ``host_out``."""

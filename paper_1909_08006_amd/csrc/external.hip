@@ -68,15 +68,21 @@ __device__ __forceinline__ bool tuple_less(const Key80 &a, uint32_t ra, uint64_t
 // search, and move lo (v below the boundary) or hi (v above it).  Every step
 // halves one interval, so it ends after at most sum(log2 len_i) + k steps.
 
-// Record m of run i: in the pinned runs, or (last non-null) for run k - 1 in
-// device memory.
-__device__ __forceinline__ const uint8_t *run_rec(const uint8_t *runs, const uint64_t *run_off, uint32_t k,
-                                                  const uint8_t *last, uint32_t i, uint64_t m) {
-    return (last && i + 1 == k) ? last + m * kRec : runs + (run_off[i] + m) * kRec;
+// Runs held in device memory instead of the pinned runs: runs first .. k - 1
+// (at most two, the last ones) at p[i - first]; first == k when none is.
+struct Resident {
+    const uint8_t *p[2];
+    uint32_t first;
+};
+
+// Record m of run i: in the pinned runs, or in device memory for a resident run.
+__device__ __forceinline__ const uint8_t *run_rec(const uint8_t *runs, const uint64_t *run_off, const Resident &res,
+                                                  uint32_t i, uint64_t m) {
+    return i >= res.first ? res.p[i - res.first] + m * kRec : runs + (run_off[i] + m) * kRec;
 }
 
 __global__ __launch_bounds__(kWG) void k_corank(const uint8_t *runs, const uint64_t *run_off, uint32_t k,
-                                                const uint8_t *last, const uint64_t *targets, uint64_t *splits,
+                                                Resident res, const uint64_t *targets, uint64_t *splits,
                                                 uint32_t *err) {
     __shared__ uint64_t lo[kMaxRuns], hi[kMaxRuns];
     __shared__ unsigned long long red_w[kWaves];
@@ -110,7 +116,7 @@ __global__ __launch_bounds__(kWG) void k_corank(const uint8_t *runs, const uint6
             if (red_w[q] > bw || (red_w[q] == bw && red_i[q] < j)) { bw = red_w[q]; j = red_i[q]; }
         if (bw == 0 || step >= max_steps) break;
         const uint64_t mid = (lo[j] + hi[j]) >> 1;
-        if (i == 0) s_v = load_key(run_rec(runs, run_off, k, last, j, mid));
+        if (i == 0) s_v = load_key(run_rec(runs, run_off, res, j, mid));
         __syncthreads();
         const Key80 v = s_v;
         // records of run i below v, over the whole run
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(kWG) void k_corank(const uint8_t *runs, const uint6
                 uint64_t a = 0, c = len_i;
                 while (a < c) {
                     const uint64_t m = (a + c) >> 1;
-                    const Key80 e = load_key(run_rec(runs, run_off, k, last, i, m));
+                    const Key80 e = load_key(run_rec(runs, run_off, res, i, m));
                     if (tuple_less(e, i, m, v, j, mid)) a = m + 1; else c = m;
                 }
                 r = a;
@@ -744,10 +750,10 @@ std::vector<uint64_t> merge_plan(uint64_t n, uint64_t k, uint64_t device_budget_
 // The merge of k sorted runs (validated by the caller) into host_out, on the
 // streams of P.  runs_dev is the device view of the pinned runs.  The chunks
 // come from merge_plan under device_budget_bytes; arena: device memory of at
-// least the plan's bytes (null: allocate them).  last: run k - 1 lives in
-// device memory there (its records are not read from the pinned runs).
+// least the plan's bytes (null: allocate them).  res: the runs that live in
+// device memory (their records are not read from the pinned runs).
 int merge_impl(Pipe &P, const uint8_t *runs_dev, const uint8_t *runs_h, const uint64_t *run_bounds, uint64_t k,
-               uint8_t *out_h, bool direct_out, uint64_t device_budget_bytes, char *arena, const uint8_t *last) {
+               uint8_t *out_h, bool direct_out, uint64_t device_budget_bytes, char *arena, Resident res) {
     const uint64_t n = run_bounds[k];
     int rc = LEYENDA_OK;
     const uint32_t rounds = merge_rounds(k);
@@ -792,7 +798,7 @@ int merge_impl(Pipe &P, const uint8_t *runs_dev, const uint8_t *runs_h, const ui
         e = hipMemcpyAsync(d_off, run_bounds, (k + 1) * 8, hipMemcpyHostToDevice, P.cs);
         if (e == hipSuccess) e = hipMemcpyAsync(d_tgt, tgt.data(), (nch - 1) * 8, hipMemcpyHostToDevice, P.cs);
         if (e != hipSuccess) return hip_fail(e, "leyenda_merge: tables");
-        k_corank<<<dim3((uint32_t)(nch - 1)), dim3(kWG), 0, P.cs>>>(runs_dev, d_off, (uint32_t)k, last, d_tgt,
+        k_corank<<<dim3((uint32_t)(nch - 1)), dim3(kWG), 0, P.cs>>>(runs_dev, d_off, (uint32_t)k, res, d_tgt,
                                                                    d_split, d_err);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "co-rank kernel");
         uint32_t err = 0;
@@ -883,9 +889,9 @@ int merge_impl(Pipe &P, const uint8_t *runs_dev, const uint8_t *runs_h, const ui
             for (uint64_t i = 0; i < k && e == hipSuccess; i++) {
                 const uint64_t len = slice_len[c][i];
                 if (!len) continue;
-                if (last && i + 1 == k)  // the run held in device memory
-                    e = hipMemcpyAsync(stage[b] + slice_off[c][i] * kRec, last + split[c * k + i] * kRec, len * kRec,
-                                       hipMemcpyDeviceToDevice, P.h2d);
+                if (i >= res.first)  // a run held in device memory
+                    e = hipMemcpyAsync(stage[b] + slice_off[c][i] * kRec, res.p[i - res.first] + split[c * k + i] * kRec,
+                                       len * kRec, hipMemcpyDeviceToDevice, P.h2d);
                 else
                     e = hipMemcpyAsync(stage[b] + slice_off[c][i] * kRec,
                                        runs_h + (run_bounds[i] + split[c * k + i]) * kRec, len * kRec,
@@ -963,18 +969,21 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
     int rc = P.init(static_cast<hipStream_t>(stream));
     if (rc) return rc;
     return merge_impl(P, runs_dev, static_cast<const uint8_t *>(host_runs), run_bounds, k,
-                      static_cast<uint8_t *>(host_out), direct_out, device_budget_bytes, nullptr, nullptr);
+                      static_cast<uint8_t *>(host_out), direct_out, device_budget_bytes, nullptr,
+                      Resident{{nullptr, nullptr}, (uint32_t)k});
 }
 
 // ---------------------------------------------------------------------------
-// Runs + merge in one call: the same two stages, except that the last run
-// stays in device memory after its sort instead of going to host_runs and
-// coming back for the merge (it is the one run whose download would have
-// nothing to overlap with, and its slices then reach the merge by device
-// copies).  The merge plans its chunks within the budget less that run; when
-// that is too little for a merge of the runs (many tiny runs under a budget
-// near one run's footprint), the last run goes to host_runs too and the merge
-// runs as leyenda_merge would with the whole budget.
+// Runs + merge in one call: the same two stages, except that the last two
+// runs stay in device memory after their sorts (in the two output buffers of
+// the run stage) instead of going to host_runs and coming back for the merge;
+// their slices reach the merge by device copies.  The merge plans its chunks
+// within the run stage's footprint less the kept runs (else within the whole
+// budget less them).  When that is too little for a merge
+// of the runs (many tiny runs under a budget near one run's footprint), only
+// the last run is kept (it is the one whose download would have nothing to
+// overlap with), and when even that leaves too little, every run goes to
+// host_runs and the merge runs as leyenda_merge would with the whole budget.
 
 extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint64_t device_budget_bytes,
                                      void *host_runs, void *host_out, void *stream) {
@@ -1003,19 +1012,34 @@ extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint6
     const size_t rb = a256(R * kRec);
     const size_t ws_bytes = plan_layout(R, 1, t).total;
     const size_t total = 4 * rb + ws_bytes + 256;  // <= the budget (plan_runs_t)
-    // the merge plans its chunks within the budget less the kept run; when
-    // that leaves too little for its tables (many tiny runs), the last run is
-    // downloaded like the others and the merge plans within the whole budget
-    uint64_t merge_bytes = 0;
-    const bool keep_last = K == 1 || !merge_plan(n, K, device_budget_bytes - rb, &merge_bytes).empty();
-    if ((rc = P.alloc(keep_last ? std::max<uint64_t>(total, rb + merge_bytes) : total, device_budget_bytes)))
+    // runs kept on the device: two (the last two) if the merge's chunks and
+    // tables fit beside them, else one, else none (many tiny runs).  The merge
+    // is planned within the run stage's own footprint first, so that the call
+    // asks for no more device memory than its run stage does (a device arena
+    // kept from an earlier external call is then reused, not replaced), and
+    // within the whole budget only when that is too little.
+    uint64_t merge_bytes = 0, kept = 0, merge_budget = 0;
+    if (K == 1) {
+        kept = 1;
+    } else {
+        for (const uint64_t lim : {(uint64_t)total, device_budget_bytes}) {
+            for (uint64_t kk = 2; kk >= 1 && !kept; kk--)
+                if (!merge_plan(n, K, lim - kk * rb, &merge_bytes).empty()) {
+                    kept = kk;
+                    merge_budget = lim - kk * rb;
+                }
+            if (kept) break;
+        }
+    }
+    if ((rc = P.alloc(kept ? std::max<uint64_t>(total, kept * rb + merge_bytes) : total, device_budget_bytes)))
         return rc;
     char *base = static_cast<char *>(P.arena);
-    // the output buffer the last run sorts into comes first, so the rest of the
-    // memory is one block for the merge
+    // the output buffers come first (the last run sorts into out[0], the one
+    // before it into out[1]), so the memory after the kept runs is one block
+    // for the merge
     uint8_t *const keep = reinterpret_cast<uint8_t *>(base);
-    uint8_t *in[2] = {reinterpret_cast<uint8_t *>(base + rb), reinterpret_cast<uint8_t *>(base + 2 * rb)};
-    uint8_t *out[2] = {keep, reinterpret_cast<uint8_t *>(base + 3 * rb)};
+    uint8_t *in[2] = {reinterpret_cast<uint8_t *>(base + 2 * rb), reinterpret_cast<uint8_t *>(base + 3 * rb)};
+    uint8_t *out[2] = {keep, reinterpret_cast<uint8_t *>(base + rb)};
     void *ws = base + 4 * rb;
     uint32_t *guard = reinterpret_cast<uint32_t *>(base + 4 * rb + a256(ws_bytes));
     const uint8_t *src = static_cast<const uint8_t *>(host_records);
@@ -1036,7 +1060,7 @@ extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint6
         if ((rc = sort_device_ws(in[b], len, out[b], P.cs, t, ws))) return rc;
         e = launch_guard_or(ws, len, t, guard, P.cs);
         if (e == hipSuccess) e = hipEventRecord(P.ev[1][b], P.cs);
-        if (e == hipSuccess && (r + 1 < K || !keep_last)) {
+        if (e == hipSuccess && r + kept < K) {  // not a kept run: to host_runs
             e = hipStreamWaitEvent(P.d2h, P.ev[1][b], 0);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(dst + off * kRec, out[b], len * kRec, hipMemcpyDeviceToHost, P.d2h);
@@ -1061,13 +1085,14 @@ extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint6
         if ((rc = bounce.b->drain(keep, out_h, n * kRec, P.ev[1][0], P.d2h))) return rc;
         return P.finish();
     }
-    if (!keep_last) {  // every run is in host_runs: the merge as leyenda_merge runs it
+    if (!kept) {  // every run is in host_runs: the merge as leyenda_merge runs it
         P.release_arena();
         return merge_impl(P, runs_dev, dst, bounds.data(), K, out_h, direct_out, device_budget_bytes, nullptr,
-                          nullptr);
+                          Resident{{nullptr, nullptr}, (uint32_t)K});
     }
-    return merge_impl(P, runs_dev, dst, bounds.data(), K, out_h, direct_out, device_budget_bytes - rb, base + rb,
-                      keep);
+    const Resident res = kept == 2 ? Resident{{out[1], out[0]}, (uint32_t)(K - 2)}
+                                   : Resident{{out[0], nullptr}, (uint32_t)(K - 1)};
+    return merge_impl(P, runs_dev, dst, bounds.data(), K, out_h, direct_out, merge_budget, base + kept * rb, res);
 }
 
 // ---------------------------------------------------------------------------

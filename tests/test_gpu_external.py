@@ -186,15 +186,16 @@ def test_keys_only_budget_and_errors(gpu):
     assert ei.value.status == -1
 
 
-# ---- runs + merge in one call, the last run kept on the device ----
+# ---- runs + merge in one call, the last two runs kept on the device ----
 
 @pytest.mark.parametrize("runs,kind,in_place,pinned_out", [
     (1, "uniform", True, False), (2, "ties", True, True), (3, "uniform", False, False),
     (7, "ties", True, False), (10, "uniform", True, True), (23, "few", False, True)])
 def test_sort_external_matches_oracle(gpu, runs, kind, in_place, pinned_out):
-    """The last run's slices reach the merge by device copies and its keys are
-    read from device memory by the co-rank; ties straddle every run (the
-    resident run included), and with many runs the merge has many chunks."""
+    """The last two runs' slices reach the merge by device copies and their
+    keys are read from device memory by the co-rank; ties straddle every run
+    (the resident runs included), and with many runs the merge has many
+    chunks."""
     import torch
     n = 150_001
     if kind == "uniform":
@@ -214,6 +215,26 @@ def test_sort_external_matches_oracle(gpu, runs, kind, in_place, pinned_out):
     np.testing.assert_array_equal(out.numpy().reshape(n, 100), oracle.sort(rec))
     if not in_place:
         np.testing.assert_array_equal(host.numpy().reshape(n, 100), rec)  # the input is left as it was
+
+
+@pytest.mark.parametrize("runs", [2, 3, 6])
+def test_sort_external_keeps_the_last_two_runs(gpu, runs):
+    """Under a budget with room for the merge beside two runs, the last two
+    runs never reach host_runs (their ranges keep the bytes the buffer held)
+    and every other run does."""
+    import torch
+    n = 120_007
+    rec = datagen.skewed(n, 150 + runs, nvals=40, dup_frac=0.3)
+    budget = budget_for_runs(gpu, n, runs)
+    r, k = gpu.plan_runs(n, budget)
+    assert k == runs
+    host_runs = torch.full((n * 100,), 0xEE, dtype=torch.uint8).pin_memory()
+    out = gpu.sort_external(pinned(rec), budget, host_runs=host_runs)
+    np.testing.assert_array_equal(out.numpy().reshape(n, 100), oracle.sort(rec))
+    hr = host_runs.numpy().reshape(n, 100)
+    for i in range(k):
+        untouched = bool((hr[i * r:min(n, (i + 1) * r)] == 0xEE).all())
+        assert untouched == (i >= k - 2), f"run {i} of {k}"
 
 
 def test_sort_external_tiny_and_errors(gpu):
@@ -237,8 +258,8 @@ def test_sort_external_tiny_and_errors(gpu):
 
 def test_sort_external_many_tiny_runs(gpu):
     """21 runs of about 340 records under a budget near one run's footprint:
-    the budget less the kept run is too small for the merge's tables, so the
-    call downloads the last run too and merges within the whole budget (found
+    the budget less one or two kept runs is too small for the merge's tables,
+    so the call downloads every run and merges within the whole budget (found
     by a random case)."""
     import torch
     n = 7111

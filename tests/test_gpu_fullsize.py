@@ -104,7 +104,7 @@ def test_external_60gb_30gb_budget(gpu):
 @pytest.mark.timeout(1500)
 def test_external_60gb_one_call(gpu):
     """The same 60 GB workload through leyenda_sort_external (runs + merge, the
-    last run kept on the device), runs written over the input."""
+    last two runs kept on the device), runs written over the input."""
     import torch
     n = 600_000_000
     budget = 30 * 10**9
