@@ -1097,12 +1097,14 @@ extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint6
 
 // ---------------------------------------------------------------------------
 // Keys-only external sort: every record's (key, index) tuple is extracted as
-// the input streams in, all tuples are sorted on the device at once, and the
-// records are then gathered in sorted order straight from the pinned input
-// (device loads of host memory) and streamed out.  Section 3.2 sorts
-// key-pointer tuples extracted while reading and then scatters the records by
-// them; here the tuples of the whole input fit the device budget, so there are
-// no runs to merge.
+// the input streams in, and all tuples are sorted on the device at once (the
+// tuples of the whole input fit the device budget, so there are no runs to
+// merge).  Then, as Section 3.2 does with key-pointer tuples extracted while
+// reading, the records are scattered by the sorted tuples: into a pinned
+// output, by a second in-order pass over the input that writes every record
+// to its place; into a pageable output, which the device cannot write, by a
+// gather in sorted order from the pinned input into pinned bounce buffers
+// that the host copies out.
 
 extern "C" int leyenda_sort_external_keys(const void *host_records, uint64_t n, uint64_t device_budget_bytes,
                                           void *host_out, void *stream) {
