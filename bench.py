@@ -544,12 +544,12 @@ def external(ley, torch, datagen, rates: dict, n: int = 600_000_000, budget: int
     keys_bound = max(n * 200 / (rates["h2d"] * 1e9), n * 100 / (rates["d2h"] * 1e9))
     duplex = rates["both_ways"] > 1.2 * max(rates["h2d"], rates["d2h"])
     duplex_bound = n * 400 / (rates["both_ways"] * 1e9) if duplex else None
-    # the one call keeps the last two runs on the device: they are neither
-    # downloaded after their sorts nor uploaded for the merge (r_kept = their
-    # records; had the call kept fewer, it moved more bytes than counted here,
-    # so the fraction below errs low)
-    r_kept = bounds[-1] - bounds[-3] if len(bounds) > 2 else bounds[-1]
-    one_each_way = (n * 200 - r_kept * 100) if len(bounds) > 2 else n * 100
+    # the one call keeps its last runs on the device (the library's plan says
+    # how many): they are neither downloaded after their sorts nor uploaded
+    # for the merge (r_kept = their records)
+    _, k_one, kept = ley.plan_external(n, budget)
+    r_kept = bounds[-1] - bounds[-1 - kept] if kept else 0
+    one_each_way = (n * 200 - r_kept * 100) if k_one > 1 else n * 100
     one_bound = max(one_each_way / (rates["h2d"] * 1e9), one_each_way / (rates["d2h"] * 1e9))
     one_duplex = 2 * one_each_way / (rates["both_ways"] * 1e9) if duplex else None
     if "t_runs_s" in pinned:
@@ -581,6 +581,7 @@ def external(ley, torch, datagen, rates: dict, n: int = 600_000_000, budget: int
                                          "bound_s": round(keys_bound, 3), "frac": round(keys_bound / t_keys, 3)},
                           "sampled_order_ok": ok_keys},
             "one_call": {"t_s": round(t_one, 3), "gbs_records_end_to_end": round(n * 100 / t_one / 1e9, 2),
+                         "runs_kept_on_device": kept,
                          "bytes_per_record_each_way": round(one_each_way / n, 2),
                          "bound_s_each_way_rates_overlapped": round(one_bound, 3),
                          "pcie_frac": round(one_bound / t_one, 3),

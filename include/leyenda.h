@@ -232,6 +232,15 @@ int leyenda_host_free(void *p);
 int leyenda_plan_runs(uint64_t n, uint64_t device_budget_bytes, uint64_t *run_records,
                       uint64_t *num_runs);
 
+/* Plan of leyenda_sort_external for n records under a budget (host-only
+ * arithmetic, no GPU work): records per run, number of runs, and how many of
+ * the last runs stay on the device between the two stages (2, 1, or 0 when
+ * the merge needs the whole budget; 1 for a single run, which is the output).
+ * LEYENDA_EINVAL (NULL), LEYENDA_EBUDGET (no run fits, or more runs than the
+ * merge takes). */
+int leyenda_plan_external(uint64_t n, uint64_t device_budget_bytes, uint64_t *run_records,
+                          uint64_t *num_runs, uint64_t *kept_runs);
+
 /* ---------------------------------------------------------------------------
  * Batched sort: many independent sort requests in one launch sequence (the
  * analogue of Algorithm 1's shared small-bucket task queue, applied across

@@ -86,6 +86,7 @@ def load():
         "leyenda_sort_external_keys": ([vp, u64, u64, vp, vp], i32),
         "leyenda_sort_external": ([vp, u64, u64, vp, vp, vp], i32),
         "leyenda_plan_runs": ([u64, u64, P64, P64], i32),
+        "leyenda_plan_external": ([u64, u64, P64, P64, P64], i32),
         "leyenda_sort_batch": ([ctypes.POINTER(Segment), u64, vp], i32),
         "leyenda_get_params": ([ctypes.POINTER(Params)], i32),
         "leyenda_set_params": ([ctypes.POINTER(Params)], i32),
@@ -207,6 +208,14 @@ def plan_runs(n: int, budget_bytes: int) -> tuple[int, int]:
     r, k = ctypes.c_uint64(0), ctypes.c_uint64(0)
     _check(load().leyenda_plan_runs(n, budget_bytes, ctypes.byref(r), ctypes.byref(k)), "leyenda_plan_runs")
     return int(r.value), int(k.value)
+
+
+def plan_external(n: int, budget_bytes: int) -> tuple[int, int, int]:
+    """(records per run, runs, runs kept on the device) of :func:`sort_external`."""
+    r, k, kept = ctypes.c_uint64(0), ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(load().leyenda_plan_external(n, budget_bytes, ctypes.byref(r), ctypes.byref(k), ctypes.byref(kept)),
+           "leyenda_plan_external")
+    return int(r.value), int(k.value), int(kept.value)
 
 
 _PINNED: dict = {}

@@ -985,6 +985,61 @@ extern "C" int leyenda_merge(const void *host_runs, const uint64_t *run_bounds, 
 // overlap with), and when even that leaves too little, every run goes to
 // host_runs and the merge runs as leyenda_merge would with the whole budget.
 
+namespace {
+
+// The plan of a one-call external sort: R records per run, K runs, and the
+// number of last runs kept on the device with the merge's budget.  Two runs
+// are kept if the merge's chunks and tables fit beside them, else one, else
+// none (many tiny runs).  The merge is planned within the run stage's own
+// footprint first, so that the call asks for no more device memory than its
+// run stage does (a device arena kept from an earlier external call is then
+// reused, not replaced), and within the whole budget only when that is too
+// little.
+struct ExternalPlan {
+    uint64_t R = 0, K = 0, kept = 0;
+    uint64_t rb = 0, ws_bytes = 0, total = 0;  // run buffer, sort workspace, run stage footprint
+    uint64_t merge_budget = 0, merge_bytes = 0;
+};
+
+int plan_external(uint64_t n, uint64_t device_budget_bytes, const Tune &t, ExternalPlan *x) {
+    int rc = plan_runs_t(n, device_budget_bytes, t, &x->R, &x->K);
+    if (rc || n == 0) return rc;
+    x->rb = a256(x->R * kRec);
+    x->ws_bytes = plan_layout(x->R, 1, t).total;
+    x->total = 4 * x->rb + x->ws_bytes + 256;  // <= the budget (plan_runs_t)
+    if (x->K == 1) {
+        x->kept = 1;
+        return LEYENDA_OK;
+    }
+    for (const uint64_t lim : {x->total, device_budget_bytes}) {
+        for (uint64_t kk = 2; kk >= 1; kk--)
+            if (!merge_plan(n, x->K, lim - kk * x->rb, &x->merge_bytes).empty()) {
+                x->kept = kk;
+                x->merge_budget = lim - kk * x->rb;
+                return LEYENDA_OK;
+            }
+    }
+    x->merge_bytes = 0;  // nothing kept: the merge plans as leyenda_merge does
+    return LEYENDA_OK;
+}
+
+}  // namespace
+
+extern "C" int leyenda_plan_external(uint64_t n, uint64_t device_budget_bytes, uint64_t *run_records,
+                                     uint64_t *num_runs, uint64_t *kept_runs) {
+    if (!run_records || !num_runs || !kept_runs) return fail(LEYENDA_EINVAL, "leyenda_plan_external: NULL");
+    ExternalPlan x;
+    const int rc = plan_external(n, device_budget_bytes, tune_of(current_params()), &x);
+    if (rc) return rc;
+    if (x.K > (uint64_t)kMaxRuns)
+        return fail(LEYENDA_EBUDGET, "leyenda_plan_external: %llu runs needed, the merge takes at most %d",
+                    (unsigned long long)x.K, kMaxRuns);
+    *run_records = x.R;
+    *num_runs = x.K;
+    *kept_runs = x.kept;
+    return LEYENDA_OK;
+}
+
 extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint64_t device_budget_bytes,
                                      void *host_runs, void *host_out, void *stream) {
     if (n == 0) return LEYENDA_OK;
@@ -1001,37 +1056,17 @@ extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint6
         return fail(LEYENDA_EINVAL, "leyenda_sort_external: host_records and host_runs must be pinned");
     const bool direct_out = pinned_device_ptr(host_out) != nullptr;
     const Tune t = tune_of(current_params());
-    uint64_t R = 0, K = 0;
-    int rc = plan_runs_t(n, device_budget_bytes, t, &R, &K);
+    ExternalPlan x;
+    int rc = plan_external(n, device_budget_bytes, t, &x);
     if (rc) return rc;
+    const uint64_t R = x.R, K = x.K, kept = x.kept;
     if (K > (uint64_t)kMaxRuns)
         return fail(LEYENDA_EBUDGET, "leyenda_sort_external: %llu runs needed, the merge takes at most %d",
                     (unsigned long long)K, kMaxRuns);
     Pipe P;
     if ((rc = P.init(static_cast<hipStream_t>(stream)))) return rc;
-    const size_t rb = a256(R * kRec);
-    const size_t ws_bytes = plan_layout(R, 1, t).total;
-    const size_t total = 4 * rb + ws_bytes + 256;  // <= the budget (plan_runs_t)
-    // runs kept on the device: two (the last two) if the merge's chunks and
-    // tables fit beside them, else one, else none (many tiny runs).  The merge
-    // is planned within the run stage's own footprint first, so that the call
-    // asks for no more device memory than its run stage does (a device arena
-    // kept from an earlier external call is then reused, not replaced), and
-    // within the whole budget only when that is too little.
-    uint64_t merge_bytes = 0, kept = 0, merge_budget = 0;
-    if (K == 1) {
-        kept = 1;
-    } else {
-        for (const uint64_t lim : {(uint64_t)total, device_budget_bytes}) {
-            for (uint64_t kk = 2; kk >= 1 && !kept; kk--)
-                if (!merge_plan(n, K, lim - kk * rb, &merge_bytes).empty()) {
-                    kept = kk;
-                    merge_budget = lim - kk * rb;
-                }
-            if (kept) break;
-        }
-    }
-    if ((rc = P.alloc(kept ? std::max<uint64_t>(total, kept * rb + merge_bytes) : total, device_budget_bytes)))
+    const size_t rb = x.rb, ws_bytes = x.ws_bytes, total = x.total;
+    if ((rc = P.alloc(kept ? std::max<uint64_t>(total, kept * rb + x.merge_bytes) : total, device_budget_bytes)))
         return rc;
     char *base = static_cast<char *>(P.arena);
     // the output buffers come first (the last run sorts into out[0], the one
@@ -1092,7 +1127,7 @@ extern "C" int leyenda_sort_external(const void *host_records, uint64_t n, uint6
     }
     const Resident res = kept == 2 ? Resident{{out[1], out[0]}, (uint32_t)(K - 2)}
                                    : Resident{{out[0], nullptr}, (uint32_t)(K - 1)};
-    return merge_impl(P, runs_dev, dst, bounds.data(), K, out_h, direct_out, merge_budget, base + kept * rb, res);
+    return merge_impl(P, runs_dev, dst, bounds.data(), K, out_h, direct_out, x.merge_budget, base + kept * rb, res);
 }
 
 // ---------------------------------------------------------------------------

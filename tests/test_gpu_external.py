@@ -217,24 +217,27 @@ def test_sort_external_matches_oracle(gpu, runs, kind, in_place, pinned_out):
         np.testing.assert_array_equal(host.numpy().reshape(n, 100), rec)  # the input is left as it was
 
 
-@pytest.mark.parametrize("runs", [2, 3, 6])
-def test_sort_external_keeps_the_last_two_runs(gpu, runs):
-    """Under a budget with room for the merge beside two runs, the last two
-    runs never reach host_runs (their ranges keep the bytes the buffer held)
-    and every other run does."""
+@pytest.mark.parametrize("n,runs,budget,kept", [
+    (120_007, 2, None, 2), (120_007, 3, None, 2), (120_007, 6, None, 2),
+    (7111, 19, 200_000, 1), (7111, 21, 186_000, 0)])
+def test_sort_external_keeps_the_last_runs(gpu, n, runs, budget, kept):
+    """The runs the plan keeps on the device (two when the merge fits beside
+    them; one, or none, for many tiny runs under a budget near one run's
+    footprint) never reach host_runs: their ranges keep the bytes the buffer
+    held, and every other run is written there."""
     import torch
-    n = 120_007
     rec = datagen.skewed(n, 150 + runs, nvals=40, dup_frac=0.3)
-    budget = budget_for_runs(gpu, n, runs)
-    r, k = gpu.plan_runs(n, budget)
-    assert k == runs
+    if budget is None:
+        budget = budget_for_runs(gpu, n, runs)
+    r, k, kk = gpu.plan_external(n, budget)
+    assert (k, kk) == (runs, kept)
     host_runs = torch.full((n * 100,), 0xEE, dtype=torch.uint8).pin_memory()
     out = gpu.sort_external(pinned(rec), budget, host_runs=host_runs)
     np.testing.assert_array_equal(out.numpy().reshape(n, 100), oracle.sort(rec))
     hr = host_runs.numpy().reshape(n, 100)
     for i in range(k):
         untouched = bool((hr[i * r:min(n, (i + 1) * r)] == 0xEE).all())
-        assert untouched == (i >= k - 2), f"run {i} of {k}"
+        assert untouched == (i >= k - kept), f"run {i} of {k}, {kept} kept"
 
 
 def test_sort_external_tiny_and_errors(gpu):

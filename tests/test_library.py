@@ -100,6 +100,31 @@ def test_plan_runs_budget_math():
     assert ley.plan_runs(0, 1000) == (0, 0)
 
 
+def test_plan_external_kept_runs():
+    """The one-call external plan: the runs of leyenda_plan_runs, and the last
+    two runs kept on the device when the merge fits beside them; many tiny runs
+    under a budget near one run's footprint keep one run or none; one run is
+    the output itself."""
+    import paper_1909_08006_amd as ley
+    assert ley.plan_external(600_000_000, 30 * 10**9) == (*ley.plan_runs(600_000_000, 30 * 10**9), 2)
+    assert ley.plan_external(1000, 1 << 30) == (1000, 1, 1)
+    assert ley.plan_external(0, 1000) == (0, 0, 0)
+    n, tiers = 7111, set()
+    for budget in range(150_000, 1_200_000, 2_000):
+        try:
+            r, k, kept = ley.plan_external(n, budget)
+        except ley.LeyendaError as exc:
+            assert exc.status == -3  # no run fits, or more runs than the merge takes
+            continue
+        assert (r, k) == ley.plan_runs(n, budget)
+        assert kept in (0, 1, 2)
+        tiers.add(kept)
+    assert tiers == {0, 1, 2}
+    with pytest.raises(ley.LeyendaError) as ei:
+        ley.plan_external(10**6, 1000)
+    assert ei.value.status == -3
+
+
 def test_bench_refuses_several_gpus():
     """bench.py sorts on one GPU: --gpus above 1 exits with status 2 and says so."""
     import subprocess
